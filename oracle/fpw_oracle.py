@@ -1,0 +1,282 @@
+"""Plain FP64 CPU oracle for the Fast Periodicity Weighting (FPW) periodogram.
+
+TEST INFRASTRUCTURE.  Only the test suite, the package smoke check and the
+benchmark's CPU-baseline leg may import or run this module.  The GPU path
+shares no code with it and never calls it.
+
+It evaluates the paper's definitions literally, one trial frequency at a
+time (vectorised over a block of frequencies with NumPy, which changes no
+operation and no summation order):
+
+* Fold and bin rule (App. A, the phase-bin index equation; Sec. 4 text and
+  the App. D listing): the phase of an observation at offset tau = t - t_ref
+  for trial frequency f is the fractional part of tau * f, and its bin is
+  the integer part of M times that phase, zero-indexed.  The products are
+  rounded in FP64 in the listing's order: p = fl(tau * f), phi = p - floor(p)
+  (exact for p >= 0), b = floor(fl(phi * M)).
+* Inverse variance (App. D listing, ``runFPW``): w = 1 / (dy * dy).
+* Mean subtraction (Eq. 1 definitions; Sec. 3.5): x is the mean-subtracted
+  flux.  Default: the inverse-variance-weighted mean (see ``center``).
+* Per-bin sums (App. A, sparse form; App. D ``deltaChi2``):
+  W_m = sum of w over points in bin m, Y_m = sum of w * x over those points.
+* Statistic (Eq. 1): S = sum_m Y_m^2 / (W_m + 1/alpha^2).  Empty bins
+  contribute zero.
+* Peaks (Sec. 3.5 post-processing): local maxima of S over the frequency
+  index, the k largest per curve.
+
+Readings where the paper is silent or inconsistent (each is listed with its
+reason in the design notes): the statistic carries no factor 1/2 by default
+(Eq. 1 and App. A; the listing's ``1/(2 W)`` is available as
+``stat_scale="listing_half"``); 1/alpha^2 defaults to 0 (App. A closing
+paragraph: small and neglected); empty bins give 0 rather than the listing's
+0 * inf; t_ref defaults to 0 (listing) and tau must be >= 0 so that the
+listing's truncation and App. A's "mod 1" coincide; the weighted mean is the
+default centring.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "OracleOptions",
+    "validate",
+    "weights",
+    "center",
+    "time_offsets",
+    "fold_phase",
+    "phase_bins",
+    "edge_distance",
+    "bin_sums",
+    "statistic",
+    "prepare_curve",
+    "curve_periodogram",
+    "curve_bins",
+    "periodogram",
+    "peak_mask",
+    "topk",
+    "batch_topk",
+]
+
+# Bins of a point closer than this many bin widths to a bin edge may
+# legitimately differ between two correct FP64 evaluation orders.
+EPS_BIN = 1e-6
+
+
+class OracleOptions:
+    """Options mirroring the library's plan options (same names and defaults)."""
+
+    def __init__(
+        self,
+        inv_alpha2: float = 0.0,
+        center: str = "weighted",
+        tref: str = "zero",
+        t_ref: float = 0.0,
+        stat_scale: str = "eq1",
+    ):
+        if center not in ("weighted", "mean", "none"):
+            raise ValueError(center)
+        if tref not in ("zero", "first", "given"):
+            raise ValueError(tref)
+        if stat_scale not in ("eq1", "listing_half"):
+            raise ValueError(stat_scale)
+        self.inv_alpha2 = float(inv_alpha2)
+        self.center = center
+        self.tref = tref
+        self.t_ref = float(t_ref)
+        self.stat_scale = stat_scale
+
+
+def validate(offsets, t, y, dy, freqs, n_bins, opt: OracleOptions | None = None):
+    """Reject inputs outside the problem statement (raise ValueError)."""
+    opt = opt or OracleOptions()
+    offsets = np.asarray(offsets)
+    if offsets.ndim != 1 or len(offsets) < 2:
+        raise ValueError("need at least one curve")
+    if offsets[0] != 0 or np.any(np.diff(offsets) < 1):
+        raise ValueError("offsets must start at 0 and every curve needs >= 1 point")
+    n = int(offsets[-1])
+    for name, a in (("t", t), ("y", y), ("dy", dy)):
+        a = np.asarray(a, dtype=np.float64)
+        if a.shape != (n,):
+            raise ValueError(f"{name} must have offsets[-1] elements")
+        if not np.all(np.isfinite(a)):
+            raise ValueError(f"{name} must be finite")
+    if not np.all(np.asarray(dy) > 0):
+        raise ValueError("dy must be > 0")
+    freqs = np.asarray(freqs, dtype=np.float64)
+    if freqs.ndim != 1 or len(freqs) < 1:
+        raise ValueError("need at least one frequency")
+    if not (np.all(np.isfinite(freqs)) and np.all(freqs > 0)):
+        raise ValueError("frequencies must be finite and > 0")
+    if int(n_bins) < 1:
+        raise ValueError("n_bins must be >= 1")
+    if not (math.isfinite(opt.inv_alpha2) and opt.inv_alpha2 >= 0):
+        raise ValueError("inv_alpha2 must be finite and >= 0")
+    for c in range(len(offsets) - 1):
+        tc = np.asarray(t[offsets[c] : offsets[c + 1]], dtype=np.float64)
+        tau = time_offsets(tc, opt)
+        if np.any(tau < 0):
+            raise ValueError("t - t_ref must be >= 0")
+
+
+def weights(dy: np.ndarray) -> np.ndarray:
+    """Inverse variance, formed as the listing does: 1 / (dy * dy)."""
+    dy = np.asarray(dy, dtype=np.float64)
+    return 1.0 / (dy * dy)
+
+
+def center(y: np.ndarray, w: np.ndarray, mode: str = "weighted") -> np.ndarray:
+    """Mean-subtracted flux x (Eq. 1 definitions, Sec. 3.5).
+
+    ``weighted``: subtract sum(w y) / sum(w), the maximum-likelihood constant,
+    which makes sum(w x) = 0 so that S is chi-square with M-1 degrees of
+    freedom on pure noise.  ``mean``: subtract the plain average.
+    ``none``: x = y.  Sums use exactly rounded ``math.fsum``.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    if mode == "none":
+        return y.copy()
+    if mode == "mean":
+        mu = math.fsum(y) / len(y)
+    elif mode == "weighted":
+        mu = math.fsum(w * y) / math.fsum(w)
+    else:
+        raise ValueError(mode)
+    return y - mu
+
+
+def time_offsets(t: np.ndarray, opt: OracleOptions) -> np.ndarray:
+    """tau = t - t_ref in FP64 (App. A): t_ref = 0, the first (minimum) time, or given."""
+    t = np.asarray(t, dtype=np.float64)
+    if opt.tref == "zero":
+        return t.copy()
+    if opt.tref == "first":
+        return t - np.min(t)
+    return t - opt.t_ref
+
+
+def fold_phase(tau: np.ndarray, f) -> np.ndarray:
+    """Phase in [0, 1): p = fl(tau * f), phi = p - floor(p) (App. A "mod 1")."""
+    p = np.multiply(tau, f)
+    return p - np.floor(p)
+
+
+def phase_bins(tau: np.ndarray, f, n_bins: int) -> np.ndarray:
+    """Zero-indexed bin floor(fl(phi * M)) (App. A bin-index equation).
+
+    The final clamp to M-1 never changes a result for phi < 1 in
+    round-to-nearest; it is kept as a guard.
+    """
+    phi = fold_phase(tau, f)
+    b = np.floor(phi * float(n_bins)).astype(np.int64)
+    return np.minimum(b, n_bins - 1)
+
+
+def edge_distance(tau: np.ndarray, f, n_bins: int) -> np.ndarray:
+    """Distance of phi * M to the nearest integer, in bin widths."""
+    u = fold_phase(tau, f) * float(n_bins)
+    return np.abs(u - np.round(u))
+
+
+def bin_sums(bins: np.ndarray, w: np.ndarray, x: np.ndarray, n_bins: int):
+    """Per-bin W_m = sum w, Y_m = sum w x and counts N_m, summed in point order."""
+    bins = np.asarray(bins, dtype=np.int64)
+    W = np.bincount(bins, weights=w, minlength=n_bins)
+    Y = np.bincount(bins, weights=w * x, minlength=n_bins)
+    N = np.bincount(bins, minlength=n_bins)
+    return W, Y, N
+
+
+def statistic(W: np.ndarray, Y: np.ndarray, inv_alpha2: float = 0.0, stat_scale: str = "eq1"):
+    """Eq. 1: S = sum over bins with W_m + 1/alpha^2 > 0 of Y_m^2 / (W_m + 1/alpha^2).
+
+    ``W`` and ``Y`` hold the bins on their last axis; one S per leading index.
+    """
+    d = np.asarray(W, dtype=np.float64) + inv_alpha2
+    Y = np.asarray(Y, dtype=np.float64)
+    terms = np.where(d > 0, Y * Y / np.where(d > 0, d, 1.0), 0.0)
+    s = terms.sum(axis=-1)
+    return 0.5 * s if stat_scale == "listing_half" else s
+
+
+def prepare_curve(t, y, dy, opt: OracleOptions | None = None):
+    """(tau, w, x) for one curve: time offsets, inverse variances, centred flux."""
+    opt = opt or OracleOptions()
+    w = weights(dy)
+    x = center(y, w, opt.center)
+    tau = time_offsets(t, opt)
+    return tau, w, x
+
+
+def curve_bins(t, freqs, n_bins, opt: OracleOptions | None = None) -> np.ndarray:
+    """Bin index of every (frequency, point) pair: int64 [n_freq, n_points]."""
+    opt = opt or OracleOptions()
+    tau = time_offsets(t, opt)
+    freqs = np.asarray(freqs, dtype=np.float64)
+    return phase_bins(tau[None, :], freqs[:, None], n_bins)
+
+
+def curve_periodogram(t, y, dy, freqs, n_bins, opt: OracleOptions | None = None, block: int = 256) -> np.ndarray:
+    """S(f) for one curve, FP64, one frequency at a time (vectorised over a block)."""
+    opt = opt or OracleOptions()
+    tau, w, x = prepare_curve(t, y, dy, opt)
+    wx = w * x
+    freqs = np.asarray(freqs, dtype=np.float64)
+    n = len(tau)
+    out = np.empty(len(freqs))
+    for a in range(0, len(freqs), block):
+        fb = freqs[a : a + block]
+        nb = len(fb)
+        bins = phase_bins(tau[None, :], fb[:, None], n_bins)  # [nb, n]
+        flat = (bins + n_bins * np.arange(nb)[:, None]).ravel()
+        W = np.bincount(flat, weights=np.broadcast_to(w, (nb, n)).ravel(), minlength=nb * n_bins)
+        Y = np.bincount(flat, weights=np.broadcast_to(wx, (nb, n)).ravel(), minlength=nb * n_bins)
+        out[a : a + nb] = statistic(W.reshape(nb, n_bins), Y.reshape(nb, n_bins), opt.inv_alpha2, opt.stat_scale)
+    return out
+
+
+def periodogram(offsets, t, y, dy, freqs, n_bins, opt: OracleOptions | None = None, curves=None) -> np.ndarray:
+    """S[c, f] for the selected curves (all by default), FP64."""
+    offsets = np.asarray(offsets)
+    if curves is None:
+        curves = range(len(offsets) - 1)
+    curves = list(curves)
+    out = np.empty((len(curves), len(freqs)))
+    for r, c in enumerate(curves):
+        a, b = int(offsets[c]), int(offsets[c + 1])
+        out[r] = curve_periodogram(t[a:b], y[a:b], dy[a:b], freqs, n_bins, opt)
+    return out
+
+
+def peak_mask(S: np.ndarray) -> np.ndarray:
+    """Index k is a peak iff S[k] > S[k-1] and S[k] >= S[k+1], with S[-1] = S[n] = -inf."""
+    S = np.asarray(S)
+    left = np.concatenate(([-np.inf], S[:-1]))
+    right = np.concatenate((S[1:], [-np.inf]))
+    return (S > left) & (S >= right)
+
+
+def topk(S: np.ndarray, k: int):
+    """The k highest peaks: ordered by S descending, then by index ascending.
+
+    Returns (idx int64 [k], val [k]); missing entries are idx -1, val -inf.
+    """
+    S = np.asarray(S)
+    cand = np.nonzero(peak_mask(S))[0]
+    order = np.lexsort((cand, -S[cand]))  # primary: -S, secondary: index
+    sel = cand[order[:k]]
+    idx = np.full(k, -1, dtype=np.int64)
+    val = np.full(k, -np.inf)
+    idx[: len(sel)] = sel
+    val[: len(sel)] = S[sel]
+    return idx, val
+
+
+def batch_topk(S2d: np.ndarray, k: int):
+    idx = np.empty((S2d.shape[0], k), dtype=np.int64)
+    val = np.empty((S2d.shape[0], k))
+    for r in range(S2d.shape[0]):
+        idx[r], val[r] = topk(S2d[r], k)
+    return idx, val
