@@ -1,0 +1,197 @@
+/*
+ * fpw.h -- C ABI of libfpw, the FPW periodogram on AMD Instinct MI355X (gfx950).
+ *
+ * The Fast Periodicity Weighting statistic (Finkbeiner, Prince & Whitebook,
+ * arXiv 2502.00243, Eq. 1) of one light curve at one trial frequency f is
+ *
+ *     S(f) = sum_m Y_m^2 / (W_m + 1/alpha^2),
+ *     W_m  = sum over points i in phase bin m of w_i,      w_i = 1 / (dy_i * dy_i)
+ *     Y_m  = sum over points i in phase bin m of w_i x_i,  x_i = y_i - mean,
+ *
+ * where point i falls in bin m_i = floor(M * frac((t_i - t_ref) * f)),
+ * zero-indexed (App. A, phase-bin equation; App. D listing).  Bins whose
+ * denominator is zero (empty, with 1/alpha^2 = 0) contribute 0.
+ *
+ * The library evaluates S for every (curve, frequency) pair of a batch of
+ * irregularly sampled light curves, and selects the k highest peaks of each
+ * curve's periodogram (Sec. 3.5 post-processing).  Inputs cross the ABI as
+ * plain pointers and sizes: host arrays at plan time, device buffers for
+ * outputs.  No C++ or torch type appears here.
+ *
+ * Errors: every entry point returns an fpw_status and never throws or aborts.
+ * On failure fpw_last_error() gives a message (thread-local, valid until the
+ * next call on the same thread).  All argument checks (FPW_EINVAL) run on
+ * the host before any HIP call.  HIP failures return FPW_EHIP.
+ *
+ * Threading: calls on one plan must not overlap; separate plans are
+ * independent.  Work is enqueued on the HIP stream passed as `stream`
+ * (a hipStream_t; NULL is the null stream); outputs are ready when that
+ * stream is synchronised.
+ */
+#ifndef FPW_H
+#define FPW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fpw_plan_s* fpw_plan_t; /* opaque; owned by the library */
+
+typedef enum {
+  FPW_OK = 0,
+  FPW_EINVAL = -1,       /* bad argument (host-side check, no HIP call made) */
+  FPW_ENOMEM = -2,       /* host or device allocation failed */
+  FPW_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
+  FPW_ESTATE = -4,       /* call not valid in the plan's state */
+  FPW_EUNSUPPORTED = -5  /* valid input beyond this build's limits */
+} fpw_status;
+
+/* Mean subtracted before folding (Eq. 1 defines x as mean-subtracted; Sec. 3.5). */
+enum {
+  FPW_CENTER_WEIGHTED = 0, /* sum(w y)/sum(w): makes sum(w x) = 0, S ~ chi2(M-1) on noise */
+  FPW_CENTER_MEAN = 1,     /* plain average of y */
+  FPW_CENTER_NONE = 2      /* x = y */
+};
+
+/* Reference time t_ref of the fold (App. A: often the first observation; listing: 0). */
+enum {
+  FPW_TREF_ZERO = 0,  /* t_ref = 0; every t must be >= 0 */
+  FPW_TREF_FIRST = 1, /* t_ref = min(t) of each curve */
+  FPW_TREF_GIVEN = 2  /* t_ref = fpw_options.t_ref; every t must be >= t_ref */
+};
+
+/* Arithmetic that forms the phase and the bin (the only step whose rounding decides bins). */
+enum {
+  FPW_PHASE_FP64 = 0,         /* FP64 fused form: phase = frac(fma(tau, f, -1/(2M))), bin =
+                                 round(M * phase) with bin M folded onto 0.  Bins equal the
+                                 exact ones except within ~1e-8 bin widths of an edge. */
+  FPW_PHASE_FP64_LISTING = 1, /* FP64 in the listing's order: p = fl(tau f), phi = p - floor(p),
+                                 bin = floor(fl(phi M)).  Bit-exact with a plain FP64 loop. */
+  FPW_PHASE_DF32 = 2,         /* compensated FP32: tau and f split hi+lo, error-free product,
+                                 compensated fraction and bin. */
+  FPW_PHASE_FP32 = 3          /* naive FP32 product (precision study only; wrong bins at
+                                 large tau f) */
+};
+
+/* Scale of the statistic. */
+enum {
+  FPW_STAT_EQ1 = 0,          /* Eq. 1 as printed */
+  FPW_STAT_LISTING_HALF = 1  /* times 1/2, as the App. D listing computes it */
+};
+
+#define FPW_MAX_BINS 255      /* largest M (phase-bin histograms live in LDS) */
+#define FPW_MAX_TOPK 16       /* largest k for peak selection */
+#define FPW_MAX_CURVE_POINTS (1 << 24)
+
+typedef struct {
+  int32_t n_bins;      /* M >= 1; > FPW_MAX_BINS -> FPW_EUNSUPPORTED.  Default 10. */
+  int32_t center;      /* FPW_CENTER_*; default WEIGHTED */
+  int32_t tref_mode;   /* FPW_TREF_*; default ZERO */
+  int32_t phase;       /* FPW_PHASE_*; default FP64 */
+  int32_t stat_scale;  /* FPW_STAT_*; default EQ1 */
+  int32_t topk;        /* k of the fused peak selection in fpw_eval_batch; 0 = none;
+                          <= FPW_MAX_TOPK */
+  double inv_alpha2;   /* 1/alpha^2 >= 0, finite (Eq. 1 prior); default 0 (alpha -> inf) */
+  double t_ref;        /* used iff tref_mode == FPW_TREF_GIVEN */
+  int32_t autotune;    /* 1: time candidate launch shapes at plan time and keep the fastest */
+  int32_t use_graph;   /* 1 (default): replay fpw_eval_batch as one captured hipGraph */
+  int32_t freqs_per_lane; /* launch shape override, 0 = default: frequencies per lane (1, 2) */
+  int32_t waves_per_group;/* launch shape override, 0 = default: waves per workgroup (1, 2, 4) */
+  int32_t chunk_freqs;    /* launch shape override, 0 = default: frequencies per work item */
+  const char* tune_cache; /* path of a JSON cache of autotune results; NULL = none */
+} fpw_options;
+
+/* Fills *opt with the defaults listed above. */
+void fpw_options_default(fpw_options* opt);
+
+/*
+ * Creates a plan for a batch of light curves (Sec. 4: "individual light
+ * curves as well as batches").  All arrays are HOST memory owned by the
+ * caller; the plan copies what it needs to the device, so they may be freed
+ * on return.
+ *   n_curves   >= 1
+ *   offsets    int64 [n_curves + 1]; curve c is points offsets[c] .. offsets[c+1]-1;
+ *              offsets[0] = 0, every curve has >= 1 point (<= FPW_MAX_CURVE_POINTS)
+ *   t, y, dy   float64 [offsets[n_curves]]: times (days), fluxes, flux errors;
+ *              all finite, dy > 0, t - t_ref >= 0
+ *   n_freq     >= 1, < 2^31
+ *   freqs      float64 [n_freq], finite, > 0, any order and spacing (Sec. 1: any grid)
+ *   opt        NULL = defaults
+ *   stream     hipStream_t used for the uploads and any autotune launches
+ * On success *out receives the plan (release with fpw_plan_destroy).
+ */
+fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, const double* t,
+                    const double* y, const double* dy, int64_t n_freq, const double* freqs,
+                    const fpw_options* opt, void* stream);
+
+/*
+ * One pass of the periodogram over the plan's batch (Eq. 1 for every curve and
+ * frequency): prepares weights, centred fluxes and time offsets on the device,
+ * folds, bins, accumulates and reduces, and selects peaks.
+ *   S_dev     DEVICE float32 [n_curves * n_freq], row-major by curve, or NULL to
+ *             not store the periodogram.
+ *   topk_idx  DEVICE int32 [n_curves * opt.topk]: frequency indices of the highest
+ *             peaks, best first (ties: lower index first); -1 where a curve has fewer.
+ *   topk_val  DEVICE float32 [n_curves * opt.topk]: their S values (-inf where idx = -1).
+ *             Both NULL, or both non-NULL with opt.topk > 0 (else FPW_EINVAL).
+ * Peak rule: index k is a peak iff S[k] > S[k-1] and S[k] >= S[k+1], with
+ * S[-1] = S[n_freq] = -inf.
+ */
+fpw_status fpw_eval_batch(fpw_plan_t plan, float* S_dev, int32_t* topk_idx, float* topk_val,
+                          void* stream);
+
+/*
+ * Peak selection over a periodogram already in device memory (Sec. 3.5):
+ *   S_dev     DEVICE float32 [n_curves * n_freq] (the plan's shape), read only
+ *   k         1 <= k <= min(FPW_MAX_TOPK, n_freq)
+ *   idx_dev   DEVICE int32 [n_curves * k]; val_dev DEVICE float32 [n_curves * k]
+ * Same peak rule and ordering as fpw_eval_batch's fused selection.
+ */
+fpw_status fpw_topk(fpw_plan_t plan, const float* S_dev, int32_t k, int32_t* idx_dev,
+                    float* val_dev, void* stream);
+
+/*
+ * The plain per-curve FP64 comparator: one launch per curve, listing-order FP64
+ * fold, FP64 per-bin sums and FP64 statistic (App. D "runFPW", re-designed as a
+ * GPU kernel).  S_dev: DEVICE float64 [n_curves * n_freq].
+ */
+fpw_status fpw_eval_fp64(fpw_plan_t plan, double* S_dev, void* stream);
+
+/*
+ * Parity hook: the bin index of every point of one curve at frequencies
+ * f_begin .. f_end-1, computed by the same device code as the main kernels
+ * for the given FPW_PHASE_* mode.
+ *   bins_dev  DEVICE int32 [(f_end - f_begin) * N_curve], row-major by frequency.
+ */
+fpw_status fpw_debug_bins(fpw_plan_t plan, int32_t phase, int64_t curve, int64_t f_begin,
+                          int64_t f_end, int32_t* bins_dev, void* stream);
+
+/* What a plan holds and the launch shape it chose. */
+typedef struct {
+  int64_t n_curves, n_freq, n_points;
+  int64_t evals;          /* n_points * n_freq: observation x frequency evaluations per pass */
+  int32_t n_bins, topk, phase;
+  int32_t freqs_per_lane, waves_per_group, chunk_freqs;
+  int32_t grid_groups;    /* persistent workgroups launched */
+  int32_t work_items;     /* (curve, frequency chunk) items in the queue */
+  int32_t lds_bytes;      /* LDS per workgroup */
+  int32_t tuned;          /* 1 if the launch shape came from the autotuner or its cache */
+} fpw_plan_info;
+
+fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);
+
+/* Releases the plan and its device memory.  NULL is a no-op. */
+void fpw_plan_destroy(fpw_plan_t plan);
+
+/* Message for the last failure on this thread ("" if none). */
+const char* fpw_last_error(void);
+
+/* Library version, e.g. "fpw 0.1.0 gfx950". */
+const char* fpw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPW_H */

@@ -1,0 +1,681 @@
+// Host runtime of libfpw: argument checks, plan construction, work queue,
+// launch-shape selection (defaults, autotuner and its cache), hipGraph
+// capture and the C ABI declared in include/fpw.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/fpw.h"
+#include "fpw_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+fpw_status fail(fpw_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+fpw_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? FPW_ENOMEM : FPW_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define FPW_HIP(call, what)                     \
+  do {                                          \
+    hipError_t e_ = (call);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// Device buffer owned by a plan.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t n) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = n;
+    return n ? hipMalloc(&p, n) : hipSuccess;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+}  // namespace
+
+struct fpw_plan_s {
+  fpw_options opt{};
+  int64_t n_curves = 0, n_freq = 0, n_points = 0;
+  int device = 0;
+  int n_cu = 0;
+  std::vector<int64_t> h_offsets;
+  std::vector<fpw::Item> h_items_nat;  // natural order (curve, chunk)
+  // device inputs and prepared data
+  DevBuf t, y, dy, offsets, freqs, rec, cc, tau64, w64, wx64;
+  // work queue and peak-selection scratch
+  DevBuf items, queue, cand_val, cand_idx, edge, slot_k0, curve_slot;
+  fpw::Shape shape{1, 1, 4096};
+  int grid_groups = 0;
+  size_t lds_bytes = 0;
+  int n_items = 0;
+  bool tuned = false;
+  // graph of one eval pass
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  float* g_S = nullptr;
+  int32_t* g_idx = nullptr;
+  float* g_val = nullptr;
+  bool graph_ok = true;
+  ~fpw_plan_s() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+namespace {
+
+const int kWave = 64;
+
+bool finite(double v) { return std::isfinite(v); }
+
+fpw_status check_options(const fpw_options& o) {
+  if (o.n_bins < 1) return fail(FPW_EINVAL, "n_bins must be >= 1 (got %d)", o.n_bins);
+  if (o.n_bins > FPW_MAX_BINS) return fail(FPW_EUNSUPPORTED, "n_bins %d exceeds FPW_MAX_BINS=%d", o.n_bins, FPW_MAX_BINS);
+  if (o.center < 0 || o.center > 2) return fail(FPW_EINVAL, "bad center mode %d", o.center);
+  if (o.tref_mode < 0 || o.tref_mode > 2) return fail(FPW_EINVAL, "bad tref_mode %d", o.tref_mode);
+  if (o.phase < 0 || o.phase > 3) return fail(FPW_EINVAL, "bad phase mode %d", o.phase);
+  if (o.stat_scale < 0 || o.stat_scale > 1) return fail(FPW_EINVAL, "bad stat_scale %d", o.stat_scale);
+  if (o.topk < 0) return fail(FPW_EINVAL, "topk must be >= 0");
+  if (o.topk > FPW_MAX_TOPK) return fail(FPW_EUNSUPPORTED, "topk %d exceeds FPW_MAX_TOPK=%d", o.topk, FPW_MAX_TOPK);
+  if (!finite(o.inv_alpha2) || o.inv_alpha2 < 0) return fail(FPW_EINVAL, "inv_alpha2 must be finite and >= 0");
+  if (o.tref_mode == FPW_TREF_GIVEN && !finite(o.t_ref)) return fail(FPW_EINVAL, "t_ref must be finite");
+  if (o.freqs_per_lane < 0 || o.freqs_per_lane > 2) return fail(FPW_EINVAL, "freqs_per_lane must be 0, 1 or 2");
+  if (o.freqs_per_lane == 2 && o.phase >= FPW_PHASE_DF32)
+    return fail(FPW_EUNSUPPORTED, "freqs_per_lane 2 is built for the FP64 phase modes only");
+  if (!(o.waves_per_group == 0 || o.waves_per_group == 1 || o.waves_per_group == 2 || o.waves_per_group == 4))
+    return fail(FPW_EINVAL, "waves_per_group must be 0, 1, 2 or 4");
+  if (o.chunk_freqs < 0) return fail(FPW_EINVAL, "chunk_freqs must be >= 0");
+  return FPW_OK;
+}
+
+fpw_status validate(int64_t n_curves, const int64_t* offsets, const double* t, const double* y, const double* dy,
+                    int64_t n_freq, const double* freqs, const fpw_options& o, double* max_tau, double* max_f) {
+  if (n_curves < 1) return fail(FPW_EINVAL, "n_curves must be >= 1");
+  if (n_curves > INT32_MAX - 1) return fail(FPW_EUNSUPPORTED, "n_curves too large");
+  if (!offsets || !t || !y || !dy || !freqs) return fail(FPW_EINVAL, "null input pointer");
+  if (n_freq < 1) return fail(FPW_EINVAL, "n_freq must be >= 1");
+  if (n_freq >= INT32_MAX) return fail(FPW_EUNSUPPORTED, "n_freq must be < 2^31");
+  if (offsets[0] != 0) return fail(FPW_EINVAL, "offsets[0] must be 0");
+  for (int64_t c = 0; c < n_curves; ++c) {
+    const int64_t n = offsets[c + 1] - offsets[c];
+    if (n < 1) return fail(FPW_EINVAL, "curve %lld has no points (offsets must increase)", (long long)c);
+    if (n > FPW_MAX_CURVE_POINTS)
+      return fail(FPW_EUNSUPPORTED, "curve %lld has %lld points (> %d)", (long long)c, (long long)n, FPW_MAX_CURVE_POINTS);
+  }
+  *max_tau = 0.0;
+  for (int64_t c = 0; c < n_curves; ++c) {
+    double tmin = INFINITY, tmax = -INFINITY;
+    for (int64_t i = offsets[c]; i < offsets[c + 1]; ++i) {
+      if (!finite(t[i]) || !finite(y[i]) || !finite(dy[i]))
+        return fail(FPW_EINVAL, "non-finite t, y or dy at point %lld", (long long)i);
+      if (!(dy[i] > 0)) return fail(FPW_EINVAL, "dy must be > 0 (point %lld)", (long long)i);
+      tmin = std::min(tmin, t[i]);
+      tmax = std::max(tmax, t[i]);
+    }
+    const double tref = o.tref_mode == FPW_TREF_ZERO ? 0.0 : (o.tref_mode == FPW_TREF_FIRST ? tmin : o.t_ref);
+    if (tmin - tref < 0)
+      return fail(FPW_EINVAL, "t - t_ref must be >= 0 (curve %lld starts at %g, t_ref %g)", (long long)c, tmin, tref);
+    *max_tau = std::max(*max_tau, tmax - tref);
+  }
+  *max_f = 0.0;
+  for (int64_t k = 0; k < n_freq; ++k) {
+    if (!finite(freqs[k]) || !(freqs[k] > 0)) return fail(FPW_EINVAL, "frequency %lld must be finite and > 0", (long long)k);
+    *max_f = std::max(*max_f, freqs[k]);
+  }
+  if (o.topk > n_freq) return fail(FPW_EINVAL, "topk %d exceeds n_freq %lld", o.topk, (long long)n_freq);
+  // Range of the fold for each phase encoding.
+  const double cycles = *max_tau * *max_f;
+  if (o.phase == FPW_PHASE_FP64 && cycles * o.n_bins >= 4.0e15)
+    return fail(FPW_EUNSUPPORTED, "tau*f*M = %g too large for the fused FP64 fold", cycles * o.n_bins);
+  if ((o.phase == FPW_PHASE_DF32 || o.phase == FPW_PHASE_FP32) && cycles >= 4194304.0)
+    return fail(FPW_EUNSUPPORTED, "tau*f = %g cycles too large for the FP32 phase encodings (< 2^22)", cycles);
+  return FPW_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------- work queue
+// Frequencies of every curve are cut into chunks of `chunk` (a multiple of the
+// frequencies a wave covers per sweep).  A trailing chunk of one frequency is
+// merged into its predecessor so every chunk of a multi-frequency grid has at
+// least two frequencies, which the cross-chunk peak test relies on.
+void build_items(fpw_plan_s* p, int chunk, std::vector<fpw::Item>* nat, std::vector<int32_t>* slot_k0,
+                 std::vector<int32_t>* curve_slot) {
+  nat->clear();
+  slot_k0->clear();
+  curve_slot->assign(p->n_curves + 1, 0);
+  const int64_t nf = p->n_freq;
+  for (int64_t c = 0; c < p->n_curves; ++c) {
+    (*curve_slot)[c] = (int32_t)nat->size();
+    for (int64_t k0 = 0; k0 < nf;) {
+      int64_t k1 = std::min(k0 + chunk, nf);
+      if (nf - k1 == 1) k1 = nf;
+      fpw::Item it;
+      it.curve = (int32_t)c;
+      it.k0 = (int32_t)k0;
+      it.k1 = (int32_t)k1;
+      it.slot = (int32_t)nat->size();
+      nat->push_back(it);
+      slot_k0->push_back((int32_t)k0);
+      k0 = k1;
+    }
+  }
+  (*curve_slot)[p->n_curves] = (int32_t)nat->size();
+}
+
+// Queue order: longest curves first (their items take longest), then by curve
+// and frequency so neighbouring pops share a curve in cache.
+std::vector<fpw::Item> queue_order(const fpw_plan_s* p, const std::vector<fpw::Item>& nat) {
+  std::vector<fpw::Item> q = nat;
+  const std::vector<int64_t>& off = p->h_offsets;
+  std::stable_sort(q.begin(), q.end(), [&](const fpw::Item& a, const fpw::Item& b) {
+    const int64_t na = off[a.curve + 1] - off[a.curve], nb = off[b.curve + 1] - off[b.curve];
+    if (na != nb) return na > nb;
+    if (a.curve != b.curve) return a.curve < b.curve;
+    return a.k0 < b.k0;
+  });
+  return q;
+}
+
+int round_up(int64_t v, int64_t m) { return (int)(((v + m - 1) / m) * m); }
+
+// Default chunk: about four work items per persistent wave, at least one
+// sweep of the wave, at most 16384 frequencies.
+int default_chunk(const fpw_plan_s* p, const fpw::Shape& s, int total_waves) {
+  const int sweep = s.freqs_per_lane * kWave;
+  const double per_curve_items = std::max(1.0, 4.0 * total_waves / (double)p->n_curves);
+  int64_t chunk = (int64_t)std::ceil((double)p->n_freq / per_curve_items);
+  chunk = std::max<int64_t>(chunk, sweep);
+  chunk = std::min<int64_t>(chunk, 16384);
+  return round_up(chunk, sweep);
+}
+
+fpw_status configure_shape(fpw_plan_s* p, fpw::Shape s) {
+  const size_t lds = fpw::batched_lds_bytes(s, p->opt.n_bins);
+  if (lds > 160 * 1024) return fail(FPW_EUNSUPPORTED, "LDS %zu bytes per workgroup exceeds 160 KiB", lds);
+  int per_cu = 0;
+  FPW_HIP(fpw::batched_groups_per_cu(s, p->opt.phase, p->opt.topk, lds, &per_cu), "occupancy query");
+  if (per_cu < 1) return fail(FPW_EUNSUPPORTED, "batched kernel does not fit on a CU with %zu bytes of LDS", lds);
+  p->shape = s;
+  p->lds_bytes = lds;
+  p->grid_groups = per_cu * p->n_cu;
+  if (s.chunk_freqs <= 0) p->shape.chunk_freqs = default_chunk(p, s, p->grid_groups * s.waves_per_group);
+  p->shape.chunk_freqs = round_up(p->shape.chunk_freqs, s.freqs_per_lane * kWave);
+  return FPW_OK;
+}
+
+fpw_status upload_items(fpw_plan_s* p) {
+  std::vector<fpw::Item> nat;
+  std::vector<int32_t> slot_k0, curve_slot;
+  build_items(p, p->shape.chunk_freqs, &nat, &slot_k0, &curve_slot);
+  std::vector<fpw::Item> q = queue_order(p, nat);
+  p->n_items = (int)q.size();
+  p->h_items_nat = nat;
+  FPW_HIP(p->items.alloc(q.size() * sizeof(fpw::Item)), "alloc items");
+  FPW_HIP(hipMemcpy(p->items.p, q.data(), q.size() * sizeof(fpw::Item), hipMemcpyHostToDevice), "upload items");
+  FPW_HIP(p->slot_k0.alloc(slot_k0.size() * sizeof(int32_t)), "alloc slot_k0");
+  FPW_HIP(hipMemcpy(p->slot_k0.p, slot_k0.data(), slot_k0.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload slot_k0");
+  FPW_HIP(p->curve_slot.alloc(curve_slot.size() * sizeof(int32_t)), "alloc curve_slot");
+  FPW_HIP(hipMemcpy(p->curve_slot.p, curve_slot.data(), curve_slot.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+          "upload curve_slot");
+  if (p->opt.topk > 0) {
+    const size_t ns = nat.size();
+    FPW_HIP(p->cand_val.alloc(ns * p->opt.topk * sizeof(float)), "alloc cand_val");
+    FPW_HIP(p->cand_idx.alloc(ns * p->opt.topk * sizeof(int32_t)), "alloc cand_idx");
+    FPW_HIP(p->edge.alloc(ns * 4 * sizeof(float)), "alloc edge");
+  }
+  // the graph holds the old buffers: drop it
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  return FPW_OK;
+}
+
+fpw::BatchArgs batch_args(const fpw_plan_s* p, float* S, const DevBuf& items, int n_items) {
+  fpw::BatchArgs a{};
+  a.rec = p->rec.as<fpw::Rec>();
+  a.offsets = p->offsets.as<int64_t>();
+  a.cc = p->cc.as<fpw::CurveConst>();
+  a.freqs = p->freqs.as<double>();
+  a.items = items.as<fpw::Item>();
+  a.n_items = n_items;
+  a.n_freq = (int32_t)p->n_freq;
+  a.n_bins = p->opt.n_bins;
+  a.topk = p->opt.topk;
+  a.S = S;
+  a.cand_val = p->cand_val.as<float>();
+  a.cand_idx = p->cand_idx.as<int32_t>();
+  a.edge = p->edge.as<float>();
+  a.queue = p->queue.as<uint32_t>();
+  return a;
+}
+
+fpw::PrepArgs prep_args(const fpw_plan_s* p) {
+  fpw::PrepArgs a{};
+  a.t = p->t.as<double>();
+  a.y = p->y.as<double>();
+  a.dy = p->dy.as<double>();
+  a.offsets = p->offsets.as<int64_t>();
+  a.n_curves = p->n_curves;
+  a.center = p->opt.center;
+  a.tref_mode = p->opt.tref_mode;
+  a.phase = p->opt.phase;
+  a.t_ref = p->opt.t_ref;
+  a.inv_alpha2 = p->opt.inv_alpha2;
+  a.stat_scale = p->opt.stat_scale == FPW_STAT_LISTING_HALF ? 0.5f : 1.0f;
+  a.rec = p->rec.as<fpw::Rec>();
+  a.cc = p->cc.as<fpw::CurveConst>();
+  a.tau64 = p->tau64.as<double>();
+  a.w64 = p->w64.as<double>();
+  a.wx64 = p->wx64.as<double>();
+  return a;
+}
+
+fpw::MergeArgs merge_args(const fpw_plan_s* p, int32_t* idx, float* val) {
+  fpw::MergeArgs m{};
+  m.cand_val = p->cand_val.as<float>();
+  m.cand_idx = p->cand_idx.as<int32_t>();
+  m.edge = p->edge.as<float>();
+  m.slot_k0 = p->slot_k0.as<int32_t>();
+  m.curve_slot = p->curve_slot.as<int32_t>();
+  m.n_curves = (int32_t)p->n_curves;
+  m.n_freq = (int32_t)p->n_freq;
+  m.topk = p->opt.topk;
+  m.out_idx = idx;
+  m.out_val = val;
+  return m;
+}
+
+// One full pass: prepare, fold/bin/accumulate/reduce (+ fused peaks), merge.
+fpw_status enqueue_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipStream_t s) {
+  FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
+  FPW_HIP(fpw::launch_batched(batch_args(p, S, p->items, p->n_items), p->shape, p->opt.phase, p->grid_groups, p->lds_bytes, s),
+          "batched kernel");
+  if (idx != nullptr) FPW_HIP(fpw::launch_merge(merge_args(p, idx, val), s), "merge kernel");
+  return FPW_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+std::string tune_key(const fpw_plan_s* p) {
+  hipDeviceProp_t prop;
+  std::string arch = "gfx";
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  const double mean_n = (double)p->n_points / (double)p->n_curves;
+  const int nb = (int)std::floor(std::log2(std::max(1.0, mean_n)));
+  std::ostringstream k;
+  k << arch << "|M=" << p->opt.n_bins << "|phase=" << p->opt.phase << "|topk=" << fpw::topk_capacity(p->opt.topk)
+    << "|log2N=" << nb;
+  return k.str();
+}
+
+// Cache file: one line per key, "key fl waves chunk".
+bool cache_lookup(const char* path, const std::string& key, fpw::Shape* s) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string k;
+  int fl, w, ch;
+  while (f >> k >> fl >> w >> ch) {
+    if (k == key) {
+      s->freqs_per_lane = fl;
+      s->waves_per_group = w;
+      s->chunk_freqs = ch;
+      return true;
+    }
+  }
+  return false;
+}
+
+void cache_store(const char* path, const std::string& key, const fpw::Shape& s) {
+  if (!path) return;
+  std::map<std::string, std::string> lines;
+  {
+    std::ifstream f(path);
+    std::string k, rest;
+    while (f >> k && std::getline(f, rest)) lines[k] = rest;
+  }
+  std::ostringstream v;
+  v << " " << s.freqs_per_lane << " " << s.waves_per_group << " " << s.chunk_freqs;
+  lines[key] = v.str();
+  std::ofstream f(path, std::ios::trunc);
+  for (auto& kv : lines) f << kv.first << kv.second << "\n";
+}
+
+// Times each candidate shape on a calibration slice (every stride-th curve)
+// and keeps the fastest.
+fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
+  const std::string key = tune_key(p);
+  fpw::Shape best{};
+  if (cache_lookup(p->opt.tune_cache, key, &best)) {
+    fpw_status st = configure_shape(p, best);
+    if (st == FPW_OK) {
+      p->tuned = true;
+      return FPW_OK;
+    }
+  }
+  std::vector<fpw::Shape> cands;
+  const int fls = p->opt.phase <= FPW_PHASE_FP64_LISTING ? 2 : 1;
+  for (int fl = 1; fl <= fls; ++fl)
+    for (int w : {1, 2, 4})
+      for (int cm : {1, 4}) cands.push_back(fpw::Shape{fl, w, -cm});
+  // calibration slice: about 2e9 evaluations
+  const double target = 2e9;
+  const double per_curve = (double)p->n_points / p->n_curves * (double)p->n_freq;
+  const int64_t want = std::max<int64_t>(1, (int64_t)(target / std::max(1.0, per_curve)));
+  const int64_t stride = std::max<int64_t>(1, p->n_curves / want);
+  hipEvent_t e0, e1;
+  FPW_HIP(hipEventCreate(&e0), "event");
+  FPW_HIP(hipEventCreate(&e1), "event");
+  double best_t = INFINITY;
+  fpw::Shape best_s = p->shape;
+  for (const fpw::Shape& c0 : cands) {
+    fpw::Shape c = c0;
+    c.chunk_freqs = 0;
+    if (configure_shape(p, c) != FPW_OK) continue;
+    if (c0.chunk_freqs == -4) p->shape.chunk_freqs = round_up(std::min<int64_t>(p->n_freq, 4 * (int64_t)p->shape.chunk_freqs), c.freqs_per_lane * kWave);
+    std::vector<fpw::Item> nat;
+    std::vector<int32_t> sk, cs;
+    build_items(p, p->shape.chunk_freqs, &nat, &sk, &cs);
+    std::vector<fpw::Item> q;
+    for (const fpw::Item& it : queue_order(p, nat))
+      if (it.curve % stride == 0) q.push_back(it);
+    DevBuf items;
+    FPW_HIP(items.alloc(q.size() * sizeof(fpw::Item)), "alloc tune items");
+    FPW_HIP(hipMemcpy(items.p, q.data(), q.size() * sizeof(fpw::Item), hipMemcpyHostToDevice), "upload tune items");
+    // candidate scratch sized for this chunking
+    DevBuf cv, ci, ed;
+    fpw::BatchArgs a = batch_args(p, nullptr, items, (int)q.size());
+    if (p->opt.topk > 0) {
+      FPW_HIP(cv.alloc(nat.size() * p->opt.topk * sizeof(float)), "alloc");
+      FPW_HIP(ci.alloc(nat.size() * p->opt.topk * sizeof(int32_t)), "alloc");
+      FPW_HIP(ed.alloc(nat.size() * 4 * sizeof(float)), "alloc");
+      a.cand_val = cv.as<float>();
+      a.cand_idx = ci.as<int32_t>();
+      a.edge = ed.as<float>();
+    }
+    double tmin = INFINITY;
+    for (int rep = 0; rep < 3; ++rep) {
+      FPW_HIP(hipEventRecord(e0, s), "event");
+      FPW_HIP(fpw::launch_batched(a, p->shape, p->opt.phase, p->grid_groups, p->lds_bytes, s), "tune launch");
+      FPW_HIP(hipEventRecord(e1, s), "event");
+      FPW_HIP(hipEventSynchronize(e1), "event sync");
+      float ms = 0;
+      FPW_HIP(hipEventElapsedTime(&ms, e0, e1), "event time");
+      if (rep > 0) tmin = std::min(tmin, (double)ms);
+    }
+    if (tmin < best_t) {
+      best_t = tmin;
+      best_s = p->shape;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  fpw_status st = configure_shape(p, best_s);
+  if (st != FPW_OK) return st;
+  p->tuned = true;
+  cache_store(p->opt.tune_cache, key, p->shape);
+  return FPW_OK;
+}
+
+template <class T>
+fpw_status upload(DevBuf& b, const T* src, size_t n, hipStream_t s, const char* what) {
+  FPW_HIP(b.alloc(n * sizeof(T)), what);
+  if (n) FPW_HIP(hipMemcpyAsync(b.p, src, n * sizeof(T), hipMemcpyHostToDevice, s), what);
+  return FPW_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+void fpw_options_default(fpw_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->n_bins = 10;
+  o->center = FPW_CENTER_WEIGHTED;
+  o->tref_mode = FPW_TREF_ZERO;
+  o->phase = FPW_PHASE_FP64;
+  o->stat_scale = FPW_STAT_EQ1;
+  o->topk = 0;
+  o->inv_alpha2 = 0.0;
+  o->t_ref = 0.0;
+  o->autotune = 0;
+  o->use_graph = 1;
+  o->tune_cache = nullptr;
+}
+
+const char* fpw_last_error(void) { return g_err.c_str(); }
+
+const char* fpw_version(void) { return "fpw 0.1.0 gfx950"; }
+
+fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, const double* t, const double* y,
+                    const double* dy, int64_t n_freq, const double* freqs, const fpw_options* opt, void* stream) {
+  g_err.clear();
+  if (!out) return fail(FPW_EINVAL, "out is NULL");
+  *out = nullptr;
+  fpw_options o;
+  fpw_options_default(&o);
+  if (opt) o = *opt;
+  fpw_status st = check_options(o);
+  if (st != FPW_OK) return st;
+  double max_tau = 0, max_f = 0;
+  st = validate(n_curves, offsets, t, y, dy, n_freq, freqs, o, &max_tau, &max_f);
+  if (st != FPW_OK) return st;
+  // ---- all checks passed: from here on HIP calls are made
+  try {
+    fpw_plan_s* p = new fpw_plan_s();
+    std::unique_ptr<fpw_plan_s> guard(p);
+    p->opt = o;
+    p->n_curves = n_curves;
+    p->n_freq = n_freq;
+    p->n_points = offsets[n_curves];
+    p->h_offsets.assign(offsets, offsets + n_curves + 1);
+    hipStream_t s = (hipStream_t)stream;
+    FPW_HIP(hipGetDevice(&p->device), "hipGetDevice");
+    FPW_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device), "CU count");
+    const size_t np = (size_t)p->n_points;
+    st = upload(p->t, t, np, s, "upload t");
+    if (st == FPW_OK) st = upload(p->y, y, np, s, "upload y");
+    if (st == FPW_OK) st = upload(p->dy, dy, np, s, "upload dy");
+    if (st == FPW_OK) st = upload(p->offsets, offsets, (size_t)n_curves + 1, s, "upload offsets");
+    if (st == FPW_OK) st = upload(p->freqs, freqs, (size_t)n_freq, s, "upload freqs");
+    if (st != FPW_OK) return st;
+    FPW_HIP(p->rec.alloc(np * sizeof(fpw::Rec)), "alloc records");
+    FPW_HIP(p->cc.alloc((size_t)n_curves * sizeof(fpw::CurveConst)), "alloc curve constants");
+    FPW_HIP(p->tau64.alloc(np * sizeof(double)), "alloc tau64");
+    FPW_HIP(p->w64.alloc(np * sizeof(double)), "alloc w64");
+    FPW_HIP(p->wx64.alloc(np * sizeof(double)), "alloc wx64");
+    FPW_HIP(p->queue.alloc(2 * sizeof(uint32_t)), "alloc queue");
+    FPW_HIP(hipMemsetAsync(p->queue.p, 0, 2 * sizeof(uint32_t), s), "clear queue");
+    // prepared records are needed by autotune, fpw_eval_fp64 and fpw_debug_bins
+    FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
+    fpw::Shape sh{o.freqs_per_lane ? o.freqs_per_lane : 1, o.waves_per_group ? o.waves_per_group : 1, o.chunk_freqs};
+    if (o.autotune && !o.freqs_per_lane && !o.waves_per_group && !o.chunk_freqs) {
+      st = autotune(p, s);
+    } else {
+      st = configure_shape(p, sh);
+    }
+    if (st != FPW_OK) return st;
+    st = upload_items(p);
+    if (st != FPW_OK) return st;
+    FPW_HIP(hipStreamSynchronize(s), "plan sync");
+    *out = guard.release();
+    return FPW_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FPW_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(FPW_EHIP, "unexpected exception");
+  }
+}
+
+fpw_status fpw_eval_batch(fpw_plan_t p, float* S_dev, int32_t* topk_idx, float* topk_val, void* stream) {
+  g_err.clear();
+  if (!p) return fail(FPW_EINVAL, "plan is NULL");
+  if ((topk_idx == nullptr) != (topk_val == nullptr)) return fail(FPW_EINVAL, "topk_idx and topk_val must both be set or both NULL");
+  if (topk_idx && p->opt.topk <= 0) return fail(FPW_EINVAL, "plan was made with topk = 0");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    if (p->opt.use_graph && p->graph_ok) {
+      if (!p->graph_exec || p->g_S != S_dev || p->g_idx != topk_idx || p->g_val != topk_val) {
+        if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->graph_exec = nullptr;
+        p->graph = nullptr;
+        if (!p->cap_stream) FPW_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "capture stream");
+        bool ok = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        fpw_status st = FPW_OK;
+        if (ok) st = enqueue_pass(p, S_dev, topk_idx, topk_val, p->cap_stream);
+        hipGraph_t g = nullptr;
+        const bool ended = ok && hipStreamEndCapture(p->cap_stream, &g) == hipSuccess && g != nullptr;
+        if (ended && st == FPW_OK && hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0) == hipSuccess) {
+          p->graph = g;
+          p->g_S = S_dev;
+          p->g_idx = topk_idx;
+          p->g_val = topk_val;
+        } else {
+          if (g) (void)hipGraphDestroy(g);
+          p->graph_exec = nullptr;
+          p->graph_ok = false;  // fall back to direct launches from now on
+          (void)hipGetLastError();
+        }
+      }
+      if (p->graph_exec) {
+        FPW_HIP(hipGraphLaunch(p->graph_exec, s), "graph launch");
+        return FPW_OK;
+      }
+    }
+    return enqueue_pass(p, S_dev, topk_idx, topk_val, s);
+  } catch (...) {
+    return fail(FPW_EHIP, "unexpected exception");
+  }
+}
+
+fpw_status fpw_topk(fpw_plan_t p, const float* S_dev, int32_t k, int32_t* idx_dev, float* val_dev, void* stream) {
+  g_err.clear();
+  if (!p) return fail(FPW_EINVAL, "plan is NULL");
+  if (!S_dev || !idx_dev || !val_dev) return fail(FPW_EINVAL, "null device pointer");
+  if (k < 1 || k > p->n_freq) return fail(FPW_EINVAL, "k must be in [1, n_freq]");
+  if (k > FPW_MAX_TOPK) return fail(FPW_EUNSUPPORTED, "k %d exceeds FPW_MAX_TOPK=%d", k, FPW_MAX_TOPK);
+  fpw::TopkArgs a{};
+  a.S = S_dev;
+  a.n_curves = (int32_t)p->n_curves;
+  a.n_freq = (int32_t)p->n_freq;
+  a.k = k;
+  a.out_idx = idx_dev;
+  a.out_val = val_dev;
+  FPW_HIP(fpw::launch_topk(a, (hipStream_t)stream), "top-k kernel");
+  return FPW_OK;
+}
+
+fpw_status fpw_eval_fp64(fpw_plan_t p, double* S_dev, void* stream) {
+  g_err.clear();
+  if (!p) return fail(FPW_EINVAL, "plan is NULL");
+  if (!S_dev) return fail(FPW_EINVAL, "S_dev is NULL");
+  if ((size_t)2 * p->opt.n_bins * kWave * sizeof(double) > 160 * 1024)
+    return fail(FPW_EUNSUPPORTED, "the FP64 comparator holds 2*M doubles per lane in LDS: M <= 160");
+  hipStream_t s = (hipStream_t)stream;
+  FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
+  for (int64_t c = 0; c < p->n_curves; ++c) {
+    fpw::Fp64Args a{};
+    a.tau = p->tau64.as<double>();
+    a.w = p->w64.as<double>();
+    a.wx = p->wx64.as<double>();
+    a.freqs = p->freqs.as<double>();
+    a.p0 = p->h_offsets[c];
+    a.n = (int32_t)(p->h_offsets[c + 1] - p->h_offsets[c]);
+    a.n_freq = (int32_t)p->n_freq;
+    a.n_bins = p->opt.n_bins;
+    a.inv_alpha2 = p->opt.inv_alpha2;
+    a.scale = p->opt.stat_scale == FPW_STAT_LISTING_HALF ? 0.5 : 1.0;
+    a.S = S_dev + c * p->n_freq;
+    FPW_HIP(fpw::launch_fp64(a, s), "fp64 kernel");
+  }
+  return FPW_OK;
+}
+
+fpw_status fpw_debug_bins(fpw_plan_t p, int32_t phase, int64_t curve, int64_t f_begin, int64_t f_end, int32_t* bins_dev,
+                          void* stream) {
+  g_err.clear();
+  if (!p) return fail(FPW_EINVAL, "plan is NULL");
+  if (!bins_dev) return fail(FPW_EINVAL, "bins_dev is NULL");
+  if (phase < 0 || phase > 3) return fail(FPW_EINVAL, "bad phase mode %d", phase);
+  if (curve < 0 || curve >= p->n_curves) return fail(FPW_EINVAL, "curve out of range");
+  if (f_begin < 0 || f_end > p->n_freq || f_begin >= f_end) return fail(FPW_EINVAL, "bad frequency range");
+  fpw::BinsArgs a{};
+  a.rec = p->rec.as<fpw::Rec>();
+  a.tau64 = p->tau64.as<double>();
+  a.freqs = p->freqs.as<double>();
+  a.p0 = p->h_offsets[curve];
+  a.n = (int32_t)(p->h_offsets[curve + 1] - p->h_offsets[curve]);
+  a.f_begin = (int32_t)f_begin;
+  a.f_end = (int32_t)f_end;
+  a.n_bins = p->opt.n_bins;
+  a.phase = phase;
+  a.out = bins_dev;
+  FPW_HIP(fpw::launch_bins(a, (hipStream_t)stream), "bins kernel");
+  return FPW_OK;
+}
+
+fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
+  g_err.clear();
+  if (!p || !info) return fail(FPW_EINVAL, "NULL argument");
+  info->n_curves = p->n_curves;
+  info->n_freq = p->n_freq;
+  info->n_points = p->n_points;
+  info->evals = p->n_points * p->n_freq;
+  info->n_bins = p->opt.n_bins;
+  info->topk = p->opt.topk;
+  info->phase = p->opt.phase;
+  info->freqs_per_lane = p->shape.freqs_per_lane;
+  info->waves_per_group = p->shape.waves_per_group;
+  info->chunk_freqs = p->shape.chunk_freqs;
+  info->grid_groups = p->grid_groups;
+  info->work_items = p->n_items;
+  info->lds_bytes = (int32_t)p->lds_bytes;
+  info->tuned = p->tuned ? 1 : 0;
+  return FPW_OK;
+}
+
+void fpw_plan_destroy(fpw_plan_t p) { delete p; }
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Internal interface between the host runtime (fpw_host.cpp) and the HIP
+// kernels (fpw_device.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fpw {
+
+// One prepared observation, 16 bytes.  `tau` holds the time offset in the
+// encoding of the plan's phase mode (FP64, or two FP32 words hi/lo, or one
+// FP32).  `pk` packs the fixed-point weight (high 32 bits, unsigned) and the
+// fixed-point weighted residual (low 32 bits, two's complement) so that one
+// 64-bit integer add accumulates both per-bin sums exactly.
+struct alignas(16) Rec {
+  uint64_t tau_bits;
+  uint64_t pk;
+};
+
+// Per-curve constants produced by the prepare kernel.
+struct alignas(16) CurveConst {
+  float kc;     // s_w / s_y^2: converts sum Y_q^2 / W_q back to data units
+  float ia2q;   // inv_alpha2 * s_w: the prior term in fixed-point weight units
+  float scale;  // 0.5 for the listing's half scale, else 1
+  float pad;
+};
+
+struct PrepArgs {
+  const double* t;
+  const double* y;
+  const double* dy;
+  const int64_t* offsets;
+  int64_t n_curves;
+  int center;       // FPW_CENTER_*
+  int tref_mode;    // FPW_TREF_*
+  int phase;        // FPW_PHASE_*
+  double t_ref;
+  double inv_alpha2;
+  float stat_scale;
+  Rec* rec;              // [n_points]
+  CurveConst* cc;        // [n_curves]
+  double* tau64;         // [n_points] FP64 arrays for the plain comparator
+  double* w64;
+  double* wx64;
+};
+
+// Work item: curve, frequency range [k0, k1), output slot (natural order).
+struct alignas(16) Item {
+  int32_t curve, k0, k1, slot;
+};
+
+struct BatchArgs {
+  const Rec* rec;
+  const int64_t* offsets;
+  const CurveConst* cc;
+  const double* freqs;
+  const Item* items;      // in queue order (longest curves first)
+  int32_t n_items;
+  int32_t n_freq;
+  int32_t n_bins;
+  int32_t topk;           // 0 = no peak selection
+  float* S;               // [n_curves * n_freq] or null
+  float* cand_val;        // [n_slots * topk]
+  int32_t* cand_idx;      // [n_slots * topk]
+  float* edge;            // [n_slots * 4]: S at k0, k0+1, k1-2, k1-1 (-inf if absent)
+  uint32_t* queue;        // [2]: next item, finished waves (self-resetting)
+};
+
+struct MergeArgs {
+  const float* cand_val;
+  const int32_t* cand_idx;
+  const float* edge;
+  const int32_t* slot_k0;     // [n_slots + n_curves]: k0 of each slot in natural order
+  const int32_t* curve_slot;  // [n_curves + 1]: first slot of each curve
+  int32_t n_curves;
+  int32_t n_freq;
+  int32_t topk;
+  int32_t* out_idx;
+  float* out_val;
+};
+
+struct TopkArgs {
+  const float* S;
+  int32_t n_curves;
+  int32_t n_freq;
+  int32_t k;
+  int32_t* out_idx;
+  float* out_val;
+};
+
+struct Fp64Args {
+  const double* tau;
+  const double* w;
+  const double* wx;
+  const double* freqs;
+  int64_t p0;          // first point of the curve
+  int32_t n;           // points in the curve
+  int32_t n_freq;
+  int32_t n_bins;
+  double inv_alpha2;
+  double scale;
+  double* S;           // row of the curve: [n_freq]
+};
+
+struct BinsArgs {
+  const Rec* rec;
+  const double* tau64;
+  const double* freqs;
+  int64_t p0;
+  int32_t n;
+  int32_t f_begin, f_end;
+  int32_t n_bins;
+  int32_t phase;
+  int32_t* out;
+};
+
+// Launch shapes of the batched kernel.
+struct Shape {
+  int freqs_per_lane;   // 1 or 2
+  int waves_per_group;  // 1, 2 or 4
+  int chunk_freqs;      // frequencies per work item
+};
+
+// Launchers; each returns the hipError_t of its launch.
+hipError_t launch_prepare(const PrepArgs& a, hipStream_t s);
+hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int grid_groups,
+                          size_t lds_bytes, hipStream_t s);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
+hipError_t launch_fp64(const Fp64Args& a, hipStream_t s);
+hipError_t launch_bins(const BinsArgs& a, hipStream_t s);
+
+// LDS bytes the batched kernel needs per workgroup.
+size_t batched_lds_bytes(const Shape& shape, int n_bins);
+// Persistent workgroups per CU the batched kernel reaches for this shape.
+hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, size_t lds_bytes, int* out);
+// Top-k list length the kernels are instantiated for (smallest of 4, 8, 16 >= k).
+int topk_capacity(int k);
+
+}  // namespace fpw

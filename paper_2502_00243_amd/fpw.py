@@ -1,0 +1,289 @@
+"""ctypes binding of libfpw (include/fpw.h), with torch tensors for device memory.
+
+Argument marshalling only: every step of the periodogram runs in the HIP
+library.  Loading fails loudly when ``libfpw.so`` has not been built; there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfpw.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "fpw.h")
+
+# status codes
+OK, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "FPW_OK", -1: "FPW_EINVAL", -2: "FPW_ENOMEM", -3: "FPW_EHIP", -4: "FPW_ESTATE", -5: "FPW_EUNSUPPORTED"}
+
+CENTER = {"weighted": 0, "mean": 1, "none": 2}
+TREF = {"zero": 0, "first": 1, "given": 2}
+PHASE = {"fp64": 0, "fp64_listing": 1, "df32": 2, "fp32": 3}
+STAT = {"eq1": 0, "listing_half": 1}
+MAX_BINS = 255
+MAX_TOPK = 16
+
+
+class FpwError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("n_bins", ctypes.c_int32),
+        ("center", ctypes.c_int32),
+        ("tref_mode", ctypes.c_int32),
+        ("phase", ctypes.c_int32),
+        ("stat_scale", ctypes.c_int32),
+        ("topk", ctypes.c_int32),
+        ("inv_alpha2", ctypes.c_double),
+        ("t_ref", ctypes.c_double),
+        ("autotune", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("freqs_per_lane", ctypes.c_int32),
+        ("waves_per_group", ctypes.c_int32),
+        ("chunk_freqs", ctypes.c_int32),
+        ("tune_cache", ctypes.c_char_p),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_curves", ctypes.c_int64),
+        ("n_freq", ctypes.c_int64),
+        ("n_points", ctypes.c_int64),
+        ("evals", ctypes.c_int64),
+        ("n_bins", ctypes.c_int32),
+        ("topk", ctypes.c_int32),
+        ("phase", ctypes.c_int32),
+        ("freqs_per_lane", ctypes.c_int32),
+        ("waves_per_group", ctypes.c_int32),
+        ("chunk_freqs", ctypes.c_int32),
+        ("grid_groups", ctypes.c_int32),
+        ("work_items", ctypes.c_int32),
+        ("lds_bytes", ctypes.c_int32),
+        ("tuned", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/fpw.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpw_[a-z0-9_]+)\s*\(", text)))
+
+
+def load(path: str = LIB_PATH):
+    """Loads libfpw.so (once).  torch is imported first so both share one HIP runtime."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401  (binds the process to torch's HIP runtime first)
+    except ImportError:
+        pass
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with `python -m paper_2502_00243_amd.build_lib` "
+            "(the FPW periodogram has no CPU fallback)"
+        )
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i64, i32 = ctypes.c_int64, ctypes.c_int32
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.fpw_options_default.argtypes = [ctypes.POINTER(Options)]
+    lib.fpw_options_default.restype = None
+    lib.fpw_plan.argtypes = [ctypes.POINTER(P), i64, ctypes.POINTER(i64), dp, dp, dp, i64, dp, ctypes.POINTER(Options), P]
+    lib.fpw_plan.restype = ctypes.c_int
+    lib.fpw_eval_batch.argtypes = [P, P, P, P, P]
+    lib.fpw_eval_batch.restype = ctypes.c_int
+    lib.fpw_topk.argtypes = [P, P, i32, P, P, P]
+    lib.fpw_topk.restype = ctypes.c_int
+    lib.fpw_eval_fp64.argtypes = [P, P, P]
+    lib.fpw_eval_fp64.restype = ctypes.c_int
+    lib.fpw_debug_bins.argtypes = [P, i32, i64, i64, i64, P, P]
+    lib.fpw_debug_bins.restype = ctypes.c_int
+    lib.fpw_get_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+    lib.fpw_get_plan_info.restype = ctypes.c_int
+    lib.fpw_plan_destroy.argtypes = [P]
+    lib.fpw_plan_destroy.restype = None
+    lib.fpw_last_error.argtypes = []
+    lib.fpw_last_error.restype = ctypes.c_char_p
+    lib.fpw_version.argtypes = []
+    lib.fpw_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise FpwError(status, load().fpw_last_error().decode())
+
+
+def default_options() -> Options:
+    o = Options()
+    load().fpw_options_default(ctypes.byref(o))
+    return o
+
+
+def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="fp64", stat_scale="eq1", topk=0,
+                 inv_alpha2=0.0, autotune=False, use_graph=True, freqs_per_lane=0, waves_per_group=0, chunk_freqs=0,
+                 tune_cache=None) -> Options:
+    o = default_options()
+    o.n_bins = int(n_bins)
+    o.center = CENTER[center] if isinstance(center, str) else int(center)
+    o.tref_mode = TREF[tref] if isinstance(tref, str) else int(tref)
+    o.t_ref = float(t_ref)
+    o.phase = PHASE[phase] if isinstance(phase, str) else int(phase)
+    o.stat_scale = STAT[stat_scale] if isinstance(stat_scale, str) else int(stat_scale)
+    o.topk = int(topk)
+    o.inv_alpha2 = float(inv_alpha2)
+    o.autotune = int(bool(autotune))
+    o.use_graph = int(bool(use_graph))
+    o.freqs_per_lane = int(freqs_per_lane)
+    o.waves_per_group = int(waves_per_group)
+    o.chunk_freqs = int(chunk_freqs)
+    o.tune_cache = tune_cache.encode() if tune_cache else None
+    return o
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _stream_handle(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A planned batch: light curves (CSR offsets + concatenated t, y, dy) and a frequency grid."""
+
+    def __init__(self, offsets, t, y, dy, freqs, n_bins, stream=None, **opts):
+        lib = load()
+        self._offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self._t, self._y, self._dy, self._freqs = _f64(t), _f64(y), _f64(dy), _f64(freqs)
+        self.options = make_options(n_bins, **opts)
+        self.n_curves = len(self._offsets) - 1
+        self.n_freq = len(self._freqs)
+        self.n_bins = int(n_bins)
+        self.topk_k = int(opts.get("topk", 0))
+        h = ctypes.c_void_p()
+        st = lib.fpw_plan(ctypes.byref(h), self.n_curves, _ptr(self._offsets, ctypes.c_int64), _ptr(self._t, ctypes.c_double),
+                          _ptr(self._y, ctypes.c_double), _ptr(self._dy, ctypes.c_double), self.n_freq,
+                          _ptr(self._freqs, ctypes.c_double), ctypes.byref(self.options), _stream_handle(stream))
+        _check(st)
+        self._h = h
+
+    @classmethod
+    def from_batch(cls, batch, stream=None, **opts):
+        n_bins = opts.pop("n_bins", batch.n_bins)
+        return cls(batch.offsets, batch.t, batch.y, batch.dy, batch.freqs, n_bins, stream=stream, **opts)
+
+    # -------------------------------------------------------------- calls
+    def eval(self, store_s=True, topk=None, S_out=None, idx_out=None, val_out=None, stream=None):
+        """One pass; returns (S [n_curves, n_freq] float32 or None, idx, val) as device tensors."""
+        import torch
+
+        if topk is None:
+            topk = self.topk_k > 0
+        S = S_out
+        if store_s and S is None:
+            S = torch.empty((self.n_curves, self.n_freq), dtype=torch.float32, device="cuda")
+        idx = val = None
+        if topk:
+            idx = idx_out if idx_out is not None else torch.empty((self.n_curves, self.topk_k), dtype=torch.int32, device="cuda")
+            val = val_out if val_out is not None else torch.empty((self.n_curves, self.topk_k), dtype=torch.float32, device="cuda")
+        _check(load().fpw_eval_batch(self._h, ctypes.c_void_p(S.data_ptr() if S is not None else 0),
+                                     ctypes.c_void_p(idx.data_ptr() if idx is not None else 0),
+                                     ctypes.c_void_p(val.data_ptr() if val is not None else 0), _stream_handle(stream)))
+        return S, idx, val
+
+    def topk(self, S, k, stream=None):
+        """Peaks of a stored periodogram S (device float32 [n_curves, n_freq])."""
+        import torch
+
+        assert S.dtype == torch.float32 and S.is_cuda and S.is_contiguous()
+        assert tuple(S.shape) == (self.n_curves, self.n_freq)
+        idx = torch.empty((self.n_curves, k), dtype=torch.int32, device="cuda")
+        val = torch.empty((self.n_curves, k), dtype=torch.float32, device="cuda")
+        _check(load().fpw_topk(self._h, ctypes.c_void_p(S.data_ptr()), int(k), ctypes.c_void_p(idx.data_ptr()),
+                               ctypes.c_void_p(val.data_ptr()), _stream_handle(stream)))
+        return idx, val
+
+    def eval_fp64(self, stream=None):
+        """The plain per-curve FP64 comparator: S [n_curves, n_freq] float64 on the device."""
+        import torch
+
+        S = torch.empty((self.n_curves, self.n_freq), dtype=torch.float64, device="cuda")
+        _check(load().fpw_eval_fp64(self._h, ctypes.c_void_p(S.data_ptr()), _stream_handle(stream)))
+        return S
+
+    def debug_bins(self, curve, f_begin, f_end, phase=None, stream=None):
+        """Bin of every point of `curve` at frequencies f_begin..f_end-1: int32 [f_end-f_begin, N_curve]."""
+        import torch
+
+        if phase is None:
+            phase = self.options.phase
+        elif isinstance(phase, str):
+            phase = PHASE[phase]
+        n = int(self._offsets[curve + 1] - self._offsets[curve])
+        out = torch.empty((f_end - f_begin, n), dtype=torch.int32, device="cuda")
+        _check(load().fpw_debug_bins(self._h, int(phase), int(curve), int(f_begin), int(f_end),
+                                     ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def info(self) -> PlanInfo:
+        inf = PlanInfo()
+        _check(load().fpw_get_plan_info(self._h, ctypes.byref(inf)))
+        return inf
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            load().fpw_plan_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def plan_status(offsets, t, y, dy, freqs, n_bins, **opts):
+    """Calls fpw_plan and returns (status, message) without raising (for argument-check tests)."""
+    lib = load()
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    t, y, dy, freqs = _f64(t), _f64(y), _f64(dy), _f64(freqs)
+    o = make_options(n_bins, **opts)
+    h = ctypes.c_void_p()
+    st = lib.fpw_plan(ctypes.byref(h), len(offsets) - 1, _ptr(offsets, ctypes.c_int64), _ptr(t, ctypes.c_double),
+                      _ptr(y, ctypes.c_double), _ptr(dy, ctypes.c_double), len(freqs), _ptr(freqs, ctypes.c_double),
+                      ctypes.byref(o), ctypes.c_void_p(0))
+    msg = lib.fpw_last_error().decode()
+    if st == OK and h:
+        lib.fpw_plan_destroy(h)
+    return st, msg

@@ -1,0 +1,112 @@
+"""C ABI checks that need no GPU: the library loads, exports every function the
+header declares, and rejects bad arguments on the host before any HIP call."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2502_00243_amd import fpw
+
+LIB = fpw.LIB_PATH
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libfpw.so not built (run __graft_entry__.build())")
+
+
+def test_exports_every_declared_function():
+    names = fpw.header_functions()
+    assert {"fpw_plan", "fpw_eval_batch", "fpw_topk", "fpw_eval_fp64", "fpw_debug_bins", "fpw_plan_destroy",
+            "fpw_last_error", "fpw_options_default", "fpw_get_plan_info", "fpw_version"} <= set(names)
+    lib = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    for n in names:
+        assert f" T {n}\n" in out, n
+
+
+def test_library_has_gfx950_code_object():
+    # the fat binary embedded in the library names its offload target
+    data = open(LIB, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+def test_options_defaults():
+    o = fpw.default_options()
+    assert (o.n_bins, o.center, o.tref_mode, o.phase, o.stat_scale, o.topk) == (10, 0, 0, 0, 0, 0)
+    assert o.inv_alpha2 == 0.0 and o.use_graph == 1 and o.autotune == 0
+    assert fpw.load().fpw_version().decode().startswith("fpw ")
+
+
+def _good():
+    off = np.array([0, 3, 5], dtype=np.int64)
+    t = np.array([0.1, 2.0, 7.5, 1.0, 3.0])
+    y = np.array([1.0, 2.0, 1.5, 0.0, 0.3])
+    dy = np.full(5, 0.1)
+    f = np.linspace(0.1, 3.0, 40)
+    return off, t, y, dy, f
+
+
+CASES = [
+    ("no curves", dict(offsets=[0]), fpw.EINVAL),
+    ("offsets[0] != 0", dict(offsets=[1, 3, 5]), fpw.EINVAL),
+    ("empty curve", dict(offsets=[0, 0, 5]), fpw.EINVAL),
+    ("dy = 0", dict(dy=[0.1, 0.1, 0.0, 0.1, 0.1]), fpw.EINVAL),
+    ("dy < 0", dict(dy=[0.1, -0.1, 0.1, 0.1, 0.1]), fpw.EINVAL),
+    ("nan y", dict(y=[1.0, np.nan, 1.5, 0.0, 0.3]), fpw.EINVAL),
+    ("inf t", dict(t=[0.1, np.inf, 7.5, 1.0, 3.0]), fpw.EINVAL),
+    ("negative t with t_ref 0", dict(t=[-0.1, 2.0, 7.5, 1.0, 3.0]), fpw.EINVAL),
+    ("f = 0", dict(freqs=[0.0, 1.0]), fpw.EINVAL),
+    ("f < 0", dict(freqs=[-1.0]), fpw.EINVAL),
+    ("nan f", dict(freqs=[np.nan]), fpw.EINVAL),
+    ("M = 0", dict(n_bins=0), fpw.EINVAL),
+    ("M too large", dict(n_bins=fpw.MAX_BINS + 1), fpw.EUNSUPPORTED),
+    ("topk > n_freq", dict(freqs=[1.0, 2.0], opts=dict(topk=3)), fpw.EINVAL),
+    ("topk too large", dict(opts=dict(topk=fpw.MAX_TOPK + 1)), fpw.EUNSUPPORTED),
+    ("negative alpha prior", dict(opts=dict(inv_alpha2=-1.0)), fpw.EINVAL),
+    ("nan alpha prior", dict(opts=dict(inv_alpha2=np.nan)), fpw.EINVAL),
+    ("t below given t_ref", dict(opts=dict(tref="given", t_ref=0.5)), fpw.EINVAL),
+    ("bad phase", dict(opts=dict(phase=7)), fpw.EINVAL),
+    ("bad center", dict(opts=dict(center=9)), fpw.EINVAL),
+    ("fp32 fold range", dict(t=[0.1, 2.0, 7.5e6, 1.0, 3.0], opts=dict(phase="df32")), fpw.EUNSUPPORTED),
+    ("two freqs per lane in df32", dict(opts=dict(phase="df32", freqs_per_lane=2)), fpw.EUNSUPPORTED),
+    ("bad waves per group", dict(opts=dict(waves_per_group=3)), fpw.EINVAL),
+]
+
+
+@pytest.mark.parametrize("name,change,expect", CASES, ids=[c[0] for c in CASES])
+def test_plan_rejects_bad_arguments_on_host(name, change, expect):
+    off, t, y, dy, f = _good()
+    args = dict(offsets=off, t=t, y=y, dy=dy, freqs=f, n_bins=4)
+    opts = change.pop("opts", {}) if "opts" in change else {}
+    args.update({k: np.asarray(v) for k, v in change.items() if k != "n_bins"})
+    if "n_bins" in change:
+        args["n_bins"] = change["n_bins"]
+    st, msg = fpw.plan_status(args["offsets"], args["t"], args["y"], args["dy"], args["freqs"], args["n_bins"], **opts)
+    assert st == expect, (name, st, msg)
+    assert msg
+
+
+def test_null_pointers_rejected():
+    lib = fpw.load()
+    h = ctypes.c_void_p()
+    st = lib.fpw_plan(ctypes.byref(h), 1, None, None, None, None, 1, None, None, None)
+    assert st == fpw.EINVAL
+    assert lib.fpw_plan(None, 1, None, None, None, None, 1, None, None, None) == fpw.EINVAL
+    assert lib.fpw_eval_batch(None, None, None, None, None) == fpw.EINVAL
+    assert lib.fpw_topk(None, None, 1, None, None, None) == fpw.EINVAL
+    assert lib.fpw_eval_fp64(None, None, None) == fpw.EINVAL
+    assert lib.fpw_debug_bins(None, 0, 0, 0, 1, None, None) == fpw.EINVAL
+    assert lib.fpw_get_plan_info(None, None) == fpw.EINVAL
+    lib.fpw_plan_destroy(None)  # no-op
+
+
+def test_valid_plan_without_gpu_reports_hip_error():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    off, t, y, dy, f = _good()
+    st, msg = fpw.plan_status(off, t, y, dy, f, 4)
+    assert st == fpw.EHIP and msg
