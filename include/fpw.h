@@ -100,7 +100,10 @@ typedef struct {
   int32_t freqs_per_lane; /* launch shape override, 0 = default: frequencies per lane (1, 2) */
   int32_t waves_per_group;/* launch shape override, 0 = default: waves per workgroup (1, 2, 4) */
   int32_t chunk_freqs;    /* launch shape override, 0 = default: frequencies per work item */
-  const char* tune_cache; /* path of a JSON cache of autotune results; NULL = none */
+  const char* tune_cache; /* path of a text cache of autotune results; NULL = none */
+  int32_t profile;        /* 1: record HIP events around each kernel of fpw_eval_batch
+                             (read them with fpw_pass_timings); the pass is then
+                             launched kernel by kernel instead of as a graph */
 } fpw_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -167,6 +170,15 @@ fpw_status fpw_eval_fp64(fpw_plan_t plan, double* S_dev, void* stream);
  */
 fpw_status fpw_debug_bins(fpw_plan_t plan, int32_t phase, int64_t curve, int64_t f_begin,
                           int64_t f_end, int32_t* bins_dev, void* stream);
+
+/*
+ * Kernel durations of the most recent fpw_eval_batch of a plan made with
+ * opt.profile = 1, in milliseconds, measured with HIP events recorded on the
+ * stream the kernels ran on: ms[0] prepare, ms[1] fold/bin/accumulate/reduce
+ * (+ fused peaks), ms[2] peak merge (0 if not run).  Waits for that pass to
+ * finish.  FPW_ESTATE if profiling is off or no pass has run.
+ */
+fpw_status fpw_pass_timings(fpw_plan_t plan, float ms[3]);
 
 /* What a plan holds and the launch shape it chose. */
 typedef struct {

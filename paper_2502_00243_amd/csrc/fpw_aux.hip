@@ -1,0 +1,248 @@
+// Auxiliary HIP kernels of libfpw: the per-curve prepare pass, the
+// per-curve peak merge, peak selection over a stored periodogram, the plain
+// FP64 comparator and the bin parity hook.
+#include "fpw_common.h"
+
+namespace fpw {
+namespace {
+
+using namespace dev;
+
+// ---------------------------------------------------------------- chunk merge
+// One wave per curve: lanes take the curve's chunks in turn, keep the best
+// candidates and decide the peaks on the chunk boundaries, then the wave
+// selects the curve's top k.
+template <int K>
+__global__ __launch_bounds__(256) void merge_kernel(MergeArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (c >= a.n_curves) return;  // wave-uniform
+  TopList<K> l;
+  l.init();
+  const int q0 = a.curve_slot[c], q1 = a.curve_slot[c + 1];
+  for (int q = q0 + lane; q < q1; q += kWave) {
+    for (int r = 0; r < a.topk; ++r) {
+      const int ci = a.cand_idx[(int64_t)q * a.topk + r];
+      l.insert(a.cand_val[(int64_t)q * a.topk + r], ci, ci >= 0);
+    }
+    if (q > q0) {
+      // b = first frequency of this chunk, b-1 = last of the previous one
+      const int b = a.slot_k0[q];
+      const float* ep = a.edge + (int64_t)(q - 1) * 4;
+      const float* eq = a.edge + (int64_t)q * 4;
+      const float sa_left = ep[2], sa = ep[3], sb = eq[0], sb_right = eq[1];
+      l.insert(sa, b - 1, sa > sa_left && sa >= sb);
+      l.insert(sb, b, sb > sa && sb >= sb_right);
+    }
+  }
+  wave_select<K>(l, a.topk, a.out_val + (int64_t)c * a.topk, a.out_idx + (int64_t)c * a.topk, lane);
+}
+
+// ---------------------------------------------------------------- top-k over a stored periodogram
+template <int K>
+__global__ __launch_bounds__(256) void topk_kernel(TopkArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (c >= a.n_curves) return;  // wave-uniform
+  const float* S = a.S + (int64_t)c * a.n_freq;
+  TopList<K> l;
+  l.init();
+  for (int k = lane; k < a.n_freq; k += kWave) {
+    const float s = S[k];
+    const float left = k > 0 ? S[k - 1] : -INFINITY;
+    const float right = k + 1 < a.n_freq ? S[k + 1] : -INFINITY;
+    l.insert(s, k, s > left && s >= right);
+  }
+  wave_select<K>(l, a.k, a.out_val + (int64_t)c * a.k, a.out_idx + (int64_t)c * a.k, lane);
+}
+
+// ---------------------------------------------------------------- prepare
+// One workgroup per curve: inverse variances, centring, time offsets and the
+// fixed-point scales, then the packed records.  Reductions use a fixed tree,
+// so results are deterministic.
+constexpr int kPrepThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  red[t] = v;
+  __syncthreads();
+  for (int s = kPrepThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = red[t] + red[t + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+__device__ __forceinline__ double block_min(double v, double* red) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  red[t] = v;
+  __syncthreads();
+  for (int s = kPrepThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmin(red[t], red[t + s]);
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepArgs a) {
+  __shared__ double red[kPrepThreads];
+  const int t = threadIdx.x;
+  for (int64_t c = blockIdx.x; c < a.n_curves; c += gridDim.x) {
+    const int64_t p0 = a.offsets[c];
+    const int n = (int)(a.offsets[c + 1] - p0);
+    double sw = 0.0, swy = 0.0, sy = 0.0, tmin = INFINITY;
+    for (int i = t; i < n; i += kPrepThreads) {
+      const double d = a.dy[p0 + i];
+      const double w = 1.0 / (d * d);
+      const double yy = a.y[p0 + i];
+      sw += w;
+      swy += w * yy;
+      sy += yy;
+      tmin = fmin(tmin, a.t[p0 + i]);
+    }
+    sw = block_sum(sw, red);
+    swy = block_sum(swy, red);
+    sy = block_sum(sy, red);
+    tmin = block_min(tmin, red);
+    const double mu = a.center == 0 ? swy / sw : (a.center == 1 ? sy / (double)n : 0.0);
+    const double tref = a.tref_mode == 0 ? 0.0 : (a.tref_mode == 1 ? tmin : a.t_ref);
+    double ay = 0.0;
+    for (int i = t; i < n; i += kPrepThreads) {
+      const double d = a.dy[p0 + i];
+      const double w = 1.0 / (d * d);
+      ay += fabs(w * (a.y[p0 + i] - mu));
+    }
+    ay = block_sum(ay, red);
+    // Fixed-point scales: sum of |weights| < 2^32 and sum of |w x| < 2^31 for
+    // any subset of points, so no bin sum can leave its 32-bit field.
+    const double s_w = (4294967296.0 - 2.0 - 2.0 * (double)n) / sw;
+    const double s_y = ay > 0.0 ? (2147483648.0 - 2.0 - (double)n) / ay : 1.0;
+    for (int i = t; i < n; i += kPrepThreads) {
+      const int64_t p = p0 + i;
+      const double d = a.dy[p];
+      const double w = 1.0 / (d * d);
+      const double wx = w * (a.y[p] - mu);
+      const double tau = a.t[p] - tref;
+      const double wqd = fmax(1.0, rint(w * s_w));
+      const uint64_t wq = (uint64_t)wqd;
+      const int64_t yq = (int64_t)rint(wx * s_y);
+      Rec r;
+      r.tau_bits = encode_tau(tau, a.phase);
+      r.pk = (wq << 32) + (uint64_t)yq;
+      a.rec[p] = r;
+      a.tau64[p] = tau;
+      a.w64[p] = w;
+      a.wx64[p] = wx;
+    }
+    if (t == 0) {
+      CurveConst k;
+      k.kc = (float)(s_w / (s_y * s_y));
+      k.ia2q = (float)(a.inv_alpha2 * s_w);
+      k.scale = a.stat_scale;
+      k.pad = 0.f;
+      a.cc[c] = k;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- plain FP64 comparator
+// One launch per curve, one lane per frequency, FP64 histograms in LDS
+// ([bin][lane], ds_add_f64), listing-order fold, IEEE division.
+__global__ __launch_bounds__(64) void fp64_kernel(Fp64Args a) {
+  extern __shared__ __align__(16) double hist64[];
+  const int lane = threadIdx.x;
+  const int M = a.n_bins;
+  double* Wh = hist64 + lane;
+  double* Yh = hist64 + M * kWave + lane;
+  for (int m = 0; m < M; ++m) {
+    Wh[m * kWave] = 0.0;
+    Yh[m * kWave] = 0.0;
+  }
+  const int k = blockIdx.x * kWave + lane;
+  Folder<PH_LISTING> fo;
+  fo.init(a.freqs[k < a.n_freq ? k : a.n_freq - 1], M);
+  const double* tau = a.tau + a.p0;
+  const double* w = a.w + a.p0;
+  const double* wx = a.wx + a.p0;
+  for (int i = 0; i < a.n; ++i) {
+    const int b = fo.bin((uint64_t)__double_as_longlong(tau[i]));
+    __hip_atomic_fetch_add(Wh + b * kWave, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(Yh + b * kWave, wx[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  double s = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const double d = Wh[m * kWave] + a.inv_alpha2;
+    const double yv = Yh[m * kWave];
+    if (d > 0.0) s += yv * yv / d;
+  }
+  if (k < a.n_freq) a.S[k] = a.scale * s;
+}
+
+// ---------------------------------------------------------------- bins (parity hook)
+template <int PH>
+__global__ __launch_bounds__(256) void bins_kernel(BinsArgs a) {
+  const int64_t nf = a.f_end - a.f_begin;
+  const int64_t total = nf * a.n;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t fi = g / a.n;
+    const int i = (int)(g - fi * a.n);
+    Folder<PH> fo;
+    fo.init(a.freqs[a.f_begin + fi], a.n_bins);
+    int b = fo.bin(encode_tau(a.tau64[a.p0 + i], PH));
+    if (PH == PH_FP64 && b == a.n_bins) b = 0;
+    a.out[g] = b;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_prepare(const PrepArgs& a, hipStream_t s) {
+  const int64_t g = a.n_curves < 65536 ? a.n_curves : 65536;
+  hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)g), dim3(kPrepThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
+  const int blocks = (a.n_curves + 3) / 4;
+  if (a.topk <= 8)
+    hipLaunchKernelGGL(merge_kernel<8>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(merge_kernel<16>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk(const TopkArgs& a, hipStream_t s) {
+  const int blocks = (a.n_curves + 3) / 4;
+  if (a.k <= 8)
+    hipLaunchKernelGGL(topk_kernel<8>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(topk_kernel<16>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fp64(const Fp64Args& a, hipStream_t s) {
+  const int blocks = (a.n_freq + kWave - 1) / kWave;
+  const size_t lds = (size_t)2 * a.n_bins * kWave * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)fp64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fp64_kernel, dim3(blocks), dim3(kWave), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bins(const BinsArgs& a, hipStream_t s) {
+  const int64_t total = (int64_t)(a.f_end - a.f_begin) * a.n;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  switch (a.phase) {
+    case PH_FP64: hipLaunchKernelGGL(bins_kernel<PH_FP64>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+    case PH_LISTING: hipLaunchKernelGGL(bins_kernel<PH_LISTING>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+    case PH_DF32: hipLaunchKernelGGL(bins_kernel<PH_DF32>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(bins_kernel<PH_FP32>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fpw

@@ -1,0 +1,233 @@
+// HIP kernels of the FPW periodogram for CDNA4 (gfx950).
+//
+// Statistic (Eq. 1 of Finkbeiner, Prince & Whitebook): for each light curve
+// and trial frequency f, observations are folded into M phase bins
+// (App. A phase-bin equation), the per-bin sums W_m = sum w and
+// Y_m = sum w x are accumulated (App. A sparse form) and reduced to
+// S = sum_m Y_m^2 / (W_m + 1/alpha^2).  Peaks of S over f are then selected
+// (Sec. 3.5).
+//
+// Mapping to the chip:
+//  * one lane = one trial frequency; a wave sweeps 64 (or 128) consecutive
+//    frequencies of one curve, so every observation is wave-uniform and is
+//    fetched once per wave through the scalar cache into SGPRs;
+//  * each lane owns a private histogram of M+1 packed 64-bit fixed-point
+//    words in LDS, laid out [bin][lane] so the 64 lanes of a wave always hit
+//    distinct banks whatever their bins are;
+//  * one `ds_add_u64` per (observation, frequency) accumulates both sums
+//    exactly: the weight sits in the high word, the weighted residual in the
+//    low word, and integer addition carries them without rounding;
+//  * the phase is formed in FP64 (full rate on CDNA), and the bin index
+//    comes out of the low word of one more FP64 fma, so a fold costs three
+//    FP64 instructions plus the LDS address;
+//  * work is a queue of (curve, frequency chunk) items, longest curves first,
+//    popped by persistent waves with one atomic each; the peak selection is
+//    fused so that large periodograms never reach HBM.
+#include "fpw_common.h"
+
+namespace fpw {
+namespace {
+
+using namespace dev;
+
+// ---------------------------------------------------------------- batched kernel
+// Read-only inputs of the batched kernel.  They are separate __restrict__
+// kernel arguments so that the compiler may fetch them through the scalar
+// cache (nothing the kernel writes can alias them).
+struct RO {
+  const Rec* __restrict__ rec;
+  const int64_t* __restrict__ offsets;
+  const CurveConst* __restrict__ cc;
+  const double* __restrict__ freqs;
+};
+
+template <int PH, int FL, int KC>
+__device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, const Item& item, uint64_t* hist,
+                                             int lane) {
+  const int M = a.n_bins;
+  const int slots = M + 1;
+  const int c = item.curve, k0 = item.k0, k1 = item.k1;
+  const int64_t p0 = ro.offsets[c];
+  const int n = (int)(ro.offsets[c + 1] - p0);
+  const Rec* __restrict__ rc = ro.rec + p0;
+  const CurveConst cc = ro.cc[c];
+  const float outscale = cc.kc * cc.scale;
+
+  constexpr int KL = KC > 0 ? KC : 1;
+  TopList<KL> list;
+  if (KC > 0) list.init();
+  float pend_s = -INFINITY, pend_left = -INFINITY;  // S at kb-1 and kb-2 (wave-uniform)
+  bool pend = false;                                 // index kb-1 still waits for its right neighbour
+
+  for (int kt = k0; kt < k1; kt += FL * kWave) {
+    Folder<PH> fo[FL];
+    uint64_t* h[FL];
+#pragma unroll
+    for (int j = 0; j < FL; ++j) {
+      const int k = kt + j * kWave + lane;
+      fo[j].init(ro.freqs[k < k1 ? k : k1 - 1], M);
+      h[j] = hist + (j * slots) * kWave + lane;
+    }
+    // fold, bin and accumulate every observation of the curve
+    int i = 0;
+    for (; i + kBatch <= n; i += kBatch) {
+      Rec r[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) r[q] = rc[i + q];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+#pragma unroll
+        for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r[q].tau_bits) * kWave, r[q].pk);
+      }
+    }
+    for (; i < n; ++i) {
+      const Rec r = rc[i];
+#pragma unroll
+      for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r.tau_bits) * kWave, r.pk);
+    }
+    // reduce each sub-tile of 64 frequencies, store, and pick peaks
+#pragma unroll
+    for (int j = 0; j < FL; ++j) {
+      const int kb = kt + j * kWave;
+      if (kb >= k1) break;
+      const float s = outscale * reduce_hist<PH>(h[j], M, cc.ia2q);
+      const int k = kb + lane;
+      const bool valid = k < k1;
+      if (a.S != nullptr && valid) a.S[(int64_t)c * a.n_freq + k] = s;
+      if (KC > 0) {
+        const float sv = valid ? s : -INFINITY;
+        const float up = __shfl_up(sv, 1);
+        const float dn = __shfl_down(sv, 1);
+        // index kb-1 (lane 63 of the previous sub-tile) now has its right neighbour
+        const float s0 = __shfl(sv, 0);
+        if (pend) list.insert(pend_s, kb - 1, lane == kWave - 1 && pend_s > pend_left && pend_s >= s0);
+        // left neighbour, or "undecided" at a chunk start that is not frequency 0
+        float left = up;
+        bool decided = valid;
+        if (lane == 0) {
+          if (kb == k0) {
+            left = -INFINITY;
+            decided = decided && k0 == 0;
+          } else {
+            left = pend_s;
+          }
+        }
+        // right neighbour: the chunk end, or the next sub-tile for lane 63
+        float right = dn;
+        const bool last_of_chunk = k == k1 - 1;
+        if (last_of_chunk) {
+          right = -INFINITY;
+          decided = decided && k1 == a.n_freq;
+        } else if (lane == kWave - 1) {
+          decided = false;  // deferred to the next sub-tile
+        }
+        list.insert(s, k, decided && s > left && s >= right);
+        // carry lane 63 (and 62) forward
+        pend_s = __shfl(sv, kWave - 1);
+        pend_left = __shfl(sv, kWave - 2);
+        pend = kb + kWave - 1 < k1 - 1;
+        // chunk-edge values for the merge
+        if (valid) {
+          float* e = a.edge + (int64_t)item.slot * 4;
+          if (k == k0) {
+            e[0] = s;
+            if (k0 + 1 >= k1) e[1] = -INFINITY;
+            if (k1 - 2 < k0) e[2] = -INFINITY;
+          }
+          if (k == k0 + 1) e[1] = s;
+          if (k == k1 - 2) e[2] = s;
+          if (k == k1 - 1) e[3] = s;
+        }
+      }
+    }
+  }
+  if (KC > 0) {
+    wave_select<KL>(list, a.topk, a.cand_val + (int64_t)item.slot * a.topk, a.cand_idx + (int64_t)item.slot * a.topk, lane);
+  }
+}
+
+template <int PH, int FL, int KC>
+__global__ __launch_bounds__(256) void batched_kernel(BatchArgs a, const Rec* __restrict__ rec,
+                                                      const int64_t* __restrict__ offsets,
+                                                      const CurveConst* __restrict__ ccs,
+                                                      const double* __restrict__ freqs,
+                                                      const Item* __restrict__ items) {
+  const RO ro{rec, offsets, ccs, freqs};
+  extern __shared__ __align__(16) uint64_t lds[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int slots = a.n_bins + 1;
+  uint64_t* hist = lds + (size_t)wave * FL * slots * kWave;  // this wave's histograms: [j][bin][lane]
+  for (int s = 0; s < FL * slots; ++s) hist[s * kWave + lane] = 0;
+  for (;;) {
+    int it = 0;
+    if (lane == 0) it = (int)atomicAdd(a.queue, 1u);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= a.n_items) break;
+    const Item item = items[it];
+    process_item<PH, FL, KC>(a, ro, item, hist, lane);
+  }
+  // The last wave out resets the queue, so the next launch (or graph replay)
+  // starts from zero without a memset.
+  if (lane == 0) {
+    __threadfence();
+    const uint32_t total = gridDim.x * (blockDim.x / kWave);
+    if (atomicAdd(a.queue + 1, 1u) == total - 1) {
+      atomicExch(a.queue, 0u);
+      atomicExch(a.queue + 1, 0u);
+    }
+  }
+}
+
+template <int PH, int FL, int KC>
+void* batched_ptr() {
+  return (void*)&batched_kernel<PH, FL, KC>;
+}
+
+template <int PH, int FL>
+void* batched_ptr_k(int kc) {
+  switch (kc) {
+    case 0: return batched_ptr<PH, FL, 0>();
+    case 8: return batched_ptr<PH, FL, 8>();
+    default: return batched_ptr<PH, FL, 16>();
+  }
+}
+
+void* batched_fn(int phase, int fl, int kc) {
+  switch (phase) {
+    case PH_FP64: return fl == 2 ? batched_ptr_k<PH_FP64, 2>(kc) : batched_ptr_k<PH_FP64, 1>(kc);
+    case PH_LISTING: return fl == 2 ? batched_ptr_k<PH_LISTING, 2>(kc) : batched_ptr_k<PH_LISTING, 1>(kc);
+    case PH_DF32: return batched_ptr_k<PH_DF32, 1>(kc);
+    default: return batched_ptr_k<PH_FP32, 1>(kc);
+  }
+}
+
+}  // namespace
+
+int topk_capacity(int k) { return k <= 0 ? 0 : (k <= 8 ? 8 : 16); }
+
+size_t batched_lds_bytes(const Shape& shape, int n_bins) {
+  return (size_t)shape.waves_per_group * shape.freqs_per_lane * (size_t)(n_bins + 1) * kWave * sizeof(uint64_t);
+}
+
+hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, size_t lds_bytes, int* out) {
+  void* fn = batched_fn(phase, shape.freqs_per_lane, topk_capacity(topk));
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, shape.waves_per_group * kWave, lds_bytes);
+}
+
+hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int grid_groups, size_t lds_bytes,
+                          hipStream_t s) {
+  void* fn = batched_fn(phase, shape.freqs_per_lane, topk_capacity(a.topk));
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  BatchArgs args = a;
+  const Rec* rec = a.rec;
+  const int64_t* offsets = a.offsets;
+  const CurveConst* ccs = a.cc;
+  const double* freqs = a.freqs;
+  const Item* items = a.items;
+  void* params[] = {&args, &rec, &offsets, &ccs, &freqs, &items};
+  return hipLaunchKernel(fn, dim3(grid_groups), dim3(shape.waves_per_group * kWave), params, lds_bytes, s);
+}
+
+}  // namespace fpw

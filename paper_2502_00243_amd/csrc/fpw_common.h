@@ -1,0 +1,234 @@
+// Device code shared by every kernel of libfpw: the fold/bin variants,
+// the LDS histogram helpers and the top-k lists.  The main batched kernel,
+// the parity hook and the FP64 comparator all bin through these same
+// functions.
+#pragma once
+
+#include <float.h>
+#include <math.h>
+
+#include "fpw_internal.h"
+
+namespace fpw {
+namespace dev {
+
+constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52: fma(x, M, kMagic) rounds to an integer in the low word
+constexpr int kBatch = 8;                       // observations per scalar-load batch
+constexpr int kWave = 64;
+
+enum { PH_FP64 = 0, PH_LISTING = 1, PH_DF32 = 2, PH_FP32 = 3 };
+
+__device__ __forceinline__ uint32_t lo32(uint64_t v) { return (uint32_t)v; }
+__device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
+
+// Time-offset encodings stored in a record for each phase mode.
+__device__ __forceinline__ uint64_t encode_tau(double tau, int phase) {
+  if (phase == PH_DF32) {
+    const float th = (float)tau;
+    const float tl = (float)(tau - (double)th);
+    return ((uint64_t)__float_as_uint(tl) << 32) | (uint64_t)__float_as_uint(th);
+  }
+  if (phase == PH_FP32) return (uint64_t)__float_as_uint((float)tau);
+  return (uint64_t)__double_as_longlong(tau);
+}
+
+// ---------------------------------------------------------------- fold + bin
+// Folder<PH>::bin(tau) returns the bin of one observation at the lane's
+// frequency.  All results lie in [0, M]; only PH_FP64 produces M, which
+// stands for bin 0 (see below) and is folded onto it when the bins are read.
+template <int PH>
+struct Folder;
+
+// FP64, fused: the fold is shifted by half a bin, phase' = frac(tau f - 1/(2M)),
+// and round(M phase') (one fma into the magic constant) equals
+// floor(M frac(tau f)) except within rounding of an edge; phase' just below 1
+// rounds to M, which is bin 0.  tau f - 1/(2M) is formed with one rounding
+// (fma), so the bin is exact up to ~M * ulp(tau f) bin widths.
+template <>
+struct Folder<PH_FP64> {
+  double f, nh, md;
+  __device__ __forceinline__ void init(double freq, int M) {
+    f = freq;
+    md = (double)M;
+    nh = -0.5 / (double)M;
+  }
+  __device__ __forceinline__ int bin(uint64_t tb) const {
+    const double tau = __longlong_as_double((long long)tb);
+    const double ph = __builtin_amdgcn_fract(__builtin_fma(tau, f, nh));
+    return (int)lo32((uint64_t)__double_as_longlong(__builtin_fma(ph, md, kMagic)));
+  }
+};
+
+// FP64 in the order of the paper's listing: p = fl(tau f); phi = p - floor(p)
+// (exact for p >= 0); bin = trunc(fl(phi M)).  Identical to a plain FP64 loop.
+template <>
+struct Folder<PH_LISTING> {
+  double f, md;
+  __device__ __forceinline__ void init(double freq, int M) {
+    f = freq;
+    md = (double)M;
+  }
+  __device__ __forceinline__ int bin(uint64_t tb) const {
+    const double tau = __longlong_as_double((long long)tb);
+    const double p = tau * f;
+    const double ph = __builtin_amdgcn_fract(p);
+    return (int)(ph * md);
+  }
+};
+
+// Compensated FP32 ("double-float"): tau = th + tl and f = fh + fl.  The
+// product th*fh is split exactly (fma), the cross terms are added to the low
+// part, the fraction is taken from the exact high part, and the bin is the
+// floor of M*(fraction + low part) formed with an exact product and one
+// final correction step.
+template <>
+struct Folder<PH_DF32> {
+  float fh, fl, mf;
+  int m;
+  __device__ __forceinline__ void init(double freq, int M) {
+    fh = (float)freq;
+    fl = (float)(freq - (double)fh);
+    mf = (float)M;
+    m = M;
+  }
+  __device__ __forceinline__ int bin(uint64_t tb) const {
+    const float th = __uint_as_float(lo32(tb));
+    const float tl = __uint_as_float(hi32(tb));
+    const float ph = th * fh;
+    float pl = __builtin_fmaf(th, fh, -ph);
+    pl = __builtin_fmaf(th, fl, pl);
+    pl = __builtin_fmaf(tl, fh, pl);
+    const float fr = ph - floorf(ph);        // exact: ph < 2^23
+    const float uh = mf * fr;
+    const float ul = __builtin_fmaf(mf, fr, -uh);  // uh + ul = M*fr exactly
+    const float c = __builtin_fmaf(mf, pl, ul);
+    const float b0 = floorf(uh);
+    const float r = (uh - b0) + c;           // uh - b0 exact
+    int b = (int)b0 + (int)floorf(r);
+    b = b % m;
+    return b < 0 ? b + m : b;
+  }
+};
+
+// Naive FP32 product, for the precision study only.
+template <>
+struct Folder<PH_FP32> {
+  float f, mf;
+  int m;
+  __device__ __forceinline__ void init(double freq, int M) {
+    f = (float)freq;
+    mf = (float)M;
+    m = M;
+  }
+  __device__ __forceinline__ int bin(uint64_t tb) const {
+    const float p = __uint_as_float(lo32(tb)) * f;
+    const float fr = p - floorf(p);
+    const int b = (int)(fr * mf);
+    return b < m - 1 ? b : m - 1;
+  }
+};
+
+// ---------------------------------------------------------------- LDS histograms
+__device__ __forceinline__ void lds_add(uint64_t* p, uint64_t v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t lds_take(uint64_t* p) {
+  return __hip_atomic_exchange(p, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Eq. 1 term of one bin from its packed fixed-point word: Y_q^2 / (W_q + ia2q).
+__device__ __forceinline__ float bin_term(uint64_t v, float ia2q) {
+  const uint32_t l = lo32(v);
+  const int32_t yq = (int32_t)l;
+  const uint32_t wq = hi32(v) + (l >> 31);  // undo the borrow of a negative low word
+  const float d = (float)wq + ia2q;
+  const float yf = (float)yq;
+  const float t = yf * (yf * __builtin_amdgcn_rcpf(d));
+  return d > 0.f ? t : 0.f;
+}
+
+// Reads and clears one lane's histogram (slot m at h + 64 m) and returns
+// sum_m Y_m^2 / (W_m + 1/alpha^2) in fixed-point units.
+template <int PH>
+__device__ __forceinline__ float reduce_hist(uint64_t* h, int M, float ia2q) {
+  uint64_t v0 = lds_take(h);
+  if (PH == PH_FP64) v0 += lds_take(h + M * kWave);
+  float acc = bin_term(v0, ia2q);
+  for (int m = 1; m < M; ++m) acc += bin_term(lds_take(h + m * kWave), ia2q);
+  return acc;
+}
+
+// ---------------------------------------------------------------- top-k lists
+// Strict total order of peaks: larger S first, then lower frequency index.
+__device__ __forceinline__ bool better(float av, int ai, float bv, int bi) {
+  return av > bv || (av == bv && ai < bi);
+}
+
+template <int K>
+struct TopList {
+  float v[K];
+  int i[K];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      v[q] = -INFINITY;
+      i[q] = INT_MAX;
+    }
+  }
+  // Inserts (s, k) when `pred`, keeping the K best in order.
+  __device__ __forceinline__ void insert(float s, int k, bool pred) {
+    if (pred && better(s, k, v[K - 1], i[K - 1])) {
+      bool b[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) b[q] = better(s, k, v[q], i[q]);
+#pragma unroll
+      for (int q = K - 1; q >= 0; --q) {
+        const bool prev = q > 0 ? b[q - 1] : false;
+        if (prev) {
+          v[q] = v[q - 1];
+          i[q] = i[q - 1];
+        } else if (b[q]) {
+          v[q] = s;
+          i[q] = k;
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ void pop_front() {
+#pragma unroll
+    for (int q = 0; q < K - 1; ++q) {
+      v[q] = v[q + 1];
+      i[q] = i[q + 1];
+    }
+    v[K - 1] = -INFINITY;
+    i[K - 1] = INT_MAX;
+  }
+};
+
+// Merges the 64 lanes' lists: writes the `k` best (value, index) of the wave,
+// best first; missing entries are (-inf, -1).  Every lane must call it.
+template <int K>
+__device__ __forceinline__ void wave_select(TopList<K>& l, int k, float* out_v, int32_t* out_i, int lane) {
+  for (int r = 0; r < k; ++r) {
+    float bv = l.v[0];
+    int bi = l.i[0];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (better(ov, oi, bv, bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    const bool none = bv == -INFINITY;
+    if (lane == 0) {
+      out_v[r] = bv;
+      out_i[r] = none ? -1 : bi;
+    }
+    if (!none && l.i[0] == bi) l.pop_front();
+  }
+}
+
+}  // namespace dev
+}  // namespace fpw

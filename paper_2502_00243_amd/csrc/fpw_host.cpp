@@ -90,7 +90,13 @@ struct fpw_plan_s {
   int32_t* g_idx = nullptr;
   float* g_val = nullptr;
   bool graph_ok = true;
+  // profiling events: before prepare, after prepare, after batched, after merge
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ev_recorded = false;
+  bool ev_merge = false;
   ~fpw_plan_s() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -269,6 +275,13 @@ fpw_status upload_items(fpw_plan_s* p) {
   return FPW_OK;
 }
 
+// Persistent workgroups actually launched: never more than the items can keep busy.
+int launch_groups(const fpw_plan_s* p, int n_items) {
+  const int wpg = p->shape.waves_per_group;
+  const int need = (n_items + wpg - 1) / wpg;
+  return std::max(1, std::min(p->grid_groups, need));
+}
+
 fpw::BatchArgs batch_args(const fpw_plan_s* p, float* S, const DevBuf& items, int n_items) {
   fpw::BatchArgs a{};
   a.rec = p->rec.as<fpw::Rec>();
@@ -326,10 +339,17 @@ fpw::MergeArgs merge_args(const fpw_plan_s* p, int32_t* idx, float* val) {
 
 // One full pass: prepare, fold/bin/accumulate/reduce (+ fused peaks), merge.
 fpw_status enqueue_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipStream_t s) {
+  const bool prof = p->opt.profile != 0;
+  if (prof) FPW_HIP(hipEventRecord(p->ev[0], s), "event record");
   FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
-  FPW_HIP(fpw::launch_batched(batch_args(p, S, p->items, p->n_items), p->shape, p->opt.phase, p->grid_groups, p->lds_bytes, s),
+  if (prof) FPW_HIP(hipEventRecord(p->ev[1], s), "event record");
+  FPW_HIP(fpw::launch_batched(batch_args(p, S, p->items, p->n_items), p->shape, p->opt.phase,
+                              launch_groups(p, p->n_items), p->lds_bytes, s),
           "batched kernel");
+  if (prof) FPW_HIP(hipEventRecord(p->ev[2], s), "event record");
   if (idx != nullptr) FPW_HIP(fpw::launch_merge(merge_args(p, idx, val), s), "merge kernel");
+  if (prof) FPW_HIP(hipEventRecord(p->ev[3], s), "event record");
+  p->ev_merge = idx != nullptr;
   return FPW_OK;
 }
 
@@ -434,7 +454,8 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
     double tmin = INFINITY;
     for (int rep = 0; rep < 3; ++rep) {
       FPW_HIP(hipEventRecord(e0, s), "event");
-      FPW_HIP(fpw::launch_batched(a, p->shape, p->opt.phase, p->grid_groups, p->lds_bytes, s), "tune launch");
+      FPW_HIP(fpw::launch_batched(a, p->shape, p->opt.phase, launch_groups(p, (int)q.size()), p->lds_bytes, s),
+              "tune launch");
       FPW_HIP(hipEventRecord(e1, s), "event");
       FPW_HIP(hipEventSynchronize(e1), "event sync");
       float ms = 0;
@@ -525,6 +546,8 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     FPW_HIP(p->tau64.alloc(np * sizeof(double)), "alloc tau64");
     FPW_HIP(p->w64.alloc(np * sizeof(double)), "alloc w64");
     FPW_HIP(p->wx64.alloc(np * sizeof(double)), "alloc wx64");
+    if (o.profile)
+      for (hipEvent_t& e : p->ev) FPW_HIP(hipEventCreate(&e), "event create");
     FPW_HIP(p->queue.alloc(2 * sizeof(uint32_t)), "alloc queue");
     FPW_HIP(hipMemsetAsync(p->queue.p, 0, 2 * sizeof(uint32_t), s), "clear queue");
     // prepared records are needed by autotune, fpw_eval_fp64 and fpw_debug_bins
@@ -555,7 +578,9 @@ fpw_status fpw_eval_batch(fpw_plan_t p, float* S_dev, int32_t* topk_idx, float* 
   if (topk_idx && p->opt.topk <= 0) return fail(FPW_EINVAL, "plan was made with topk = 0");
   hipStream_t s = (hipStream_t)stream;
   try {
-    if (p->opt.use_graph && p->graph_ok) {
+    // Profiling records plain stream events, so a profiled pass is launched
+    // directly rather than replayed from the graph.
+    if (p->opt.use_graph && p->graph_ok && !p->opt.profile) {
       if (!p->graph_exec || p->g_S != S_dev || p->g_idx != topk_idx || p->g_val != topk_val) {
         if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
         if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -581,10 +606,13 @@ fpw_status fpw_eval_batch(fpw_plan_t p, float* S_dev, int32_t* topk_idx, float* 
       }
       if (p->graph_exec) {
         FPW_HIP(hipGraphLaunch(p->graph_exec, s), "graph launch");
+        p->ev_recorded = p->opt.profile != 0;
         return FPW_OK;
       }
     }
-    return enqueue_pass(p, S_dev, topk_idx, topk_val, s);
+    fpw_status st = enqueue_pass(p, S_dev, topk_idx, topk_val, s);
+    p->ev_recorded = st == FPW_OK && p->opt.profile != 0;
+    return st;
   } catch (...) {
     return fail(FPW_EHIP, "unexpected exception");
   }
@@ -653,6 +681,22 @@ fpw_status fpw_debug_bins(fpw_plan_t p, int32_t phase, int64_t curve, int64_t f_
   a.phase = phase;
   a.out = bins_dev;
   FPW_HIP(fpw::launch_bins(a, (hipStream_t)stream), "bins kernel");
+  return FPW_OK;
+}
+
+fpw_status fpw_pass_timings(fpw_plan_t p, float ms[3]) {
+  g_err.clear();
+  if (!p || !ms) return fail(FPW_EINVAL, "NULL argument");
+  if (!p->opt.profile) return fail(FPW_ESTATE, "plan was made with profile = 0");
+  if (!p->ev_recorded) return fail(FPW_ESTATE, "no fpw_eval_batch has run on this plan");
+  FPW_HIP(hipEventSynchronize(p->ev[3]), "event sync");
+  FPW_HIP(hipEventElapsedTime(&ms[0], p->ev[0], p->ev[1]), "event time");
+  FPW_HIP(hipEventElapsedTime(&ms[1], p->ev[1], p->ev[2]), "event time");
+  if (p->ev_merge) {
+    FPW_HIP(hipEventElapsedTime(&ms[2], p->ev[2], p->ev[3]), "event time");
+  } else {
+    ms[2] = 0.f;
+  }
   return FPW_OK;
 }
 

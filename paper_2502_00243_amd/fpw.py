@@ -51,6 +51,7 @@ class Options(ctypes.Structure):
         ("waves_per_group", ctypes.c_int32),
         ("chunk_freqs", ctypes.c_int32),
         ("tune_cache", ctypes.c_char_p),
+        ("profile", ctypes.c_int32),
     ]
 
 
@@ -113,6 +114,8 @@ def load(path: str = LIB_PATH):
     lib.fpw_eval_fp64.restype = ctypes.c_int
     lib.fpw_debug_bins.argtypes = [P, i32, i64, i64, i64, P, P]
     lib.fpw_debug_bins.restype = ctypes.c_int
+    lib.fpw_pass_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
+    lib.fpw_pass_timings.restype = ctypes.c_int
     lib.fpw_get_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     lib.fpw_get_plan_info.restype = ctypes.c_int
     lib.fpw_plan_destroy.argtypes = [P]
@@ -138,7 +141,7 @@ def default_options() -> Options:
 
 def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="fp64", stat_scale="eq1", topk=0,
                  inv_alpha2=0.0, autotune=False, use_graph=True, freqs_per_lane=0, waves_per_group=0, chunk_freqs=0,
-                 tune_cache=None) -> Options:
+                 tune_cache=None, profile=False) -> Options:
     o = default_options()
     o.n_bins = int(n_bins)
     o.center = CENTER[center] if isinstance(center, str) else int(center)
@@ -154,6 +157,7 @@ def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="
     o.waves_per_group = int(waves_per_group)
     o.chunk_freqs = int(chunk_freqs)
     o.tune_cache = tune_cache.encode() if tune_cache else None
+    o.profile = int(bool(profile))
     return o
 
 
@@ -248,6 +252,12 @@ class Plan:
         _check(load().fpw_debug_bins(self._h, int(phase), int(curve), int(f_begin), int(f_end),
                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
+
+    def timings(self):
+        """(prepare, batched, merge) kernel milliseconds of the last eval (plan made with profile=True)."""
+        ms = (ctypes.c_float * 3)()
+        _check(load().fpw_pass_timings(self._h, ms))
+        return float(ms[0]), float(ms[1]), float(ms[2])
 
     def info(self) -> PlanInfo:
         inf = PlanInfo()
