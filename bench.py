@@ -29,7 +29,7 @@ N_CU = 256
 CLOCK_HZ = 2.4e9
 VALU_PEAK = N_CU * 64 * CLOCK_HZ  # lane-ops/s: 64 lanes per CU per clock (FP64 FMA = 78.6 TFLOP/s / 2)
 LDS_PEAK = N_CU * 128 * CLOCK_HZ  # bytes/s: 128 B per CU per clock
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batched_config2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batched_ztf1000.json")
 # sources of the dominant (batched) kernel: its traffic figures are valid only for this exact code
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2502_00243_amd", "csrc", f) for f in ("fpw_batched.hip", "fpw_common.h")]
 
@@ -108,17 +108,28 @@ def main():
     ap.add_argument("--no-latency", action="store_true", help="skip the single-curve latency run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--workload", default="ztf1000", choices=["ztf1000", "uneven", "stress", "precision"],
+                    help="ztf1000: the headline line (default); uneven: 1e5 uneven curves, 2e5 freqs, "
+                         "M in {10,20,40}, top-5; stress: 2e4 x 3000-point curves, 1e6 freqs, M=50, top-5; "
+                         "precision: phase-arithmetic study on the ztf1000 data")
+    ap.add_argument("--curves", type=int, default=0, help="curve count override for uneven/stress")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the FPW build has no multi-GPU path "
               "(curves shard across GPUs with no collective in the hot loop; see the design notes).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "uneven":
+        return bench_uneven(args)
+    if args.workload == "stress":
+        return bench_stress(args)
+    if args.workload == "precision":
+        return bench_precision(args)
 
     import numpy as np
 
     from paper_2502_00243_amd import synth
 
-    batch = synth.config2()
+    batch = synth.ztf_batch()
     n_bins = batch.n_bins
     evals = batch.evals()
 
@@ -162,7 +173,7 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == "config2":
+        if tr.get("kernel_sha") == kernel_hash() and tr.get("workload") == "ztf1000":
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {
         "bound": "alu",
@@ -206,7 +217,7 @@ def main():
     # single-curve latency (1 curve, 200 points, 1e4 frequencies, M = 10), outputs preallocated
     lat_us = None
     if not args.no_latency:
-        b1 = synth.config1()
+        b1 = synth.single_curve()
         p1 = fpw.Plan.from_batch(b1, topk=1)
         S1 = torch.empty((1, len(b1.freqs)), dtype=torch.float32, device="cuda")
         i1 = torch.empty((1, 1), dtype=torch.int32, device="cuda")
@@ -253,6 +264,168 @@ def main():
         "latency_single_curve_us": lat_us,
     }
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------- other workloads
+def _time_passes(plan, steps, warmup, **kw):
+    import numpy as np
+    import torch
+
+    for _ in range(warmup):
+        plan.eval(**kw)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.eval(**kw)
+        kms.append(plan.timings())
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return wall, np.asarray(kms)
+
+
+def _roofline(evals, n_curves, n_freq, n_bins, n_points, kernel_ms):
+    ops = evals * 6.0 + n_curves * n_freq * 6.0 * n_bins
+    return {"bound": "alu", "achieved": ops / (kernel_ms * 1e-3) / 1e12, "peak": VALU_PEAK / 1e12,
+            "unit": "T lane-ops/s", "frac": ops / (kernel_ms * 1e-3) / VALU_PEAK,
+            "ops_per_eval": 6.0 + 6.0 * n_bins / (n_points / n_curves), "kernel_ms": kernel_ms,
+            "lds_frac": evals * 8 / (kernel_ms * 1e-3) / LDS_PEAK}
+
+
+def _fp64_rate(plan, evals):
+    import torch
+
+    plan.eval_fp64()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.eval_fp64()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"value": evals / (ms * 1e-3) / 1e9, "unit": "G evals/s", "ms": ms}
+
+
+def bench_uneven(args):
+    """1e5 curves of lognormal length (50-2000), 2e5 frequencies, M in {10, 20, 40}, fused top-5 only."""
+    import torch
+
+    from paper_2502_00243_amd import fpw, synth
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    batch = synth.uneven_batch(args.curves or 100_000)
+    log(f"generated {batch.n_curves} curves ({batch.n_points} points) in {time.perf_counter() - t0:.1f} s")
+    evals = batch.evals()
+    res = {}
+    total_ms = 0.0
+    for M in (10, 20, 40):
+        plan = fpw.Plan.from_batch(batch, n_bins=M, topk=5, profile=True)
+        idx = torch.empty((batch.n_curves, 5), dtype=torch.int32, device="cuda")
+        val = torch.empty((batch.n_curves, 5), dtype=torch.float32, device="cuda")
+        wall, kms = _time_passes(plan, max(1, min(args.steps, 3)), 1, store_s=False, idx_out=idx, val_out=val, topk=True)
+        info = plan.info()
+        total_ms += wall * 1e3
+        res[f"M{M}"] = {"ms_per_pass": wall * 1e3, "G_evals_per_s": evals / wall / 1e9,
+                        "kernel_ms": float(kms[:, 1].mean()), "merge_ms": float(kms[:, 2].mean()),
+                        "chunk_freqs": info.chunk_freqs, "grid_groups": info.grid_groups,
+                        "roofline": _roofline(evals, batch.n_curves, len(batch.freqs), M, batch.n_points,
+                                              float(kms[:, 1].mean()))}
+        log(f"M={M}: {wall * 1e3:.1f} ms/pass, {evals / wall / 1e9:.0f} G evals/s")
+        plan.close()
+        del idx, val
+    print(json.dumps({"workload": f"uneven: {batch.n_curves} curves (N lognormal 50-2000, sum {batch.n_points}), "
+                                  f"{len(batch.freqs)} freqs 0.05-50 /d, M in {{10,20,40}}, top-5, periodogram not stored",
+                      "evals_per_M": evals, "total_ms_three_M": total_ms,
+                      "value": 3 * evals / (total_ms * 1e-3) / 1e9, "unit": "G evals/s", "per_M": res}), flush=True)
+
+
+def bench_stress(args):
+    """2e4 curves x 3000 points over 2000 d, 1e6 frequencies to 200 /d, M = 50, top-5; FP64 comparator on a subset."""
+    import torch
+
+    from paper_2502_00243_amd import fpw, synth
+
+    torch.cuda.set_device(0)
+    batch = synth.stress_batch(args.curves or 20_000)
+    evals = batch.evals()
+    plan = fpw.Plan.from_batch(batch, topk=5, profile=True)
+    idx = torch.empty((batch.n_curves, 5), dtype=torch.int32, device="cuda")
+    val = torch.empty((batch.n_curves, 5), dtype=torch.float32, device="cuda")
+    wall, kms = _time_passes(plan, 1, 1, store_s=False, idx_out=idx, val_out=val, topk=True)
+    info = plan.info()
+    log(f"stress: {wall:.2f} s/pass, {evals / wall / 1e9:.0f} G evals/s")
+    plan.close()
+    # batched vs plain FP64 on the same 200-curve subset (the comparator stores the periodogram)
+    sub = batch.subset(range(min(200, batch.n_curves)))
+    ps = fpw.Plan.from_batch(sub, profile=True)
+    wall_s, kms_s = _time_passes(ps, 2, 1, store_s=True, topk=False)
+    fp = _fp64_rate(ps, sub.evals())
+    ps.close()
+    print(json.dumps({"workload": f"stress: {batch.n_curves} curves x 3000 points over 2000 d, "
+                                  f"{len(batch.freqs)} freqs 0.01-200 /d, M=50, top-5, periodogram not stored",
+                      "evals": evals, "s_per_pass": wall, "value": evals / wall / 1e9, "unit": "G evals/s",
+                      "chunk_freqs": info.chunk_freqs, "grid_groups": info.grid_groups,
+                      "roofline": _roofline(evals, batch.n_curves, len(batch.freqs), 50, batch.n_points,
+                                            float(kms[:, 1].mean())),
+                      "subset200": {"batched_G_evals_per_s": sub.evals() / wall_s / 1e9,
+                                    "fp64_plain": fp, "speedup": (sub.evals() / wall_s / 1e9) / fp["value"]}}),
+          flush=True)
+
+
+def bench_precision(args):
+    """Phase arithmetic study on the ztf1000 data: bin flips, S error and speed of each phase mode."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2502_00243_amd import fpw, synth
+
+    torch.cuda.set_device(0)
+    batch = synth.ztf_batch()
+    evals = batch.evals()
+    rng = np.random.default_rng(3)
+    curves = rng.choice(batch.n_curves, 24, replace=False)
+    fidx = np.sort(rng.choice(len(batch.freqs), 400, replace=False))
+    # oracle references for the sample
+    refs = {}
+    for c in curves:
+        t, y, dy = batch.curve(int(c))
+        tau, w, x = oracle.prepare_curve(t, y, dy)
+        f = batch.freqs[fidx]
+        ob = oracle.phase_bins(tau[None, :], f[:, None], batch.n_bins)
+        near = oracle.edge_distance(tau[None, :], f[:, None], batch.n_bins) < oracle.EPS_BIN
+        S = np.array([oracle.statistic(*oracle.bin_sums(ob[r], w, x, batch.n_bins)[:2]) for r in range(len(f))])
+        refs[int(c)] = (ob, near, S)
+    out = {}
+    for phase in ("fp64", "fp64_listing", "df32", "fp32"):
+        plan = fpw.Plan.from_batch(batch, topk=5, phase=phase, profile=True)
+        S_gpu = torch.empty((batch.n_curves, len(batch.freqs)), dtype=torch.float32, device="cuda")
+        wall, kms = _time_passes(plan, 5, 2, S_out=S_gpu, topk=False)
+        S_host = S_gpu.cpu().numpy()
+        flips = total = flips_off = 0
+        rel = []
+        for c, (ob, near, S) in refs.items():
+            gb = plan.debug_bins(c, 0, len(batch.freqs)).cpu().numpy()[fidx]
+            d = gb != ob
+            flips += int(d.sum())
+            flips_off += int((d & ~near).sum())
+            total += d.size
+            r = np.abs(S_host[c, fidx] - S) / np.maximum(S, 1e-300)
+            rel.append(r)
+        rel = np.concatenate(rel)
+        out[phase] = {"kernel_ms": float(kms[:, 1].mean()), "G_evals_per_s": evals / (kms[:, 1].mean() * 1e-3) / 1e9,
+                      "bin_flip_fraction": flips / total, "off_edge_flip_fraction": flips_off / total,
+                      "S_rel_err_median": float(np.median(rel)), "S_rel_err_p99": float(np.quantile(rel, 0.99)),
+                      "S_rel_err_max": float(rel.max())}
+        log(f"{phase}: {out[phase]}")
+        plan.close()
+    base = out["fp64"]["kernel_ms"]
+    for ph in out:
+        out[ph]["speed_vs_fp64"] = base / out[ph]["kernel_ms"]
+    print(json.dumps({"workload": "precision study on the ztf1000 data (1000 curves, 1e5 freqs, M=20); "
+                                  "bins and S checked on 24 curves x 400 sampled frequencies against the FP64 oracle",
+                      "modes": out}), flush=True)
 
 
 if __name__ == "__main__":

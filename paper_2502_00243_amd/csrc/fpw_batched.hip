@@ -76,14 +76,16 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
       for (int q = 0; q < kBatch; ++q) r[q] = rc[i + q];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
+        const uint64_t pk = uniform_to_vgpr(r[q].pk);
 #pragma unroll
-        for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r[q].tau_bits) * kWave, r[q].pk);
+        for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r[q].tau_bits) * kWave, pk);
       }
     }
     for (; i < n; ++i) {
       const Rec r = rc[i];
+      const uint64_t pk = uniform_to_vgpr(r.pk);
 #pragma unroll
-      for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r.tau_bits) * kWave, r.pk);
+      for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r.tau_bits) * kWave, pk);
     }
     // reduce each sub-tile of 64 frequencies, store, and pick peaks
 #pragma unroll

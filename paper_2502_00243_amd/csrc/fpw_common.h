@@ -136,15 +136,18 @@ __device__ __forceinline__ uint64_t lds_take(uint64_t* p) {
   return __hip_atomic_exchange(p, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Eq. 1 term of one bin from its packed fixed-point word: Y_q^2 / (W_q + ia2q).
-__device__ __forceinline__ float bin_term(uint64_t v, float ia2q) {
+// Adds the Eq. 1 term of one bin, Y_q^2 / (W_q + ia2q), from its packed
+// fixed-point word.  Every non-empty bin has W_q >= 1 (weights are clamped to
+// at least one unit), and an empty bin has Y_q = 0, so clamping the
+// denominator at 1/2 leaves every term unchanged and makes empty bins add 0
+// without a branch.
+__device__ __forceinline__ float add_bin_term(float acc, uint64_t v, float ia2q) {
   const uint32_t l = lo32(v);
   const int32_t yq = (int32_t)l;
   const uint32_t wq = hi32(v) + (l >> 31);  // undo the borrow of a negative low word
-  const float d = (float)wq + ia2q;
+  const float d = fmaxf((float)wq + ia2q, 0.5f);
   const float yf = (float)yq;
-  const float t = yf * (yf * __builtin_amdgcn_rcpf(d));
-  return d > 0.f ? t : 0.f;
+  return __builtin_fmaf(yf, yf * __builtin_amdgcn_rcpf(d), acc);
 }
 
 // Reads and clears one lane's histogram (slot m at h + 64 m) and returns
@@ -153,9 +156,17 @@ template <int PH>
 __device__ __forceinline__ float reduce_hist(uint64_t* h, int M, float ia2q) {
   uint64_t v0 = lds_take(h);
   if (PH == PH_FP64) v0 += lds_take(h + M * kWave);
-  float acc = bin_term(v0, ia2q);
-  for (int m = 1; m < M; ++m) acc += bin_term(lds_take(h + m * kWave), ia2q);
+  float acc = add_bin_term(0.f, v0, ia2q);
+  for (int m = 1; m < M; ++m) acc = add_bin_term(acc, lds_take(h + m * kWave), ia2q);
   return acc;
+}
+
+// Copies a wave-uniform 64-bit value from SGPRs to a VGPR pair in one
+// instruction (the data operand of an LDS atomic must be a VGPR).
+__device__ __forceinline__ uint64_t uniform_to_vgpr(uint64_t s) {
+  uint64_t v;
+  asm("v_mov_b64 %0, %1" : "=v"(v) : "s"(s));
+  return v;
 }
 
 // ---------------------------------------------------------------- top-k lists

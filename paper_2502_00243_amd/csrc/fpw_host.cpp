@@ -222,11 +222,12 @@ std::vector<fpw::Item> queue_order(const fpw_plan_s* p, const std::vector<fpw::I
 
 int round_up(int64_t v, int64_t m) { return (int)(((v + m - 1) / m) * m); }
 
-// Default chunk: about four work items per persistent wave, at least one
-// sweep of the wave, at most 16384 frequencies.
+// Default chunk: about twelve work items per persistent wave (enough for the
+// queue to even out the tail), at least one sweep of the wave, at most 16384
+// frequencies.
 int default_chunk(const fpw_plan_s* p, const fpw::Shape& s, int total_waves) {
   const int sweep = s.freqs_per_lane * kWave;
-  const double per_curve_items = std::max(1.0, 4.0 * total_waves / (double)p->n_curves);
+  const double per_curve_items = std::max(1.0, 12.0 * total_waves / (double)p->n_curves);
   int64_t chunk = (int64_t)std::ceil((double)p->n_freq / per_curve_items);
   chunk = std::max<int64_t>(chunk, sweep);
   chunk = std::min<int64_t>(chunk, 16384);

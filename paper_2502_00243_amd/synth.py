@@ -21,24 +21,25 @@ import numpy as np
 
 __all__ = [
     "Batch",
-    "make_config",
-    "config1",
-    "config2",
-    "config4",
-    "config5",
+    "workload",
+    "single_curve",
+    "ztf_batch",
+    "uneven_batch",
+    "stress_batch",
     "random_batch",
-    "CONFIG_FREQS",
+    "GRIDS",
 ]
 
-# Trial-frequency grids (1/day): start, stop, count.
-CONFIG_FREQS = {
-    1: (0.01, 10.0, 10_000),
-    2: (0.05, 50.0, 100_000),
-    3: (0.05, 50.0, 100_000),
-    4: (0.05, 50.0, 200_000),
-    5: (0.01, 200.0, 1_000_000),
+# Trial-frequency grids (1/day): start, stop, count; and the bin count of each workload.
+GRIDS = {
+    "single": (0.01, 10.0, 10_000),
+    "ztf": (0.05, 50.0, 100_000),
+    "uneven": (0.05, 50.0, 200_000),
+    "stress": (0.01, 200.0, 1_000_000),
 }
-CONFIG_BINS = {1: 10, 2: 20, 3: 20, 4: 20, 5: 50}
+BINS = {"single": 10, "ztf": 20, "uneven": 20, "stress": 50}
+# independent seed streams per workload
+_SEED_ID = {"single": 1, "ztf": 2, "uneven": 4, "stress": 5}
 
 _KINDS = ("noise", "sinusoid", "eclipse", "sawtooth", "double")
 
@@ -95,8 +96,8 @@ class Batch:
         )
 
 
-def _seed(cfg_id: int, n_curves: int):
-    ss = np.random.SeedSequence([2502, 243, cfg_id])
+def _seed(name: str, n_curves: int):
+    ss = np.random.SeedSequence([2502, 243, _SEED_ID[name]])
     return [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(n_curves)]
 
 
@@ -157,25 +158,25 @@ def _assemble(curves, freqs, n_bins, labels, name) -> Batch:
     )
 
 
-def _grid(cfg_id: int) -> np.ndarray:
-    lo, hi, n = CONFIG_FREQS[cfg_id]
+def _grid(name: str) -> np.ndarray:
+    lo, hi, n = GRIDS[name]
     return np.linspace(lo, hi, n)
 
 
-def config1() -> Batch:
+def single_curve() -> Batch:
     """One curve: 200 uniform times over 1000 d, a 0.05-amplitude 0.37-d sinusoid."""
-    (rng,) = _seed(1, 1)
+    (rng,) = _seed("single", 1)
     n = 200
     t = np.sort(rng.uniform(0.0, 1000.0, n))
     dy = rng.uniform(0.01, 0.05, n)
     y = 0.05 * np.sin(2.0 * np.pi * t / 0.37) + dy * rng.standard_normal(n)
     lab = [dict(kind="sinusoid", f0=1.0 / 0.37, amp=0.05)]
-    return _assemble([(t, y, dy)], _grid(1), CONFIG_BINS[1], lab, "config1")
+    return _assemble([(t, y, dy)], _grid("single"), BINS["single"], lab, "single_curve")
 
 
-def config2(n_curves: int = 1000, cfg_id: int = 2) -> Batch:
+def ztf_batch(n_curves: int = 1000) -> Batch:
     """ZTF-like cadence over 1500 d: 10% sinusoids, 10% box eclipses, 80% noise."""
-    rngs = _seed(cfg_id, n_curves)
+    rngs = _seed("ztf", n_curves)
     nights = _observable_nights(1500.0)
     curves, labels = [], []
     for c, rng in enumerate(rngs):
@@ -200,7 +201,7 @@ def config2(n_curves: int = 1000, cfg_id: int = 2) -> Batch:
         else:
             labels.append(dict(kind="noise", f0=0.0, amp=0.0))
         curves.append((t, y, dy))
-    return _assemble(curves, _grid(2), CONFIG_BINS[2], labels, "config2")
+    return _assemble(curves, _grid("ztf"), BINS["ztf"], labels, "ztf_batch")
 
 
 def _mixed_waveform_curve(rng, t, dy, f0):
@@ -214,9 +215,9 @@ def _mixed_waveform_curve(rng, t, dy, f0):
     return amp * s, dict(kind=kind, f0=f0, amp=amp, duty=duty, snr=snr_target)
 
 
-def config4(n_curves: int = 100_000, cfg_id: int = 4) -> Batch:
+def uneven_batch(n_curves: int = 100_000) -> Batch:
     """Uneven lengths (lognormal, 50-2000), 500-2000 d baselines, four waveform kinds."""
-    rngs = _seed(cfg_id, n_curves)
+    rngs = _seed("uneven", n_curves)
     curves, labels = [], []
     for rng in rngs:
         n = int(np.clip(np.round(np.exp(rng.normal(np.log(300.0), 0.8))), 50, 2000))
@@ -228,12 +229,12 @@ def config4(n_curves: int = 100_000, cfg_id: int = 4) -> Batch:
         s, lab = _mixed_waveform_curve(rng, t, dy, f0)
         curves.append((t, s + dy * rng.standard_normal(n), dy))
         labels.append(lab)
-    return _assemble(curves, _grid(4), CONFIG_BINS[4], labels, "config4")
+    return _assemble(curves, _grid("uneven"), BINS["uneven"], labels, "uneven_batch")
 
 
-def config5(n_curves: int = 20_000, cfg_id: int = 5) -> Batch:
+def stress_batch(n_curves: int = 20_000) -> Batch:
     """3000 uniform times over 2000 d per curve, periods down to ~10 min, M = 50."""
-    rngs = _seed(cfg_id, n_curves)
+    rngs = _seed("stress", n_curves)
     curves, labels = [], []
     for rng in rngs:
         n = 3000
@@ -243,19 +244,20 @@ def config5(n_curves: int = 20_000, cfg_id: int = 5) -> Batch:
         s, lab = _mixed_waveform_curve(rng, t, dy, f0)
         curves.append((t, s + dy * rng.standard_normal(n), dy))
         labels.append(lab)
-    return _assemble(curves, _grid(5), CONFIG_BINS[5], labels, "config5")
+    return _assemble(curves, _grid("stress"), BINS["stress"], labels, "stress_batch")
 
 
-def make_config(cfg_id: int, n_curves: int | None = None) -> Batch:
-    if cfg_id == 1:
-        return config1()
-    if cfg_id in (2, 3):
-        return config2(1000 if n_curves is None else n_curves, cfg_id=2)
-    if cfg_id == 4:
-        return config4(100_000 if n_curves is None else n_curves)
-    if cfg_id == 5:
-        return config5(20_000 if n_curves is None else n_curves)
-    raise ValueError(cfg_id)
+def workload(name: str, n_curves: int | None = None) -> Batch:
+    """Workload by name: single, ztf (1000 curves), uneven (1e5), stress (2e4)."""
+    if name == "single":
+        return single_curve()
+    if name == "ztf":
+        return ztf_batch(1000 if n_curves is None else n_curves)
+    if name == "uneven":
+        return uneven_batch(100_000 if n_curves is None else n_curves)
+    if name == "stress":
+        return stress_batch(20_000 if n_curves is None else n_curves)
+    raise ValueError(name)
 
 
 def random_batch(

@@ -44,9 +44,9 @@ def _check_plan_against_oracle(b, plan, opts, curves=None, exact_bins=False, fre
 
 
 @pytest.mark.parametrize("phase", ["fp64", "fp64_listing", "df32"])
-def test_config1_full(phase):
-    _say(f"config1 phase={phase}")
-    b = synth.config1()
+def test_single_curve_full(phase):
+    _say(f"single curve phase={phase}")
+    b = synth.single_curve()
     plan = fpw.Plan.from_batch(b, phase=phase, topk=5)
     g, S_gpu = _check_plan_against_oracle(b, plan, {}, exact_bins=phase == "fp64_listing")
     assert g < 1e-3
@@ -170,10 +170,10 @@ def test_graph_replays_are_identical():
     plan2.close()
 
 
-def test_config2_full_size_sampled():
+def test_ztf1000_full_size_sampled():
     """The benchmark's workload and launch configuration; sampled outputs against the oracle."""
-    _say("config2 full size")
-    b = synth.config2()
+    _say("ztf1000 full size")
+    b = synth.ztf_batch()
     plan = fpw.Plan.from_batch(b, topk=5)
     S, idx, val = plan.eval()
     torch.cuda.synchronize()
@@ -188,9 +188,75 @@ def test_config2_full_size_sampled():
         t, y, dy = b.curve(int(c))
         gb = plan.debug_bins(int(c), 0, len(b.freqs)).cpu().numpy()[fi]
         S_ref, S_abs, _ = parity.reference_for_curve(t, y, dy, b.freqs[fi], b.n_bins, opt, gpu_bins=gb)
-        parity.assert_s_close(S[c, fi], S_ref, S_abs, what=f"config2 curve {c}")
+        parity.assert_s_close(S[c, fi], S_ref, S_abs, what=f"ztf1000 curve {c}")
     # whole periodograms of two curves, and their peaks
     for c in (int(np.argmax(b.lengths)), 7):
         ref = oracle.curve_periodogram(*b.curve(c), b.freqs, b.n_bins)
         parity.assert_topk_near_oracle(ref, idx[c], val[c], 5)
+    plan.close()
+
+
+def test_uneven_subset_full_grid():
+    """Uneven lengths (50-2000 points) at the full 2e5-frequency grid, M = 40, fused top-5."""
+    _say("uneven subset")
+    b = synth.uneven_batch(300)
+    plan = fpw.Plan.from_batch(b, n_bins=40, topk=5)
+    _, idx_f, val_f = plan.eval(store_s=False)  # fused only: the periodogram never leaves the chip
+    S, idx, val = plan.eval()
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    np.testing.assert_array_equal(idx_f.cpu().numpy(), idx.cpu().numpy())
+    np.testing.assert_array_equal(val_f.cpu().numpy(), val.cpu().numpy())
+    parity.assert_topk_matches_rule(S, idx.cpu().numpy(), val.cpu().numpy(), 5)
+    rng = np.random.default_rng(4)
+    opt = parity.oracle_options()
+    for c in list(rng.choice(b.n_curves, 10, replace=False)) + [int(np.argmax(b.lengths)), int(np.argmin(b.lengths))]:
+        c = int(c)
+        fi = np.sort(rng.choice(len(b.freqs), 80, replace=False))
+        t, y, dy = b.curve(c)
+        gb = plan.debug_bins(c, 0, len(b.freqs)).cpu().numpy()[fi]
+        S_ref, S_abs, _ = parity.reference_for_curve(t, y, dy, b.freqs[fi], 40, opt, gpu_bins=gb)
+        parity.assert_s_close(S[c, fi], S_ref, S_abs, what=f"uneven curve {c}")
+    c = int(np.argmin(b.lengths))
+    ref = oracle.curve_periodogram(*b.curve(c), b.freqs, 40)
+    parity.assert_topk_near_oracle(ref, idx.cpu().numpy()[c], val.cpu().numpy()[c], 5)
+    plan.close()
+
+
+@pytest.mark.parametrize("phase", ["fp64", "df32"])
+def test_stress_subset_full_grid(phase):
+    """3000-point curves over 2000 d at the full 1e6-frequency grid to 200 /d, M = 50 (folds up to 4e5 cycles)."""
+    _say(f"stress subset phase={phase}")
+    b = synth.stress_batch(24)
+    plan = fpw.Plan.from_batch(b, topk=5, phase=phase)
+    S, idx, val = plan.eval()
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    parity.assert_topk_matches_rule(S, idx.cpu().numpy(), val.cpu().numpy(), 5)
+    rng = np.random.default_rng(5)
+    opt = parity.oracle_options()
+    nf = len(b.freqs)
+    for c in range(0, b.n_curves, 3):
+        # the highest frequencies carry the largest folds
+        f0 = int(rng.integers(nf - 20000, nf - 64))
+        t, y, dy = b.curve(c)
+        gb = plan.debug_bins(c, f0, f0 + 64).cpu().numpy()
+        S_ref, S_abs, _ = parity.reference_for_curve(t, y, dy, b.freqs[f0:f0 + 64], 50, opt, gpu_bins=gb)
+        parity.assert_s_close(S[c, f0:f0 + 64], S_ref, S_abs, what=f"stress curve {c}")
+        fi = np.sort(rng.choice(nf, 40, replace=False))
+        gb = np.stack([plan.debug_bins(c, int(k), int(k) + 1).cpu().numpy()[0] for k in fi])
+        S_ref, S_abs, _ = parity.reference_for_curve(t, y, dy, b.freqs[fi], 50, opt, gpu_bins=gb)
+        parity.assert_s_close(S[c, fi], S_ref, S_abs, what=f"stress curve {c} sampled")
+    plan.close()
+
+
+def test_fp32_naive_phase_flips_bins_at_large_folds():
+    """The naive FP32 fold is a study mode: at 1e5+ cycles it must visibly disagree with the FP64 bins."""
+    _say("naive fp32 flips")
+    b = synth.stress_batch(2)
+    plan = fpw.Plan.from_batch(b, phase="fp32")
+    nf = len(b.freqs)
+    gb = plan.debug_bins(0, nf - 64, nf).cpu().numpy()
+    ob = oracle.curve_bins(b.curve(0)[0], b.freqs[nf - 64:], 50)
+    assert (gb != ob).mean() > 0.05
     plan.close()

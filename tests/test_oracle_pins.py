@@ -334,8 +334,8 @@ def test_sampled_sinusoid_closed_form(M):
 # ---------------------------------------------------------------- periodogram behaviour
 
 
-def test_config1_peak_at_injected_period():
-    b = synth.config1()
+def test_single_curve_peak_at_injected_period():
+    b = synth.single_curve()
     S = oracle.curve_periodogram(*b.curve(0), b.freqs, b.n_bins)
     k = int(np.argmax(S))
     df = b.freqs[1] - b.freqs[0]
@@ -358,8 +358,8 @@ def test_subharmonic_peak():
     assert abs(freqs[np.argmax(S)] - f0) < 2e-3
 
 
-def test_injected_signals_recovered_config2():
-    b = synth.config2(60)
+def test_injected_signals_recovered_ztf_batch():
+    b = synth.ztf_batch(60)
     df = b.freqs[1] - b.freqs[0]
     hits = total = 0
     for c, lab in enumerate(b.labels):
