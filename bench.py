@@ -108,10 +108,11 @@ def main():
     ap.add_argument("--no-latency", action="store_true", help="skip the single-curve latency run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="ztf1000", choices=["ztf1000", "uneven", "stress", "precision"],
+    ap.add_argument("--workload", default="ztf1000", choices=["ztf1000", "uneven", "stress", "precision", "sweep"],
                     help="ztf1000: the headline line (default); uneven: 1e5 uneven curves, 2e5 freqs, "
                          "M in {10,20,40}, top-5; stress: 2e4 x 3000-point curves, 1e6 freqs, M=50, top-5; "
-                         "precision: phase-arithmetic study on the ztf1000 data")
+                         "precision: phase-arithmetic study on the ztf1000 data; "
+                         "sweep: launch shapes x M on the ztf1000 data")
     ap.add_argument("--curves", type=int, default=0, help="curve count override for uneven/stress")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -124,6 +125,8 @@ def main():
         return bench_stress(args)
     if args.workload == "precision":
         return bench_precision(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
 
     import numpy as np
 
@@ -426,6 +429,32 @@ def bench_precision(args):
     print(json.dumps({"workload": "precision study on the ztf1000 data (1000 curves, 1e5 freqs, M=20); "
                                   "bins and S checked on 24 curves x 400 sampled frequencies against the FP64 oracle",
                       "modes": out}), flush=True)
+
+
+def bench_sweep(args):
+    """Kernel time of each point source and bin count on the ztf1000 data (one JSON line per shape)."""
+    import numpy as np
+    import torch
+
+    from paper_2502_00243_amd import fpw, synth
+
+    torch.cuda.set_device(0)
+    batch = synth.ztf_batch()
+    evals = batch.evals()
+    S = torch.empty((batch.n_curves, len(batch.freqs)), dtype=torch.float32, device="cuda")
+    idx = torch.empty((batch.n_curves, 5), dtype=torch.int32, device="cuda")
+    val = torch.empty((batch.n_curves, 5), dtype=torch.float32, device="cuda")
+    for M in (10, 20, 40, 50, 100):
+        for src in ("scalar", "dpp"):
+            plan = fpw.Plan.from_batch(batch, n_bins=M, topk=5, point_source=src, profile=True)
+            info = plan.info()
+            _, kms = _time_passes(plan, 4, 1, S_out=S, idx_out=idx, val_out=val)
+            k = float(np.median(kms[:, 1]))
+            print(json.dumps({"M": M, "point_source": src, "chunk_freqs": info.chunk_freqs, "grid_groups": info.grid_groups,
+                              "kernel_ms": k, "G_evals_per_s": evals / (k * 1e-3) / 1e9,
+                              "roofline_frac": _roofline(evals, batch.n_curves, len(batch.freqs), M, batch.n_points, k)["frac"]}),
+                  flush=True)
+            plan.close()
 
 
 if __name__ == "__main__":

@@ -101,6 +101,9 @@ typedef struct {
   int32_t waves_per_group;/* launch shape override, 0 = default: waves per workgroup (1, 2, 4) */
   int32_t chunk_freqs;    /* launch shape override, 0 = default: frequencies per work item */
   const char* tune_cache; /* path of a text cache of autotune results; NULL = none */
+  int32_t point_source;   /* launch shape override: how a wave fetches observations.
+                             0 = default (by M), 1 = scalar loads, 2 = vector loads + DPP
+                             broadcast (one frequency per lane) */
   int32_t profile;        /* 1: record HIP events around each kernel of fpw_eval_batch
                              (read them with fpw_pass_timings); the pass is then
                              launched kernel by kernel instead of as a graph */
@@ -190,6 +193,7 @@ typedef struct {
   int32_t work_items;     /* (curve, frequency chunk) items in the queue */
   int32_t lds_bytes;      /* LDS per workgroup */
   int32_t tuned;          /* 1 if the launch shape came from the autotuner or its cache */
+  int32_t point_source;   /* 1 scalar loads, 2 vector loads + DPP broadcast */
 } fpw_plan_info;
 
 fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);

@@ -23,6 +23,8 @@
 //  * work is a queue of (curve, frequency chunk) items, longest curves first,
 //    popped by persistent waves with one atomic each; the peak selection is
 //    fused so that large periodograms never reach HBM.
+#include <type_traits>
+
 #include "fpw_common.h"
 
 namespace fpw {
@@ -41,7 +43,96 @@ struct RO {
   const double* __restrict__ freqs;
 };
 
-template <int PH, int FL, int KC>
+// Where a wave's observations come from.
+//  SRC_SCALAR: wave-uniform scalar loads (8 records per batch) into SGPRs; tau
+//    is an SGPR operand of the fold and the packed word takes one v_mov_b64.
+//    Waiting for a scalar load also waits for the wave's outstanding LDS
+//    atomics, which high occupancy (small M) hides.
+//  SRC_DPP: one coalesced vector load brings 16 records into every row of 16
+//    lanes; each record is broadcast with two 64-bit DPP row_newbcast moves.
+//    Only vector-memory counters are waited on, so LDS atomics stay in
+//    flight; this suits large M, where the histograms leave room for few
+//    waves per CU.
+enum { SRC_SCALAR = 0, SRC_DPP = 1 };
+
+// Lane Q of each row of 16 lanes, broadcast to its row (64-bit DPP row_newbcast).
+template <int Q>
+__device__ __forceinline__ uint64_t row_bcast(uint64_t v) {
+  // every lane reads an existing lane, so the "old" operand is never used
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + Q, 0xf, 0xf, true);
+}
+
+template <int Q, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (Q < N) {
+    f(std::integral_constant<int, Q>{});
+    static_for<Q + 1, N>(f);
+  }
+}
+
+template <int PH, int FL, int SRC>
+__device__ __forceinline__ void accumulate(const Rec* __restrict__ rc, int n, const Folder<PH> (&fo)[FL],
+                                           uint64_t* const (&h)[FL], int lane) {
+  if (SRC == SRC_SCALAR) {
+    int i = 0;
+    for (; i + kBatch <= n; i += kBatch) {
+      Rec r[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) r[q] = rc[i + q];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const uint64_t pk = uniform_to_vgpr(r[q].pk);
+#pragma unroll
+        for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r[q].tau_bits) * kWave, pk);
+      }
+    }
+    for (; i < n; ++i) {
+      const Rec r = rc[i];
+      const uint64_t pk = uniform_to_vgpr(r.pk);
+#pragma unroll
+      for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r.tau_bits) * kWave, pk);
+    }
+  } else {
+    constexpr int kGroup = 16;
+    const int sub = lane & (kGroup - 1);
+    Rec cur = rc[sub < n ? sub : n - 1];
+    for (int g = 0; g < n; g += kGroup) {
+      const int nxt = g + kGroup + sub;
+      const Rec next = rc[nxt < n ? nxt : n - 1];  // prefetch (clamped, always in bounds)
+      const int cnt = n - g;  // wave-uniform
+      if (cnt >= kGroup) {
+        // a full group, straight-line: bins of four points are formed side by
+        // side before their four atomics, so the FP64 chains overlap
+        static_for<0, kGroup / 4>([&](auto rc4) {
+          constexpr int q0 = 4 * decltype(rc4)::value;
+          const uint64_t t0 = row_bcast<q0>(cur.tau_bits), t1 = row_bcast<q0 + 1>(cur.tau_bits);
+          const uint64_t t2 = row_bcast<q0 + 2>(cur.tau_bits), t3 = row_bcast<q0 + 3>(cur.tau_bits);
+#pragma unroll
+          for (int j = 0; j < FL; ++j) {
+            const int b0 = fo[j].bin(t0), b1 = fo[j].bin(t1), b2 = fo[j].bin(t2), b3 = fo[j].bin(t3);
+            lds_add(h[j] + b0 * kWave, row_bcast<q0>(cur.pk));
+            lds_add(h[j] + b1 * kWave, row_bcast<q0 + 1>(cur.pk));
+            lds_add(h[j] + b2 * kWave, row_bcast<q0 + 2>(cur.pk));
+            lds_add(h[j] + b3 * kWave, row_bcast<q0 + 3>(cur.pk));
+          }
+        });
+      } else {
+        static_for<0, kGroup>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          if (q < cnt) {
+            const uint64_t tb = row_bcast<q>(cur.tau_bits);
+            const uint64_t pk = row_bcast<q>(cur.pk);
+#pragma unroll
+            for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(tb) * kWave, pk);
+          }
+        });
+      }
+      cur = next;
+    }
+  }
+}
+
+template <int PH, int FL, int KC, int SRC>
 __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, const Item& item, uint64_t* hist,
                                              int lane) {
   const int M = a.n_bins;
@@ -69,24 +160,7 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
       h[j] = hist + (j * slots) * kWave + lane;
     }
     // fold, bin and accumulate every observation of the curve
-    int i = 0;
-    for (; i + kBatch <= n; i += kBatch) {
-      Rec r[kBatch];
-#pragma unroll
-      for (int q = 0; q < kBatch; ++q) r[q] = rc[i + q];
-#pragma unroll
-      for (int q = 0; q < kBatch; ++q) {
-        const uint64_t pk = uniform_to_vgpr(r[q].pk);
-#pragma unroll
-        for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r[q].tau_bits) * kWave, pk);
-      }
-    }
-    for (; i < n; ++i) {
-      const Rec r = rc[i];
-      const uint64_t pk = uniform_to_vgpr(r.pk);
-#pragma unroll
-      for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(r.tau_bits) * kWave, pk);
-    }
+    accumulate<PH, FL, SRC>(rc, n, fo, h, lane);
     // reduce each sub-tile of 64 frequencies, store, and pick peaks
 #pragma unroll
     for (int j = 0; j < FL; ++j) {
@@ -148,8 +222,11 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
   }
 }
 
-template <int PH, int FL, int KC>
-__global__ __launch_bounds__(256) void batched_kernel(BatchArgs a, const Rec* __restrict__ rec,
+// The DPP-source shapes serve large M, where LDS admits at most ~2 waves per
+// SIMD; telling the compiler so lets it spend registers on overlapping the
+// FP64 fold chains instead of minimising them.
+template <int PH, int FL, int KC, int SRC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == SRC_DPP ? 2 : 10))) void batched_kernel(BatchArgs a, const Rec* __restrict__ rec,
                                                       const int64_t* __restrict__ offsets,
                                                       const CurveConst* __restrict__ ccs,
                                                       const double* __restrict__ freqs,
@@ -167,7 +244,7 @@ __global__ __launch_bounds__(256) void batched_kernel(BatchArgs a, const Rec* __
     it = __builtin_amdgcn_readfirstlane(it);
     if (it >= a.n_items) break;
     const Item item = items[it];
-    process_item<PH, FL, KC>(a, ro, item, hist, lane);
+    process_item<PH, FL, KC, SRC>(a, ro, item, hist, lane);
   }
   // The last wave out resets the queue, so the next launch (or graph replay)
   // starts from zero without a memset.
@@ -181,26 +258,34 @@ __global__ __launch_bounds__(256) void batched_kernel(BatchArgs a, const Rec* __
   }
 }
 
-template <int PH, int FL, int KC>
+template <int PH, int FL, int KC, int SRC>
 void* batched_ptr() {
-  return (void*)&batched_kernel<PH, FL, KC>;
+  return (void*)&batched_kernel<PH, FL, KC, SRC>;
 }
 
-template <int PH, int FL>
+template <int PH, int FL, int SRC>
 void* batched_ptr_k(int kc) {
   switch (kc) {
-    case 0: return batched_ptr<PH, FL, 0>();
-    case 8: return batched_ptr<PH, FL, 8>();
-    default: return batched_ptr<PH, FL, 16>();
+    case 0: return batched_ptr<PH, FL, 0, SRC>();
+    case 8: return batched_ptr<PH, FL, 8, SRC>();
+    default: return batched_ptr<PH, FL, 16, SRC>();
   }
 }
 
-void* batched_fn(int phase, int fl, int kc) {
+template <int PH>
+void* batched_ptr_src(int fl, int kc, int src) {
+  if (src == SRC_DPP) return batched_ptr_k<PH, 1, SRC_DPP>(kc);
+  return fl == 2 ? batched_ptr_k<PH, 2, SRC_SCALAR>(kc) : batched_ptr_k<PH, 1, SRC_SCALAR>(kc);
+}
+
+// Instantiated shapes: two frequencies per lane exist for the FP64 folds with
+// scalar point loads only.
+void* batched_fn(int phase, int fl, int kc, int src) {
   switch (phase) {
-    case PH_FP64: return fl == 2 ? batched_ptr_k<PH_FP64, 2>(kc) : batched_ptr_k<PH_FP64, 1>(kc);
-    case PH_LISTING: return fl == 2 ? batched_ptr_k<PH_LISTING, 2>(kc) : batched_ptr_k<PH_LISTING, 1>(kc);
-    case PH_DF32: return batched_ptr_k<PH_DF32, 1>(kc);
-    default: return batched_ptr_k<PH_FP32, 1>(kc);
+    case PH_FP64: return batched_ptr_src<PH_FP64>(fl, kc, src);
+    case PH_LISTING: return batched_ptr_src<PH_LISTING>(fl, kc, src);
+    case PH_DF32: return src == SRC_DPP ? batched_ptr_k<PH_DF32, 1, SRC_DPP>(kc) : batched_ptr_k<PH_DF32, 1, SRC_SCALAR>(kc);
+    default: return src == SRC_DPP ? batched_ptr_k<PH_FP32, 1, SRC_DPP>(kc) : batched_ptr_k<PH_FP32, 1, SRC_SCALAR>(kc);
   }
 }
 
@@ -213,13 +298,13 @@ size_t batched_lds_bytes(const Shape& shape, int n_bins) {
 }
 
 hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, size_t lds_bytes, int* out) {
-  void* fn = batched_fn(phase, shape.freqs_per_lane, topk_capacity(topk));
+  void* fn = batched_fn(phase, shape.freqs_per_lane, topk_capacity(topk), shape.point_source);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, shape.waves_per_group * kWave, lds_bytes);
 }
 
 hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int grid_groups, size_t lds_bytes,
                           hipStream_t s) {
-  void* fn = batched_fn(phase, shape.freqs_per_lane, topk_capacity(a.topk));
+  void* fn = batched_fn(phase, shape.freqs_per_lane, topk_capacity(a.topk), shape.point_source);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (e != hipSuccess) return e;
   BatchArgs args = a;

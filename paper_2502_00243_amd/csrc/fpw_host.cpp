@@ -77,7 +77,7 @@ struct fpw_plan_s {
   DevBuf t, y, dy, offsets, freqs, rec, cc, tau64, w64, wx64;
   // work queue and peak-selection scratch
   DevBuf items, queue, cand_val, cand_idx, edge, slot_k0, curve_slot;
-  fpw::Shape shape{1, 1, 4096};
+  fpw::Shape shape{1, 1, 4096, 0};
   int grid_groups = 0;
   size_t lds_bytes = 0;
   int n_items = 0;
@@ -106,6 +106,8 @@ struct fpw_plan_s {
 namespace {
 
 const int kWave = 64;
+// Smallest M for which the default point source is the DPP broadcast.
+const int kDppMinBins = 32;
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -126,6 +128,9 @@ fpw_status check_options(const fpw_options& o) {
   if (!(o.waves_per_group == 0 || o.waves_per_group == 1 || o.waves_per_group == 2 || o.waves_per_group == 4))
     return fail(FPW_EINVAL, "waves_per_group must be 0, 1, 2 or 4");
   if (o.chunk_freqs < 0) return fail(FPW_EINVAL, "chunk_freqs must be >= 0");
+  if (o.point_source < 0 || o.point_source > 2) return fail(FPW_EINVAL, "point_source must be 0, 1 or 2");
+  if (o.point_source == 2 && o.freqs_per_lane == 2)
+    return fail(FPW_EUNSUPPORTED, "DPP point broadcast is built for one frequency per lane");
   return FPW_OK;
 }
 
@@ -368,17 +373,18 @@ std::string tune_key(const fpw_plan_s* p) {
   return k.str();
 }
 
-// Cache file: one line per key, "key fl waves chunk".
+// Cache file: one line per key, "key fl waves chunk source".
 bool cache_lookup(const char* path, const std::string& key, fpw::Shape* s) {
   if (!path) return false;
   std::ifstream f(path);
   std::string k;
-  int fl, w, ch;
-  while (f >> k >> fl >> w >> ch) {
+  int fl, w, ch, src;
+  while (f >> k >> fl >> w >> ch >> src) {
     if (k == key) {
       s->freqs_per_lane = fl;
       s->waves_per_group = w;
       s->chunk_freqs = ch;
+      s->point_source = src;
       return true;
     }
   }
@@ -394,7 +400,7 @@ void cache_store(const char* path, const std::string& key, const fpw::Shape& s) 
     while (f >> k && std::getline(f, rest)) lines[k] = rest;
   }
   std::ostringstream v;
-  v << " " << s.freqs_per_lane << " " << s.waves_per_group << " " << s.chunk_freqs;
+  v << " " << s.freqs_per_lane << " " << s.waves_per_group << " " << s.chunk_freqs << " " << s.point_source;
   lines[key] = v.str();
   std::ofstream f(path, std::ios::trunc);
   for (auto& kv : lines) f << kv.first << kv.second << "\n";
@@ -414,9 +420,10 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
   }
   std::vector<fpw::Shape> cands;
   const int fls = p->opt.phase <= FPW_PHASE_FP64_LISTING ? 2 : 1;
-  for (int fl = 1; fl <= fls; ++fl)
-    for (int w : {1, 2, 4})
-      for (int cm : {1, 4}) cands.push_back(fpw::Shape{fl, w, -cm});
+  for (int src = 0; src <= 1; ++src)
+    for (int fl = 1; fl <= (src == 1 ? 1 : fls); ++fl)
+      for (int w : {1, 2})
+        for (int cm : {1, 4}) cands.push_back(fpw::Shape{fl, w, -cm, src});
   // calibration slice: about 2e9 evaluations
   const double target = 2e9;
   const double per_curve = (double)p->n_points / p->n_curves * (double)p->n_freq;
@@ -553,8 +560,12 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     FPW_HIP(hipMemsetAsync(p->queue.p, 0, 2 * sizeof(uint32_t), s), "clear queue");
     // prepared records are needed by autotune, fpw_eval_fp64 and fpw_debug_bins
     FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
-    fpw::Shape sh{o.freqs_per_lane ? o.freqs_per_lane : 1, o.waves_per_group ? o.waves_per_group : 1, o.chunk_freqs};
-    if (o.autotune && !o.freqs_per_lane && !o.waves_per_group && !o.chunk_freqs) {
+    // Large M leaves room for few waves per CU; their scalar-load waits then
+    // stall the LDS atomics, so the DPP broadcast source is the default there.
+    const int src = o.point_source ? o.point_source - 1 : (o.n_bins >= kDppMinBins ? 1 : 0);
+    fpw::Shape sh{src == 1 ? 1 : (o.freqs_per_lane ? o.freqs_per_lane : 1), o.waves_per_group ? o.waves_per_group : 1,
+                  o.chunk_freqs, src};
+    if (o.autotune && !o.freqs_per_lane && !o.waves_per_group && !o.chunk_freqs && !o.point_source) {
       st = autotune(p, s);
     } else {
       st = configure_shape(p, sh);
@@ -718,6 +729,7 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   info->work_items = p->n_items;
   info->lds_bytes = (int32_t)p->lds_bytes;
   info->tuned = p->tuned ? 1 : 0;
+  info->point_source = p->shape.point_source + 1;
   return FPW_OK;
 }
 

@@ -1,5 +1,5 @@
 // Internal interface between the host runtime (fpw_host.cpp) and the HIP
-// kernels (fpw_device.hip).  Not part of the public ABI.
+// kernels (fpw_batched.hip, fpw_aux.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -119,6 +119,7 @@ struct Shape {
   int freqs_per_lane;   // 1 or 2
   int waves_per_group;  // 1, 2 or 4
   int chunk_freqs;      // frequencies per work item
+  int point_source;     // 0: scalar loads, 1: vector loads + DPP broadcast (one frequency per lane)
 };
 
 // Launchers; each returns the hipError_t of its launch.
@@ -134,7 +135,7 @@ hipError_t launch_bins(const BinsArgs& a, hipStream_t s);
 size_t batched_lds_bytes(const Shape& shape, int n_bins);
 // Persistent workgroups per CU the batched kernel reaches for this shape.
 hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, size_t lds_bytes, int* out);
-// Top-k list length the kernels are instantiated for (smallest of 4, 8, 16 >= k).
+// Top-k list length the kernels are instantiated for (8 or 16; 0 without peaks).
 int topk_capacity(int k);
 
 }  // namespace fpw

@@ -51,6 +51,7 @@ class Options(ctypes.Structure):
         ("waves_per_group", ctypes.c_int32),
         ("chunk_freqs", ctypes.c_int32),
         ("tune_cache", ctypes.c_char_p),
+        ("point_source", ctypes.c_int32),
         ("profile", ctypes.c_int32),
     ]
 
@@ -71,6 +72,7 @@ class PlanInfo(ctypes.Structure):
         ("work_items", ctypes.c_int32),
         ("lds_bytes", ctypes.c_int32),
         ("tuned", ctypes.c_int32),
+        ("point_source", ctypes.c_int32),
     ]
 
 
@@ -141,7 +143,7 @@ def default_options() -> Options:
 
 def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="fp64", stat_scale="eq1", topk=0,
                  inv_alpha2=0.0, autotune=False, use_graph=True, freqs_per_lane=0, waves_per_group=0, chunk_freqs=0,
-                 tune_cache=None, profile=False) -> Options:
+                 tune_cache=None, profile=False, point_source=0) -> Options:
     o = default_options()
     o.n_bins = int(n_bins)
     o.center = CENTER[center] if isinstance(center, str) else int(center)
@@ -158,6 +160,7 @@ def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="
     o.chunk_freqs = int(chunk_freqs)
     o.tune_cache = tune_cache.encode() if tune_cache else None
     o.profile = int(bool(profile))
+    o.point_source = {"auto": 0, "scalar": 1, "dpp": 2}[point_source] if isinstance(point_source, str) else int(point_source)
     return o
 
 

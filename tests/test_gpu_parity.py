@@ -61,8 +61,12 @@ def test_single_curve_full(phase):
 
 
 RAGGED = [
-    # (seed, M, phase, freqs_per_lane, waves_per_group, chunk)
+    # (seed, M, phase, freqs_per_lane, waves_per_group, chunk[, point source])
     (1, 10, "fp64", 1, 1, 128),
+    (9, 10, "fp64", 1, 2, 128, "dpp"),
+    (10, 20, "fp64_listing", 1, 1, 192, "dpp"),
+    (11, 50, "fp64", 1, 1, 128, "scalar"),
+    (12, 33, "df32", 1, 1, 64, "dpp"),
     (2, 20, "fp64", 2, 4, 256),
     (3, 1, "fp64", 1, 2, 128),
     (4, 3, "fp64_listing", 1, 1, 192),
@@ -73,13 +77,18 @@ RAGGED = [
 ]
 
 
-@pytest.mark.parametrize("seed,M,phase,fl,waves,chunk", RAGGED)
-def test_ragged_batch(seed, M, phase, fl, waves, chunk):
+@pytest.mark.parametrize("case", RAGGED, ids=lambda c: "-".join(map(str, c)))
+def test_ragged_batch(case):
     """Uneven curves (1..300 points), 477 frequencies (ragged last tile), several chunks per curve."""
-    _say(f"ragged seed={seed} M={M} phase={phase} fl={fl} waves={waves} chunk={chunk}")
+    seed, M, phase, fl, waves, chunk = case[:6]
+    src = case[6] if len(case) > 6 else "auto"
+    _say(f"ragged seed={seed} M={M} phase={phase} fl={fl} waves={waves} chunk={chunk} source={src}")
     freqs = np.linspace(0.05, 30.0, 477)
     b = synth.random_batch(seed, 12, 1, 300, freqs, M)
-    plan = fpw.Plan.from_batch(b, phase=phase, topk=4, freqs_per_lane=fl, waves_per_group=waves, chunk_freqs=chunk)
+    plan = fpw.Plan.from_batch(b, phase=phase, topk=4, freqs_per_lane=fl, waves_per_group=waves, chunk_freqs=chunk,
+                               point_source=src)
+    if src != "auto":
+        assert plan.info().point_source == (1 if src == "scalar" else 2)
     _check_plan_against_oracle(b, plan, {}, exact_bins=phase == "fp64_listing")
     S, idx, val = plan.eval()
     torch.cuda.synchronize()
