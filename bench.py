@@ -337,10 +337,26 @@ def bench_uneven(args):
         log(f"M={M}: {wall * 1e3:.1f} ms/pass, {evals / wall / 1e9:.0f} G evals/s")
         plan.close()
         del idx, val
+    # the three bin counts from one M = 40 pass (Sec. 3.4): offsets 0 only, then every offset
+    multi = {}
+    for all_off in (False, True):
+        plan = fpw.Plan.from_batch(batch, n_bins=40, derived_bins=(20, 10), all_offsets=all_off, topk=5, profile=True)
+        nv = plan.n_variants
+        idx = torch.empty((nv, batch.n_curves, 5), dtype=torch.int32, device="cuda")
+        val = torch.empty((nv, batch.n_curves, 5), dtype=torch.float32, device="cuda")
+        wall, kms = _time_passes(plan, max(1, min(args.steps, 3)), 1, store_s=False, idx_out=idx, val_out=val, topk=True)
+        multi["all_offsets" if all_off else "offset0"] = {
+            "variants": nv, "ms_per_pass": wall * 1e3, "kernel_ms": float(kms[:, 1].mean()),
+            "merge_ms": float(kms[:, 2].mean()),
+            "speedup_vs_three_passes": total_ms / (wall * 1e3)}
+        log(f"multi-M (40 -> 20, 10; {nv} variants): {wall * 1e3:.1f} ms/pass")
+        plan.close()
+        del idx, val
     print(json.dumps({"workload": f"uneven: {batch.n_curves} curves (N lognormal 50-2000, sum {batch.n_points}), "
                                   f"{len(batch.freqs)} freqs 0.05-50 /d, M in {{10,20,40}}, top-5, periodogram not stored",
                       "evals_per_M": evals, "total_ms_three_M": total_ms,
-                      "value": 3 * evals / (total_ms * 1e-3) / 1e9, "unit": "G evals/s", "per_M": res}), flush=True)
+                      "value": 3 * evals / (total_ms * 1e-3) / 1e9, "unit": "G evals/s", "per_M": res,
+                      "multi_M_one_pass": multi}), flush=True)
 
 
 def bench_stress(args):

@@ -82,6 +82,8 @@ enum {
 };
 
 #define FPW_MAX_BINS 255      /* largest M (phase-bin histograms live in LDS) */
+#define FPW_MAX_DERIVED 4     /* derived bin counts per plan (multi-M reuse) */
+#define FPW_MAX_VARIANTS 8    /* periodograms per pass: (M, offset) variants */
 #define FPW_MAX_TOPK 16       /* largest k for peak selection */
 #define FPW_MAX_CURVE_POINTS (1 << 24)
 
@@ -104,6 +106,13 @@ typedef struct {
   int32_t point_source;   /* launch shape override: how a wave fetches observations.
                              0 = default (by M), 1 = scalar loads, 2 = vector loads + DPP
                              broadcast (one frequency per lane) */
+  int32_t derived_bins[FPW_MAX_DERIVED];
+                          /* multi-M reuse (Sec. 3.4): further bin counts M' < n_bins that
+                             divide n_bins, 0-terminated.  Their sums are combined from the
+                             n_bins fine sums of the same pass: coarse bin c of offset o
+                             covers fine bins o + c*k .. o + c*k + k-1 (mod n_bins),
+                             k = n_bins / M'.  Default: none. */
+  int32_t all_offsets;    /* 1: every offset o = 0..k-1 of each derived M'; 0: offset 0 only */
   int32_t profile;        /* 1: record HIP events around each kernel of fpw_eval_batch
                              (read them with fpw_pass_timings); the pass is then
                              launched kernel by kernel instead of as a graph */
@@ -135,12 +144,17 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
 /*
  * One pass of the periodogram over the plan's batch (Eq. 1 for every curve and
  * frequency): prepares weights, centred fluxes and time offsets on the device,
- * folds, bins, accumulates and reduces, and selects peaks.
- *   S_dev     DEVICE float32 [n_curves * n_freq], row-major by curve, or NULL to
- *             not store the periodogram.
- *   topk_idx  DEVICE int32 [n_curves * opt.topk]: frequency indices of the highest
- *             peaks, best first (ties: lower index first); -1 where a curve has fewer.
- *   topk_val  DEVICE float32 [n_curves * opt.topk]: their S values (-inf where idx = -1).
+ * folds, bins, accumulates and reduces, and selects peaks.  A plan has
+ * n_variants periodograms per curve (1 without derived bin counts; see
+ * fpw_variant): variant 0 is n_bins at offset 0, then each derived M' with its
+ * offsets in order.
+ *   S_dev     DEVICE float32 [n_variants * n_curves * n_freq], row-major (variant,
+ *             curve, frequency), or NULL to not store the periodogram.
+ *   topk_idx  DEVICE int32 [n_variants * n_curves * opt.topk]: frequency indices of
+ *             the highest peaks, best first (ties: lower index first); -1 where a
+ *             curve has fewer.
+ *   topk_val  DEVICE float32 [n_variants * n_curves * opt.topk]: their S values
+ *             (-inf where idx = -1).
  *             Both NULL, or both non-NULL with opt.topk > 0 (else FPW_EINVAL).
  * Peak rule: index k is a peak iff S[k] > S[k-1] and S[k] >= S[k+1], with
  * S[-1] = S[n_freq] = -inf.
@@ -183,6 +197,9 @@ fpw_status fpw_debug_bins(fpw_plan_t plan, int32_t phase, int64_t curve, int64_t
  */
 fpw_status fpw_pass_timings(fpw_plan_t plan, float ms[3]);
 
+/* Bin count and offset of periodogram variant v (0 <= v < n_variants). */
+fpw_status fpw_variant(fpw_plan_t plan, int32_t v, int32_t* n_bins, int32_t* offset);
+
 /* What a plan holds and the launch shape it chose. */
 typedef struct {
   int64_t n_curves, n_freq, n_points;
@@ -194,6 +211,7 @@ typedef struct {
   int32_t lds_bytes;      /* LDS per workgroup */
   int32_t tuned;          /* 1 if the launch shape came from the autotuner or its cache */
   int32_t point_source;   /* 1 scalar loads, 2 vector loads + DPP broadcast */
+  int32_t n_variants;     /* periodograms per curve and pass */
 } fpw_plan_info;
 
 fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);

@@ -57,6 +57,8 @@ __all__ = [
     "peak_mask",
     "topk",
     "batch_topk",
+    "combined_bins",
+    "variant_periodogram",
 ]
 
 # Bins of a point closer than this many bin widths to a bin edge may
@@ -280,3 +282,34 @@ def batch_topk(S2d: np.ndarray, k: int):
     for r in range(S2d.shape[0]):
         idx[r], val[r] = topk(S2d[r], k)
     return idx, val
+
+
+# ---------------------------------------------------------------- multiple M from M_max (Sec. 3.4)
+
+
+def combined_bins(fine_bins: np.ndarray, n_bins_max: int, n_bins: int, offset: int) -> np.ndarray:
+    """Coarse bin of each point when the fine bins of M_max are combined k = M_max / M at a time.
+
+    Sec. 3.4: sums for M = M_max / k are formed by combining the M_max sums,
+    with k choices of offset.  Coarse bin c of offset o holds fine bins
+    o + c k, ..., o + c k + k - 1 (mod M_max).
+    """
+    if n_bins_max % n_bins:
+        raise ValueError("M must divide M_max")
+    k = n_bins_max // n_bins
+    if not 0 <= offset < k:
+        raise ValueError("offset must be in [0, M_max / M)")
+    return ((np.asarray(fine_bins, dtype=np.int64) - offset) % n_bins_max) // k
+
+
+def variant_periodogram(t, y, dy, freqs, n_bins_max, n_bins, offset, opt: OracleOptions | None = None) -> np.ndarray:
+    """S(f) with M bins obtained from the M_max fine bins at the given offset (FP64)."""
+    opt = opt or OracleOptions()
+    tau, w, x = prepare_curve(t, y, dy, opt)
+    freqs = np.asarray(freqs, dtype=np.float64)
+    out = np.empty(len(freqs))
+    for r, f in enumerate(freqs):
+        b = combined_bins(phase_bins(tau, f, n_bins_max), n_bins_max, n_bins, offset)
+        W, Y, _ = bin_sums(b, w, x, n_bins)
+        out[r] = statistic(W, Y, opt.inv_alpha2, opt.stat_scale)
+    return out

@@ -9,33 +9,37 @@ namespace {
 using namespace dev;
 
 // ---------------------------------------------------------------- chunk merge
-// One wave per curve: lanes take the curve's chunks in turn, keep the best
-// candidates and decide the peaks on the chunk boundaries, then the wave
-// selects the curve's top k.
+// One wave per (curve, variant): lanes take the curve's chunks in turn, keep
+// the best candidates and decide the peaks on the chunk boundaries, then the
+// wave selects the curve's top k.
 template <int K>
 __global__ __launch_bounds__(256) void merge_kernel(MergeArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (c >= a.n_curves) return;  // wave-uniform
+  const int gw = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (gw >= a.n_curves * a.n_var) return;  // wave-uniform
+  const int v = gw / a.n_curves, c = gw - v * a.n_curves;
+  const int nv = a.n_var;
   TopList<K> l;
   l.init();
   const int q0 = a.curve_slot[c], q1 = a.curve_slot[c + 1];
   for (int q = q0 + lane; q < q1; q += kWave) {
+    const int64_t cq = ((int64_t)q * nv + v) * a.topk;
     for (int r = 0; r < a.topk; ++r) {
-      const int ci = a.cand_idx[(int64_t)q * a.topk + r];
-      l.insert(a.cand_val[(int64_t)q * a.topk + r], ci, ci >= 0);
+      const int ci = a.cand_idx[cq + r];
+      l.insert(a.cand_val[cq + r], ci, ci >= 0);
     }
     if (q > q0) {
       // b = first frequency of this chunk, b-1 = last of the previous one
       const int b = a.slot_k0[q];
-      const float* ep = a.edge + (int64_t)(q - 1) * 4;
-      const float* eq = a.edge + (int64_t)q * 4;
+      const float* ep = a.edge + ((int64_t)(q - 1) * nv + v) * 4;
+      const float* eq = a.edge + ((int64_t)q * nv + v) * 4;
       const float sa_left = ep[2], sa = ep[3], sb = eq[0], sb_right = eq[1];
       l.insert(sa, b - 1, sa > sa_left && sa >= sb);
       l.insert(sb, b, sb > sa && sb >= sb_right);
     }
   }
-  wave_select<K>(l, a.topk, a.out_val + (int64_t)c * a.topk, a.out_idx + (int64_t)c * a.topk, lane);
+  const int64_t o = ((int64_t)v * a.n_curves + c) * a.topk;
+  wave_select<K>(l, a.topk, a.out_val + o, a.out_idx + o, lane);
 }
 
 // ---------------------------------------------------------------- top-k over a stored periodogram
@@ -205,7 +209,7 @@ hipError_t launch_prepare(const PrepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
-  const int blocks = (a.n_curves + 3) / 4;
+  const int blocks = (a.n_curves * a.n_var + 3) / 4;
   if (a.topk <= 8)
     hipLaunchKernelGGL(merge_kernel<8>, dim3(blocks), dim3(256), 0, s, a);
   else

@@ -132,7 +132,123 @@ __device__ __forceinline__ void accumulate(const Rec* __restrict__ rc, int n, co
   }
 }
 
-template <int PH, int FL, int KC, int SRC>
+// Reduces one lane's fine histogram for every variant: variant v sums k[v]
+// consecutive fine bins (from fine bin o[v], cyclically) into each coarse
+// bin, exactly, then adds the Eq. 1 terms.  Two straight passes over the
+// lane's slots, with LDS traffic pipelined in blocks of eight:
+//  1. read the fine sums and write back the inclusive prefix sums
+//     P(m+1) = F(0) + ... + F(m) into slot m;
+//  2. for each variant, the coarse sum of window [s, e) is P(e) - P(s), with
+//     the prefix extended periodically, P(M + x) = P(M) + P(x), for the window
+//     that wraps around the end.  Variant 0 (the fine bins themselves) reads
+//     every slot; it goes last and clears each slot as it reads it, leaving
+//     the histogram zeroed for the next sweep.
+template <int PH, int NV>
+__device__ __forceinline__ void reduce_variants(uint64_t* h, int M, float ia2q, const Variants& vs, float (&out)[NV]) {
+  const uint64_t wrap = take_wrap_slot<PH>(h, M);
+  uint64_t run = 0;
+  for (int m0 = 0; m0 < M; m0 += kReduceBlock) {
+    uint64_t f[kReduceBlock];
+#pragma unroll
+    for (int q = 0; q < kReduceBlock; ++q) f[q] = h[min(m0 + q, M) * kWave];
+    if (m0 == 0) f[0] += wrap;
+#pragma unroll
+    for (int q = 0; q < kReduceBlock; ++q) {
+      if (m0 + q < M) {
+        run += f[q];
+        h[(m0 + q) * kWave] = run;
+      }
+    }
+  }
+  const uint64_t total = run;  // P(M)
+#pragma unroll
+  for (int vi = 0; vi < NV; ++vi) {
+    const int v = (vi + 1) % NV;  // 1, 2, ..., NV-1, then 0
+    out[v] = 0.f;
+    if (v < vs.n) {
+      const int k = vs.k[v], o = vs.o[v], mv = M / k;
+      uint64_t prev = o == 0 ? (uint64_t)0 : h[(o - 1) * kWave];  // P(o)
+      for (int c0 = 0; c0 < mv; c0 += kReduceBlock) {
+        uint64_t pe[kReduceBlock];
+#pragma unroll
+        for (int q = 0; q < kReduceBlock; ++q) {
+          // end of window c0+q: e = o + (c0+q+1) k, clamped past the last window
+          const int e = min(o + (c0 + q + 1) * k, M + o);
+          const int x = e > M ? e - M : e;  // 1 <= x <= M
+          pe[q] = v == 0 ? lds_take(h + (x - 1) * kWave) : h[(x - 1) * kWave];
+          if (e > M) pe[q] += total;
+        }
+#pragma unroll
+        for (int q = 0; q < kReduceBlock; ++q) {
+          if (c0 + q < mv) {
+            out[v] = add_bin_term(out[v], pe[q] - prev, ia2q);
+            prev = pe[q];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Peak bookkeeping of one periodogram variant along a work item.
+struct PeakState {
+  WaveTop top;
+  float pend_s, pend_left;  // S at kb-1 and kb-2 (wave-uniform)
+  __device__ __forceinline__ void init() {
+    top.init();
+    pend_s = -INFINITY;
+    pend_left = -INFINITY;
+  }
+  // One sub-tile of 64 frequencies kb .. kb+63 (lane = kb + lane), S value s.
+  // `pend`: index kb-1 still waits for its right neighbour.  Writes the four
+  // chunk-edge values to e.
+  __device__ __forceinline__ void step(float s, int kb, int k0, int k1, int n_freq, bool pend, int topk, float* e,
+                                       int lane) {
+    const int k = kb + lane;
+    const bool valid = k < k1;
+    const float sv = valid ? s : -INFINITY;
+    const float up = from_lane_below(sv);
+    const float dn = from_lane_above(sv);
+    const float s0 = lane_value(sv, 0);
+    // index kb-1 (lane 63 of the previous sub-tile) now has its right neighbour
+    if (pend && pend_s > pend_left && pend_s >= s0) top.offer(pend_s, kb - 1, lane == 0, topk, lane);
+    // left neighbour, or "undecided" at a chunk start that is not frequency 0
+    float left = up;
+    bool decided = valid;
+    if (lane == 0) {
+      if (kb == k0) {
+        left = -INFINITY;
+        decided = decided && k0 == 0;
+      } else {
+        left = pend_s;
+      }
+    }
+    // right neighbour: the chunk end, or the next sub-tile for lane 63
+    float right = dn;
+    if (k == k1 - 1) {
+      right = -INFINITY;
+      decided = decided && k1 == n_freq;
+    } else if (lane == kWave - 1) {
+      decided = false;  // deferred to the next sub-tile
+    }
+    top.offer(s, k, decided && s > left && s >= right, topk, lane);
+    pend_s = lane_value(sv, kWave - 1);
+    pend_left = lane_value(sv, kWave - 2);
+    // chunk-edge values for the merge
+    if (valid) {
+      if (k == k0) {
+        e[0] = s;
+        if (k0 + 1 >= k1) e[1] = -INFINITY;
+        if (k1 - 2 < k0) e[2] = -INFINITY;
+      }
+      if (k == k0 + 1) e[1] = s;
+      if (k == k1 - 2) e[2] = s;
+      if (k == k1 - 1) e[3] = s;
+    }
+  }
+};
+
+template <int PH, int FL, int PK, int SRC, int NV>
 __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, const Item& item, uint64_t* hist,
                                              int lane) {
   const int M = a.n_bins;
@@ -143,12 +259,15 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
   const Rec* __restrict__ rc = ro.rec + p0;
   const CurveConst cc = ro.cc[c];
   const float outscale = cc.kc * cc.scale;
+  const int nvar = NV == 1 ? 1 : a.var.n;
+  const int64_t var_stride = (int64_t)a.n_curves * a.n_freq;
 
-  constexpr int KL = KC > 0 ? KC : 1;
-  TopList<KL> list;
-  if (KC > 0) list.init();
-  float pend_s = -INFINITY, pend_left = -INFINITY;  // S at kb-1 and kb-2 (wave-uniform)
-  bool pend = false;                                 // index kb-1 still waits for its right neighbour
+  PeakState peaks[NV];
+  if (PK) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) peaks[v].init();
+  }
+  bool pend = false;  // the last index of the previous sub-tile waits for its right neighbour
 
   for (int kt = k0; kt < k1; kt += FL * kWave) {
     Folder<PH> fo[FL];
@@ -166,66 +285,39 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
     for (int j = 0; j < FL; ++j) {
       const int kb = kt + j * kWave;
       if (kb >= k1) break;
-      const float s = outscale * reduce_hist<PH>(h[j], M, cc.ia2q);
+      float sv[NV];
+      if constexpr (NV == 1) {
+        sv[0] = reduce_hist<PH>(h[j], M, cc.ia2q);
+      } else {
+        reduce_variants<PH, NV>(h[j], M, cc.ia2q, a.var, sv);
+      }
       const int k = kb + lane;
-      const bool valid = k < k1;
-      if (a.S != nullptr && valid) a.S[(int64_t)c * a.n_freq + k] = s;
-      if (KC > 0) {
-        const float sv = valid ? s : -INFINITY;
-        const float up = __shfl_up(sv, 1);
-        const float dn = __shfl_down(sv, 1);
-        // index kb-1 (lane 63 of the previous sub-tile) now has its right neighbour
-        const float s0 = __shfl(sv, 0);
-        if (pend) list.insert(pend_s, kb - 1, lane == kWave - 1 && pend_s > pend_left && pend_s >= s0);
-        // left neighbour, or "undecided" at a chunk start that is not frequency 0
-        float left = up;
-        bool decided = valid;
-        if (lane == 0) {
-          if (kb == k0) {
-            left = -INFINITY;
-            decided = decided && k0 == 0;
-          } else {
-            left = pend_s;
-          }
-        }
-        // right neighbour: the chunk end, or the next sub-tile for lane 63
-        float right = dn;
-        const bool last_of_chunk = k == k1 - 1;
-        if (last_of_chunk) {
-          right = -INFINITY;
-          decided = decided && k1 == a.n_freq;
-        } else if (lane == kWave - 1) {
-          decided = false;  // deferred to the next sub-tile
-        }
-        list.insert(s, k, decided && s > left && s >= right);
-        // carry lane 63 (and 62) forward
-        pend_s = __shfl(sv, kWave - 1);
-        pend_left = __shfl(sv, kWave - 2);
-        pend = kb + kWave - 1 < k1 - 1;
-        // chunk-edge values for the merge
-        if (valid) {
-          float* e = a.edge + (int64_t)item.slot * 4;
-          if (k == k0) {
-            e[0] = s;
-            if (k0 + 1 >= k1) e[1] = -INFINITY;
-            if (k1 - 2 < k0) e[2] = -INFINITY;
-          }
-          if (k == k0 + 1) e[1] = s;
-          if (k == k1 - 2) e[2] = s;
-          if (k == k1 - 1) e[3] = s;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (v < nvar) {
+          const float s = outscale * sv[v];
+          if (a.S != nullptr && k < k1) a.S[v * var_stride + (int64_t)c * a.n_freq + k] = s;
+          if (PK) peaks[v].step(s, kb, k0, k1, a.n_freq, pend, a.topk, a.edge + ((int64_t)item.slot * nvar + v) * 4, lane);
         }
       }
+      pend = kb + kWave - 1 < k1 - 1;
     }
   }
-  if (KC > 0) {
-    wave_select<KL>(list, a.topk, a.cand_val + (int64_t)item.slot * a.topk, a.cand_idx + (int64_t)item.slot * a.topk, lane);
+  if (PK) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (v < nvar) {
+        const int64_t o = ((int64_t)item.slot * nvar + v) * a.topk;
+        peaks[v].top.store(a.topk, a.cand_val + o, a.cand_idx + o, lane);
+      }
+    }
   }
 }
 
 // The DPP-source shapes serve large M, where LDS admits at most ~2 waves per
 // SIMD; telling the compiler so lets it spend registers on overlapping the
 // FP64 fold chains instead of minimising them.
-template <int PH, int FL, int KC, int SRC>
+template <int PH, int FL, int PK, int SRC, int NV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == SRC_DPP ? 2 : 10))) void batched_kernel(BatchArgs a, const Rec* __restrict__ rec,
                                                       const int64_t* __restrict__ offsets,
                                                       const CurveConst* __restrict__ ccs,
@@ -244,7 +336,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
     it = __builtin_amdgcn_readfirstlane(it);
     if (it >= a.n_items) break;
     const Item item = items[it];
-    process_item<PH, FL, KC, SRC>(a, ro, item, hist, lane);
+    process_item<PH, FL, PK, SRC, NV>(a, ro, item, hist, lane);
   }
   // The last wave out resets the queue, so the next launch (or graph replay)
   // starts from zero without a memset.
@@ -258,34 +350,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
   }
 }
 
-template <int PH, int FL, int KC, int SRC>
+template <int PH, int FL, int PK, int SRC, int NV>
 void* batched_ptr() {
-  return (void*)&batched_kernel<PH, FL, KC, SRC>;
+  return (void*)&batched_kernel<PH, FL, PK, SRC, NV>;
 }
 
-template <int PH, int FL, int SRC>
-void* batched_ptr_k(int kc) {
-  switch (kc) {
-    case 0: return batched_ptr<PH, FL, 0, SRC>();
-    case 8: return batched_ptr<PH, FL, 8, SRC>();
-    default: return batched_ptr<PH, FL, 16, SRC>();
-  }
+template <int PH, int FL, int SRC, int NV>
+void* batched_ptr_k(int pk) {
+  return pk ? batched_ptr<PH, FL, 1, SRC, NV>() : batched_ptr<PH, FL, 0, SRC, NV>();
 }
 
 template <int PH>
-void* batched_ptr_src(int fl, int kc, int src) {
-  if (src == SRC_DPP) return batched_ptr_k<PH, 1, SRC_DPP>(kc);
-  return fl == 2 ? batched_ptr_k<PH, 2, SRC_SCALAR>(kc) : batched_ptr_k<PH, 1, SRC_SCALAR>(kc);
+void* batched_ptr_src(int fl, int pk, int src, int nv) {
+  if (nv > 1) return src == SRC_DPP ? batched_ptr_k<PH, 1, SRC_DPP, kMaxVariants>(pk)
+                                    : batched_ptr_k<PH, 1, SRC_SCALAR, kMaxVariants>(pk);
+  if (src == SRC_DPP) return batched_ptr_k<PH, 1, SRC_DPP, 1>(pk);
+  if (PH == PH_DF32 || PH == PH_FP32) return batched_ptr_k<PH, 1, SRC_SCALAR, 1>(pk);
+  return fl == 2 ? batched_ptr_k<PH, 2, SRC_SCALAR, 1>(pk) : batched_ptr_k<PH, 1, SRC_SCALAR, 1>(pk);
 }
 
 // Instantiated shapes: two frequencies per lane exist for the FP64 folds with
-// scalar point loads only.
-void* batched_fn(int phase, int fl, int kc, int src) {
+// scalar point loads and one variant only; several variants take one
+// frequency per lane.
+void* batched_fn(int phase, int fl, int pk, int src, int nv) {
   switch (phase) {
-    case PH_FP64: return batched_ptr_src<PH_FP64>(fl, kc, src);
-    case PH_LISTING: return batched_ptr_src<PH_LISTING>(fl, kc, src);
-    case PH_DF32: return src == SRC_DPP ? batched_ptr_k<PH_DF32, 1, SRC_DPP>(kc) : batched_ptr_k<PH_DF32, 1, SRC_SCALAR>(kc);
-    default: return src == SRC_DPP ? batched_ptr_k<PH_FP32, 1, SRC_DPP>(kc) : batched_ptr_k<PH_FP32, 1, SRC_SCALAR>(kc);
+    case PH_FP64: return batched_ptr_src<PH_FP64>(fl, pk, src, nv);
+    case PH_LISTING: return batched_ptr_src<PH_LISTING>(fl, pk, src, nv);
+    case PH_DF32: return batched_ptr_src<PH_DF32>(1, pk, src, nv);
+    default: return batched_ptr_src<PH_FP32>(1, pk, src, nv);
   }
 }
 
@@ -297,14 +389,14 @@ size_t batched_lds_bytes(const Shape& shape, int n_bins) {
   return (size_t)shape.waves_per_group * shape.freqs_per_lane * (size_t)(n_bins + 1) * kWave * sizeof(uint64_t);
 }
 
-hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, size_t lds_bytes, int* out) {
-  void* fn = batched_fn(phase, shape.freqs_per_lane, topk_capacity(topk), shape.point_source);
+hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, int n_var, size_t lds_bytes, int* out) {
+  void* fn = batched_fn(phase, shape.freqs_per_lane, topk > 0, shape.point_source, n_var);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, shape.waves_per_group * kWave, lds_bytes);
 }
 
 hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int grid_groups, size_t lds_bytes,
                           hipStream_t s) {
-  void* fn = batched_fn(phase, shape.freqs_per_lane, topk_capacity(a.topk), shape.point_source);
+  void* fn = batched_fn(phase, shape.freqs_per_lane, a.topk > 0, shape.point_source, a.var.n);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (e != hipSuccess) return e;
   BatchArgs args = a;

@@ -150,15 +150,49 @@ __device__ __forceinline__ float add_bin_term(float acc, uint64_t v, float ia2q)
   return __builtin_fmaf(yf, yf * __builtin_amdgcn_rcpf(d), acc);
 }
 
+// Slots are read (and cleared) eight at a time so that the LDS round trips
+// overlap; slot indices past M are clamped to slot M, which is empty by then.
+constexpr int kReduceBlock = 8;
+
+// The FP64 fused fold files phases just below 1 in slot M; they belong to bin 0.
+template <int PH>
+__device__ __forceinline__ uint64_t take_wrap_slot(uint64_t* h, int M) {
+  return PH == PH_FP64 ? lds_take(h + M * kWave) : (uint64_t)0;
+}
+
+template <int PH>
+__device__ __forceinline__ void take_block(uint64_t* h, int M, int m0, uint64_t (&f)[kReduceBlock]) {
+#pragma unroll
+  for (int q = 0; q < kReduceBlock; ++q) f[q] = lds_take(h + min(m0 + q, M) * kWave);
+}
+
 // Reads and clears one lane's histogram (slot m at h + 64 m) and returns
-// sum_m Y_m^2 / (W_m + 1/alpha^2) in fixed-point units.
+// sum_m Y_m^2 / (W_m + 1/alpha^2) in fixed-point units, bins in order.
 template <int PH>
 __device__ __forceinline__ float reduce_hist(uint64_t* h, int M, float ia2q) {
-  uint64_t v0 = lds_take(h);
-  if (PH == PH_FP64) v0 += lds_take(h + M * kWave);
-  float acc = add_bin_term(0.f, v0, ia2q);
-  for (int m = 1; m < M; ++m) acc = add_bin_term(acc, lds_take(h + m * kWave), ia2q);
+  const uint64_t wrap = take_wrap_slot<PH>(h, M);
+  float acc = 0.f;
+  for (int m0 = 0; m0 < M; m0 += kReduceBlock) {
+    uint64_t f[kReduceBlock];
+    take_block<PH>(h, M, m0, f);
+    if (m0 == 0) f[0] += wrap;
+#pragma unroll
+    for (int q = 0; q < kReduceBlock; ++q)
+      if (m0 + q < M) acc = add_bin_term(acc, f[q], ia2q);
+  }
   return acc;
+}
+
+// Whole-wave neighbour exchange through DPP (no LDS traffic): the value of
+// lane i-1 (lane 0 keeps its own) and of lane i+1 (lane 63 keeps its own).
+__device__ __forceinline__ float from_lane_below(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_lane_above(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
 // Copies a wave-uniform 64-bit value from SGPRs to a VGPR pair in one
@@ -213,6 +247,54 @@ struct TopList {
     }
     v[K - 1] = -INFINITY;
     i[K - 1] = INT_MAX;
+  }
+};
+
+__device__ __forceinline__ int int_from_lane_below(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
+}
+
+// The k best peaks a wave has seen, spread over its lanes: lane r < k holds
+// entry r (best first), the other lanes hold (-inf, INT_MAX).  Two VGPRs per
+// list, however large k is; insertions run as a wave-uniform loop over the
+// candidate lanes, which are few once the list has filled.
+struct WaveTop {
+  float v;
+  int i;
+  __device__ __forceinline__ void init() {
+    v = -INFINITY;
+    i = INT_MAX;
+  }
+  // Offers (s, idx) of every lane where `pred` holds; k = list length.
+  __device__ __forceinline__ void offer(float s, int idx, bool pred, int k, int lane) {
+    const float tv = lane_value(v, k - 1);
+    const int ti = __builtin_amdgcn_readlane(i, k - 1);
+    uint64_t m = __ballot(pred && better(s, idx, tv, ti));
+    while (m) {
+      const int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const float cs = lane_value(s, l);
+      const int ci = __builtin_amdgcn_readlane(idx, l);
+      if (!better(cs, ci, lane_value(v, k - 1), __builtin_amdgcn_readlane(i, k - 1))) continue;
+      // entries better than the candidate form a prefix of length p
+      const int p = __popcll(__ballot(lane < k && better(v, i, cs, ci)));
+      const float vb = from_lane_below(v);
+      const int ib = int_from_lane_below(i);
+      if (lane == p) {
+        v = cs;
+        i = ci;
+      } else if (lane > p && lane < k) {
+        v = vb;
+        i = ib;
+      }
+    }
+  }
+  // Writes the list: (value, index) for r < k, index -1 where the value is -inf.
+  __device__ __forceinline__ void store(int k, float* out_v, int32_t* out_i, int lane) const {
+    if (lane < k) {
+      out_v[lane] = v;
+      out_i[lane] = v == -INFINITY ? -1 : i;
+    }
   }
 };
 

@@ -78,6 +78,8 @@ struct fpw_plan_s {
   // work queue and peak-selection scratch
   DevBuf items, queue, cand_val, cand_idx, edge, slot_k0, curve_slot;
   fpw::Shape shape{1, 1, 4096, 0};
+  fpw::Variants var{};        // periodogram variants (multi-M reuse); var.n >= 1
+  std::vector<int32_t> var_bins;  // bin count of each variant
   int grid_groups = 0;
   size_t lds_bytes = 0;
   int n_items = 0;
@@ -131,6 +133,19 @@ fpw_status check_options(const fpw_options& o) {
   if (o.point_source < 0 || o.point_source > 2) return fail(FPW_EINVAL, "point_source must be 0, 1 or 2");
   if (o.point_source == 2 && o.freqs_per_lane == 2)
     return fail(FPW_EUNSUPPORTED, "DPP point broadcast is built for one frequency per lane");
+  int nvar = 1;
+  for (int d = 0; d < FPW_MAX_DERIVED && o.derived_bins[d] != 0; ++d) {
+    const int m = o.derived_bins[d];
+    if (m < 1 || m >= o.n_bins || o.n_bins % m != 0)
+      return fail(FPW_EINVAL, "derived bin count %d must divide n_bins %d and be smaller", m, o.n_bins);
+    for (int e = 0; e < d; ++e)
+      if (o.derived_bins[e] == m) return fail(FPW_EINVAL, "derived bin count %d listed twice", m);
+    nvar += o.all_offsets ? o.n_bins / m : 1;
+  }
+  if (nvar > FPW_MAX_VARIANTS)
+    return fail(FPW_EUNSUPPORTED, "%d periodogram variants exceed FPW_MAX_VARIANTS=%d", nvar, FPW_MAX_VARIANTS);
+  if (nvar > 1 && o.freqs_per_lane == 2)
+    return fail(FPW_EUNSUPPORTED, "derived bin counts are built for one frequency per lane");
   return FPW_OK;
 }
 
@@ -243,7 +258,7 @@ fpw_status configure_shape(fpw_plan_s* p, fpw::Shape s) {
   const size_t lds = fpw::batched_lds_bytes(s, p->opt.n_bins);
   if (lds > 160 * 1024) return fail(FPW_EUNSUPPORTED, "LDS %zu bytes per workgroup exceeds 160 KiB", lds);
   int per_cu = 0;
-  FPW_HIP(fpw::batched_groups_per_cu(s, p->opt.phase, p->opt.topk, lds, &per_cu), "occupancy query");
+  FPW_HIP(fpw::batched_groups_per_cu(s, p->opt.phase, p->opt.topk, p->var.n, lds, &per_cu), "occupancy query");
   if (per_cu < 1) return fail(FPW_EUNSUPPORTED, "batched kernel does not fit on a CU with %zu bytes of LDS", lds);
   p->shape = s;
   p->lds_bytes = lds;
@@ -268,7 +283,7 @@ fpw_status upload_items(fpw_plan_s* p) {
   FPW_HIP(hipMemcpy(p->curve_slot.p, curve_slot.data(), curve_slot.size() * sizeof(int32_t), hipMemcpyHostToDevice),
           "upload curve_slot");
   if (p->opt.topk > 0) {
-    const size_t ns = nat.size();
+    const size_t ns = nat.size() * (size_t)p->var.n;
     FPW_HIP(p->cand_val.alloc(ns * p->opt.topk * sizeof(float)), "alloc cand_val");
     FPW_HIP(p->cand_idx.alloc(ns * p->opt.topk * sizeof(int32_t)), "alloc cand_idx");
     FPW_HIP(p->edge.alloc(ns * 4 * sizeof(float)), "alloc edge");
@@ -299,6 +314,8 @@ fpw::BatchArgs batch_args(const fpw_plan_s* p, float* S, const DevBuf& items, in
   a.n_freq = (int32_t)p->n_freq;
   a.n_bins = p->opt.n_bins;
   a.topk = p->opt.topk;
+  a.n_curves = (int32_t)p->n_curves;
+  a.var = p->var;
   a.S = S;
   a.cand_val = p->cand_val.as<float>();
   a.cand_idx = p->cand_idx.as<int32_t>();
@@ -338,6 +355,7 @@ fpw::MergeArgs merge_args(const fpw_plan_s* p, int32_t* idx, float* val) {
   m.n_curves = (int32_t)p->n_curves;
   m.n_freq = (int32_t)p->n_freq;
   m.topk = p->opt.topk;
+  m.n_var = p->var.n;
   m.out_idx = idx;
   m.out_val = val;
   return m;
@@ -419,7 +437,7 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
     }
   }
   std::vector<fpw::Shape> cands;
-  const int fls = p->opt.phase <= FPW_PHASE_FP64_LISTING ? 2 : 1;
+  const int fls = (p->opt.phase <= FPW_PHASE_FP64_LISTING && p->var.n == 1) ? 2 : 1;
   for (int src = 0; src <= 1; ++src)
     for (int fl = 1; fl <= (src == 1 ? 1 : fls); ++fl)
       for (int w : {1, 2})
@@ -452,9 +470,10 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
     DevBuf cv, ci, ed;
     fpw::BatchArgs a = batch_args(p, nullptr, items, (int)q.size());
     if (p->opt.topk > 0) {
-      FPW_HIP(cv.alloc(nat.size() * p->opt.topk * sizeof(float)), "alloc");
-      FPW_HIP(ci.alloc(nat.size() * p->opt.topk * sizeof(int32_t)), "alloc");
-      FPW_HIP(ed.alloc(nat.size() * 4 * sizeof(float)), "alloc");
+      const size_t ns = nat.size() * (size_t)p->var.n;
+      FPW_HIP(cv.alloc(ns * p->opt.topk * sizeof(float)), "alloc");
+      FPW_HIP(ci.alloc(ns * p->opt.topk * sizeof(int32_t)), "alloc");
+      FPW_HIP(ed.alloc(ns * 4 * sizeof(float)), "alloc");
       a.cand_val = cv.as<float>();
       a.cand_idx = ci.as<int32_t>();
       a.edge = ed.as<float>();
@@ -539,6 +558,20 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     p->n_freq = n_freq;
     p->n_points = offsets[n_curves];
     p->h_offsets.assign(offsets, offsets + n_curves + 1);
+    // variant 0: the fine binning; then each derived M' with its offsets
+    p->var.n = 1;
+    p->var.k[0] = 1;
+    p->var.o[0] = 0;
+    p->var_bins.assign(1, o.n_bins);
+    for (int d = 0; d < FPW_MAX_DERIVED && o.derived_bins[d] != 0; ++d) {
+      const int k = o.n_bins / o.derived_bins[d];
+      for (int off = 0; off < (o.all_offsets ? k : 1); ++off) {
+        p->var.k[p->var.n] = k;
+        p->var.o[p->var.n] = off;
+        p->var_bins.push_back(o.derived_bins[d]);
+        ++p->var.n;
+      }
+    }
     hipStream_t s = (hipStream_t)stream;
     FPW_HIP(hipGetDevice(&p->device), "hipGetDevice");
     FPW_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device), "CU count");
@@ -563,8 +596,8 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     // Large M leaves room for few waves per CU; their scalar-load waits then
     // stall the LDS atomics, so the DPP broadcast source is the default there.
     const int src = o.point_source ? o.point_source - 1 : (o.n_bins >= kDppMinBins ? 1 : 0);
-    fpw::Shape sh{src == 1 ? 1 : (o.freqs_per_lane ? o.freqs_per_lane : 1), o.waves_per_group ? o.waves_per_group : 1,
-                  o.chunk_freqs, src};
+    const int fl = (src == 1 || p->var.n > 1) ? 1 : (o.freqs_per_lane ? o.freqs_per_lane : 1);
+    fpw::Shape sh{fl, o.waves_per_group ? o.waves_per_group : 1, o.chunk_freqs, src};
     if (o.autotune && !o.freqs_per_lane && !o.waves_per_group && !o.chunk_freqs && !o.point_source) {
       st = autotune(p, s);
     } else {
@@ -712,6 +745,15 @@ fpw_status fpw_pass_timings(fpw_plan_t p, float ms[3]) {
   return FPW_OK;
 }
 
+fpw_status fpw_variant(fpw_plan_t p, int32_t v, int32_t* n_bins, int32_t* offset) {
+  g_err.clear();
+  if (!p || !n_bins || !offset) return fail(FPW_EINVAL, "NULL argument");
+  if (v < 0 || v >= p->var.n) return fail(FPW_EINVAL, "variant %d out of range [0, %d)", v, p->var.n);
+  *n_bins = p->var_bins[v];
+  *offset = p->var.o[v];
+  return FPW_OK;
+}
+
 fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   g_err.clear();
   if (!p || !info) return fail(FPW_EINVAL, "NULL argument");
@@ -730,6 +772,7 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   info->lds_bytes = (int32_t)p->lds_bytes;
   info->tuned = p->tuned ? 1 : 0;
   info->point_source = p->shape.point_source + 1;
+  info->n_variants = p->var.n;
   return FPW_OK;
 }
 

@@ -49,6 +49,16 @@ struct alignas(16) Item {
   int32_t curve, k0, k1, slot;
 };
 
+// Periodogram variants of one pass (multi-M reuse): variant v combines k[v]
+// fine bins per coarse bin, starting at fine bin o[v].  Variant 0 is always
+// the fine binning itself (k = 1, o = 0).
+constexpr int kMaxVariants = 8;
+struct Variants {
+  int32_t n;
+  int32_t k[kMaxVariants];
+  int32_t o[kMaxVariants];
+};
+
 struct BatchArgs {
   const Rec* rec;
   const int64_t* offsets;
@@ -59,10 +69,12 @@ struct BatchArgs {
   int32_t n_freq;
   int32_t n_bins;
   int32_t topk;           // 0 = no peak selection
-  float* S;               // [n_curves * n_freq] or null
-  float* cand_val;        // [n_slots * topk]
-  int32_t* cand_idx;      // [n_slots * topk]
-  float* edge;            // [n_slots * 4]: S at k0, k0+1, k1-2, k1-1 (-inf if absent)
+  int32_t n_curves;
+  Variants var;
+  float* S;               // [n_var * n_curves * n_freq] or null
+  float* cand_val;        // [(n_slots * n_var) * topk]
+  int32_t* cand_idx;      // [(n_slots * n_var) * topk]
+  float* edge;            // [(n_slots * n_var) * 4]: S at k0, k0+1, k1-2, k1-1 (-inf if absent)
   uint32_t* queue;        // [2]: next item, finished waves (self-resetting)
 };
 
@@ -75,7 +87,8 @@ struct MergeArgs {
   int32_t n_curves;
   int32_t n_freq;
   int32_t topk;
-  int32_t* out_idx;
+  int32_t n_var;
+  int32_t* out_idx;           // [n_var * n_curves * topk]
   float* out_val;
 };
 
@@ -125,7 +138,7 @@ struct Shape {
 // Launchers; each returns the hipError_t of its launch.
 hipError_t launch_prepare(const PrepArgs& a, hipStream_t s);
 hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int grid_groups,
-                          size_t lds_bytes, hipStream_t s);
+                          size_t lds_bytes, hipStream_t s);  // n_var > 1 needs one frequency per lane
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
 hipError_t launch_fp64(const Fp64Args& a, hipStream_t s);
@@ -134,7 +147,7 @@ hipError_t launch_bins(const BinsArgs& a, hipStream_t s);
 // LDS bytes the batched kernel needs per workgroup.
 size_t batched_lds_bytes(const Shape& shape, int n_bins);
 // Persistent workgroups per CU the batched kernel reaches for this shape.
-hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, size_t lds_bytes, int* out);
+hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, int n_var, size_t lds_bytes, int* out);
 // Top-k list length the kernels are instantiated for (8 or 16; 0 without peaks).
 int topk_capacity(int k);
 

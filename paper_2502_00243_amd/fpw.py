@@ -52,6 +52,8 @@ class Options(ctypes.Structure):
         ("chunk_freqs", ctypes.c_int32),
         ("tune_cache", ctypes.c_char_p),
         ("point_source", ctypes.c_int32),
+        ("derived_bins", ctypes.c_int32 * 4),
+        ("all_offsets", ctypes.c_int32),
         ("profile", ctypes.c_int32),
     ]
 
@@ -73,6 +75,7 @@ class PlanInfo(ctypes.Structure):
         ("lds_bytes", ctypes.c_int32),
         ("tuned", ctypes.c_int32),
         ("point_source", ctypes.c_int32),
+        ("n_variants", ctypes.c_int32),
     ]
 
 
@@ -118,6 +121,8 @@ def load(path: str = LIB_PATH):
     lib.fpw_debug_bins.restype = ctypes.c_int
     lib.fpw_pass_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
     lib.fpw_pass_timings.restype = ctypes.c_int
+    lib.fpw_variant.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.fpw_variant.restype = ctypes.c_int
     lib.fpw_get_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     lib.fpw_get_plan_info.restype = ctypes.c_int
     lib.fpw_plan_destroy.argtypes = [P]
@@ -143,7 +148,7 @@ def default_options() -> Options:
 
 def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="fp64", stat_scale="eq1", topk=0,
                  inv_alpha2=0.0, autotune=False, use_graph=True, freqs_per_lane=0, waves_per_group=0, chunk_freqs=0,
-                 tune_cache=None, profile=False, point_source=0) -> Options:
+                 tune_cache=None, profile=False, point_source=0, derived_bins=(), all_offsets=False) -> Options:
     o = default_options()
     o.n_bins = int(n_bins)
     o.center = CENTER[center] if isinstance(center, str) else int(center)
@@ -161,6 +166,11 @@ def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="
     o.tune_cache = tune_cache.encode() if tune_cache else None
     o.profile = int(bool(profile))
     o.point_source = {"auto": 0, "scalar": 1, "dpp": 2}[point_source] if isinstance(point_source, str) else int(point_source)
+    if len(derived_bins) > 4:
+        raise ValueError("at most 4 derived bin counts")
+    for i in range(4):
+        o.derived_bins[i] = int(derived_bins[i]) if i < len(derived_bins) else 0
+    o.all_offsets = int(bool(all_offsets))
     return o
 
 
@@ -197,6 +207,7 @@ class Plan:
                           _ptr(self._freqs, ctypes.c_double), ctypes.byref(self.options), _stream_handle(stream))
         _check(st)
         self._h = h
+        self.n_variants = self.info().n_variants
 
     @classmethod
     def from_batch(cls, batch, stream=None, **opts):
@@ -211,12 +222,15 @@ class Plan:
         if topk is None:
             topk = self.topk_k > 0
         S = S_out
+        nv = self.n_variants
+        lead = (nv,) if nv > 1 else ()
         if store_s and S is None:
-            S = torch.empty((self.n_curves, self.n_freq), dtype=torch.float32, device="cuda")
+            S = torch.empty(lead + (self.n_curves, self.n_freq), dtype=torch.float32, device="cuda")
         idx = val = None
         if topk:
-            idx = idx_out if idx_out is not None else torch.empty((self.n_curves, self.topk_k), dtype=torch.int32, device="cuda")
-            val = val_out if val_out is not None else torch.empty((self.n_curves, self.topk_k), dtype=torch.float32, device="cuda")
+            shp = lead + (self.n_curves, self.topk_k)
+            idx = idx_out if idx_out is not None else torch.empty(shp, dtype=torch.int32, device="cuda")
+            val = val_out if val_out is not None else torch.empty(shp, dtype=torch.float32, device="cuda")
         _check(load().fpw_eval_batch(self._h, ctypes.c_void_p(S.data_ptr() if S is not None else 0),
                                      ctypes.c_void_p(idx.data_ptr() if idx is not None else 0),
                                      ctypes.c_void_p(val.data_ptr() if val is not None else 0), _stream_handle(stream)))
@@ -261,6 +275,12 @@ class Plan:
         ms = (ctypes.c_float * 3)()
         _check(load().fpw_pass_timings(self._h, ms))
         return float(ms[0]), float(ms[1]), float(ms[2])
+
+    def variant(self, v):
+        """(bin count, offset) of periodogram variant v."""
+        m, o = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().fpw_variant(self._h, int(v), ctypes.byref(m), ctypes.byref(o)))
+        return m.value, o.value
 
     def info(self) -> PlanInfo:
         inf = PlanInfo()

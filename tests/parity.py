@@ -101,3 +101,24 @@ def assert_topk_near_oracle(S_ref, idx, val, k, rel=2e-5):
             continue
         # a different index must carry a value tied with the oracle's choice
         assert abs(S_ref[gi[r]] - ov[r]) <= rel * abs(ov[r]) + 1e-6 * np.max(np.abs(S_ref)), (r, gi, oi, gv, ov)
+
+
+def reference_for_variant(t, y, dy, freqs, n_bins_max, n_bins, offset, opt, gpu_fine_bins):
+    """Oracle S of an (M, offset) variant combined from M_max fine bins; near-edge fine bins follow the GPU."""
+    tau, w, x = oracle.prepare_curve(t, y, dy, opt)
+    freqs = np.asarray(freqs, dtype=np.float64)
+    ob = oracle.phase_bins(tau[None, :], freqs[:, None], n_bins_max)
+    near = oracle.edge_distance(tau[None, :], freqs[:, None], n_bins_max) < EPS_BIN
+    gb = np.asarray(gpu_fine_bins, dtype=np.int64)
+    assert not ((gb != ob) & ~near).any(), "off-edge fine bins differ"
+    fine = np.where(near, gb, ob)
+    S = np.empty(len(freqs))
+    Sabs = np.empty(len(freqs))
+    awx = np.abs(w * x)
+    for r in range(len(freqs)):
+        cb = oracle.combined_bins(fine[r], n_bins_max, n_bins, offset)
+        W, Y, _ = oracle.bin_sums(cb, w, x, n_bins)
+        A = np.bincount(cb, weights=awx, minlength=n_bins)
+        S[r] = oracle.statistic(W, Y, opt.inv_alpha2, opt.stat_scale)
+        Sabs[r] = oracle.statistic(W, A, opt.inv_alpha2, opt.stat_scale)
+    return S, Sabs

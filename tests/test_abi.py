@@ -72,6 +72,11 @@ CASES = [
     ("fp32 fold range", dict(t=[0.1, 2.0, 7.5e6, 1.0, 3.0], opts=dict(phase="df32")), fpw.EUNSUPPORTED),
     ("two freqs per lane in df32", dict(opts=dict(phase="df32", freqs_per_lane=2)), fpw.EUNSUPPORTED),
     ("bad waves per group", dict(opts=dict(waves_per_group=3)), fpw.EINVAL),
+    ("derived M does not divide", dict(n_bins=12, opts=dict(derived_bins=(5,))), fpw.EINVAL),
+    ("derived M not smaller", dict(n_bins=12, opts=dict(derived_bins=(12,))), fpw.EINVAL),
+    ("derived M twice", dict(n_bins=12, opts=dict(derived_bins=(6, 6))), fpw.EINVAL),
+    ("too many variants", dict(n_bins=40, opts=dict(derived_bins=(5, 10), all_offsets=True)), fpw.EUNSUPPORTED),
+    ("two freqs per lane with variants", dict(n_bins=12, opts=dict(derived_bins=(6,), freqs_per_lane=2)), fpw.EUNSUPPORTED),
 ]
 
 

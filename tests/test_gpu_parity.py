@@ -269,3 +269,37 @@ def test_fp32_naive_phase_flips_bins_at_large_folds():
     ob = oracle.curve_bins(b.curve(0)[0], b.freqs[nf - 64:], 50)
     assert (gb != ob).mean() > 0.05
     plan.close()
+
+
+@pytest.mark.parametrize("M_max,derived,all_offsets,src", [(40, (20, 10), True, "auto"), (60, (20, 12, 4), False, "auto"),
+                                                           (20, (10, 5), False, "scalar"), (12, (6,), True, "dpp")])
+def test_multi_m_variants(M_max, derived, all_offsets, src):
+    """Sec. 3.4: every (M, offset) variant combined from the M_max sums of one pass."""
+    _say(f"multi-M {M_max} {derived} all_offsets={all_offsets} source={src}")
+    freqs = np.linspace(0.05, 30.0, 477)
+    b = synth.random_batch(50 + M_max, 10, 1, 300, freqs, M_max)
+    plan = fpw.Plan.from_batch(b, topk=4, derived_bins=derived, all_offsets=all_offsets, chunk_freqs=128,
+                               point_source=src)
+    nv = plan.n_variants
+    expect = 1 + sum((M_max // m) if all_offsets else 1 for m in derived)
+    assert nv == expect
+    S, idx, val = plan.eval()
+    torch.cuda.synchronize()
+    S, idx, val = S.cpu().numpy(), idx.cpu().numpy(), val.cpu().numpy()
+    opt = parity.oracle_options()
+    for v in range(nv):
+        M, o = plan.variant(v)
+        parity.assert_topk_matches_rule(S[v], idx[v], val[v], 4)
+        for c in range(0, b.n_curves, 2):
+            t, y, dy = b.curve(c)
+            gb = plan.debug_bins(c, 0, len(freqs)).cpu().numpy()
+            S_ref, S_abs = parity.reference_for_variant(t, y, dy, freqs, M_max, M, o, opt, gb)
+            parity.assert_s_close(S[v, c], S_ref, S_abs, what=f"variant {v} (M={M}, o={o}) curve {c}")
+    # variant 0 is bit-identical to a plan without derived bin counts
+    p0 = fpw.Plan.from_batch(b, topk=4, chunk_freqs=128, point_source=src)
+    S0, i0, v0 = p0.eval()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(S0.cpu().numpy(), S[0])
+    np.testing.assert_array_equal(i0.cpu().numpy(), idx[0])
+    plan.close()
+    p0.close()

@@ -422,3 +422,52 @@ def test_validation_rejects_bad_inputs():
             oracle.validate(*args)
     with pytest.raises(ValueError):
         oracle.validate([0, 2], t, y, dy, f, 4, OracleOptions(inv_alpha2=-1.0))
+
+
+# ---------------------------------------------------------------- multiple M from M_max (Sec. 3.4)
+
+
+@pytest.mark.parametrize("M_max,M", [(40, 20), (40, 10), (60, 12), (20, 5), (12, 12)])
+def test_combined_bins_are_shifted_coarse_bins(M_max, M):
+    """Combining k fine bins from offset o is binning the phase shifted by o / M_max into M bins:
+    floor(M frac(phi - o / M_max)), checked in exact rationals off-edge.  Offset 0 is the plain M-bin fold."""
+    rng = np.random.default_rng(M_max + M)
+    tau = rng.uniform(0, 2000, 300)
+    f = rng.uniform(0.05, 50, 300)
+    fine = oracle.phase_bins(tau, f, M_max)
+    k = M_max // M
+    for o in range(k):
+        cb = oracle.combined_bins(fine, M_max, M, o)
+        for i in range(len(tau)):
+            p = Fraction(float(tau[i])) * Fraction(float(f[i]))
+            phi = p - math.floor(p) - Fraction(o, M_max)
+            phi -= math.floor(phi)
+            u = phi * M
+            dist = float(min(u - math.floor(u), math.floor(u) + 1 - u))
+            if dist > 1e-6:
+                assert cb[i] == math.floor(u), (o, i)
+        if o == 0:
+            off = oracle.edge_distance(tau, f, M) > 1e-6
+            assert np.array_equal(cb[off], oracle.phase_bins(tau, f, M)[off])
+
+
+def test_variant_statistic_on_noise_is_chi2():
+    """Any (M, offset) variant of pure noise is chi-square with M-1 dof."""
+    rng = np.random.default_rng(91)
+    n, f = 300, 2.2
+    t = np.sort(rng.uniform(0, 900, n))
+    dy = rng.uniform(0.01, 0.05, n)
+    for M, o in ((10, 0), (10, 3), (20, 1)):
+        S = np.array([oracle.variant_periodogram(t, dy * rng.standard_normal(n), dy, [f], 40, M, o)[0] for _ in range(3000)])
+        assert abs(S.mean() - (M - 1)) < 5 * math.sqrt(2 * (M - 1) / len(S))
+
+
+def test_variant_offset_zero_equals_direct_fold_off_edge():
+    rng = np.random.default_rng(92)
+    t, y, dy = _noise_curve(rng, 200)
+    freqs = np.linspace(0.05, 10, 300)
+    direct = oracle.curve_periodogram(t, y, dy, freqs, 10)
+    comb = oracle.variant_periodogram(t, y, dy, freqs, 40, 10, 0)
+    tau = oracle.time_offsets(t, OracleOptions())
+    clean = np.array([np.all(oracle.edge_distance(tau, f, 40) > 1e-6) for f in freqs])
+    np.testing.assert_allclose(comb[clean], direct[clean], rtol=1e-12)
