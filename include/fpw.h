@@ -197,6 +197,23 @@ fpw_status fpw_debug_bins(fpw_plan_t plan, int32_t phase, int64_t curve, int64_t
  */
 fpw_status fpw_pass_timings(fpw_plan_t plan, float ms[3]);
 
+/*
+ * Phase entropy of each curve's observation times at given trial frequencies
+ * (App. C): H = -sum_m (N_m/N) log(N_m/N) over the plan's n_bins phase bins
+ * (N_m observations of the curve in bin m, natural log), with the expectation
+ * E and variance V of H for equiprobable bins (Hutcheson, as quoted in
+ * App. C: E = log M - (M-1)/(2N) - (M^2-1)/(12N^2), V = (M-1)/(2N^2) +
+ * (M^2-1)/(6N^3)).  A peak whose H lies far below E comes from regularities
+ * of the sampling rather than from the source.  Bins follow the plan's phase
+ * mode, as in fpw_eval_batch.
+ *   freq_idx_dev  DEVICE int32 [n_curves * k]: frequency index for each (curve, slot),
+ *                 e.g. fpw_eval_batch's top-k output; slots with index < 0 are skipped
+ *   H_dev, E_dev, V_dev  DEVICE float32 [n_curves * k]; NaN in skipped slots
+ *   k             1 <= k <= n_freq
+ */
+fpw_status fpw_phase_entropy(fpw_plan_t plan, const int32_t* freq_idx_dev, int32_t k, float* H_dev,
+                             float* E_dev, float* V_dev, void* stream);
+
 /* Bin count and offset of periodogram variant v (0 <= v < n_variants). */
 fpw_status fpw_variant(fpw_plan_t plan, int32_t v, int32_t* n_bins, int32_t* offset);
 

@@ -59,6 +59,9 @@ __all__ = [
     "batch_topk",
     "combined_bins",
     "variant_periodogram",
+    "phase_entropy",
+    "entropy_expectation",
+    "entropy_variance",
 ]
 
 # Bins of a point closer than this many bin widths to a bin edge may
@@ -313,3 +316,28 @@ def variant_periodogram(t, y, dy, freqs, n_bins_max, n_bins, offset, opt: Oracle
         W, Y, _ = bin_sums(b, w, x, n_bins)
         out[r] = statistic(W, Y, opt.inv_alpha2, opt.stat_scale)
     return out
+
+
+# ---------------------------------------------------------------- phase entropy (App. C)
+
+
+def phase_entropy(tau: np.ndarray, f: float, n_bins: int) -> float:
+    """H = -sum_m (N_m / N) log(N_m / N) over occupied bins (App. C), natural log.
+
+    N_m counts the observations in phase bin m at trial frequency f.
+    """
+    counts = np.bincount(phase_bins(np.asarray(tau, dtype=np.float64), f, n_bins), minlength=n_bins)
+    p = counts[counts > 0] / float(len(tau))
+    return float(-np.sum(p * np.log(p)))
+
+
+def entropy_expectation(n_bins: int, n_obs: int) -> float:
+    """App. C (Hutcheson): E(H) for equiprobable bins, to order 1/N^2."""
+    M, N = float(n_bins), float(n_obs)
+    return math.log(M) - (M - 1.0) / (2.0 * N) - (M - 1.0) * (M + 1.0) / (12.0 * N * N)
+
+
+def entropy_variance(n_bins: int, n_obs: int) -> float:
+    """App. C (Hutcheson): Var(H) for equiprobable bins, to order 1/N^3."""
+    M, N = float(n_bins), float(n_obs)
+    return (M - 1.0) / (2.0 * N * N) + (M * M - 1.0) / (6.0 * N * N * N)

@@ -3,6 +3,9 @@
 // FP64 comparator and the bin parity hook.
 #include "fpw_common.h"
 
+// histogram slots per wave of the entropy kernel: FPW_MAX_BINS + 1
+#define FPW_ENTROPY_MAX_SLOTS 256
+
 namespace fpw {
 namespace {
 
@@ -200,6 +203,58 @@ __global__ __launch_bounds__(256) void bins_kernel(BinsArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- phase entropy (App. C)
+// One wave per (curve, slot): the curve's observations are binned at the
+// slot's frequency with the plan's fold, counted with LDS atomics in a
+// per-wave histogram, and H = -sum p log p is reduced across the wave in FP64.
+constexpr int kEntropyWaves = 4;
+
+template <int PH>
+__global__ __launch_bounds__(kEntropyWaves * 64) void entropy_kernel(EntropyArgs a) {
+  __shared__ uint32_t cnt[kEntropyWaves][FPW_ENTROPY_MAX_SLOTS];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int gw = blockIdx.x * kEntropyWaves + wv;
+  if (gw >= a.n_curves * a.k) return;  // wave-uniform
+  const int c = gw / a.k;
+  const int idx = a.freq_idx[gw];
+  if (idx < 0 || idx >= a.n_freq) {
+    if (lane == 0) {
+      a.H[gw] = NAN;
+      a.E[gw] = NAN;
+      a.V[gw] = NAN;
+    }
+    return;
+  }
+  const int M = a.n_bins;
+  for (int m = lane; m <= M; m += kWave) cnt[wv][m] = 0;
+  const int64_t p0 = a.offsets[c];
+  const int n = (int)(a.offsets[c + 1] - p0);
+  Folder<PH> fo;
+  fo.init(a.freqs[idx], M);
+  for (int i = lane; i < n; i += kWave) {
+    int b = fo.bin(encode_tau(a.tau64[p0 + i], PH));
+    if (b >= M) b = 0;  // the fused fold files phases just below 1 as M
+    atomicAdd(&cnt[wv][b], 1u);
+  }
+  double h = 0.0;
+  const double inv_n = 1.0 / (double)n;
+  for (int m = lane; m < M; m += kWave) {
+    const uint32_t nm = cnt[wv][m];
+    if (nm > 0) {
+      const double p = (double)nm * inv_n;
+      h -= p * log(p);
+    }
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) h += __shfl_xor(h, off);
+  if (lane == 0) {
+    const double Md = M, Nd = n;
+    a.H[gw] = (float)h;
+    a.E[gw] = (float)(log(Md) - (Md - 1.0) / (2.0 * Nd) - (Md - 1.0) * (Md + 1.0) / (12.0 * Nd * Nd));
+    a.V[gw] = (float)((Md - 1.0) / (2.0 * Nd * Nd) + (Md * Md - 1.0) / (6.0 * Nd * Nd * Nd));
+  }
+}
+
 }  // namespace
 
 hipError_t launch_prepare(const PrepArgs& a, hipStream_t s) {
@@ -245,6 +300,22 @@ hipError_t launch_bins(const BinsArgs& a, hipStream_t s) {
     case PH_LISTING: hipLaunchKernelGGL(bins_kernel<PH_LISTING>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
     case PH_DF32: hipLaunchKernelGGL(bins_kernel<PH_DF32>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL(bins_kernel<PH_FP32>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fpw
+
+namespace fpw {
+
+hipError_t launch_entropy(const EntropyArgs& a, hipStream_t s) {
+  const int waves = a.n_curves * a.k;
+  const int blocks = (waves + kEntropyWaves - 1) / kEntropyWaves;
+  switch (a.phase) {
+    case PH_FP64: hipLaunchKernelGGL(entropy_kernel<PH_FP64>, dim3(blocks), dim3(kEntropyWaves * 64), 0, s, a); break;
+    case PH_LISTING: hipLaunchKernelGGL(entropy_kernel<PH_LISTING>, dim3(blocks), dim3(kEntropyWaves * 64), 0, s, a); break;
+    case PH_DF32: hipLaunchKernelGGL(entropy_kernel<PH_DF32>, dim3(blocks), dim3(kEntropyWaves * 64), 0, s, a); break;
+    default: hipLaunchKernelGGL(entropy_kernel<PH_FP32>, dim3(blocks), dim3(kEntropyWaves * 64), 0, s, a); break;
   }
   return hipGetLastError();
 }

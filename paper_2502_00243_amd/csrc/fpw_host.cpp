@@ -745,6 +745,30 @@ fpw_status fpw_pass_timings(fpw_plan_t p, float ms[3]) {
   return FPW_OK;
 }
 
+fpw_status fpw_phase_entropy(fpw_plan_t p, const int32_t* freq_idx_dev, int32_t k, float* H_dev, float* E_dev,
+                             float* V_dev, void* stream) {
+  g_err.clear();
+  if (!p) return fail(FPW_EINVAL, "plan is NULL");
+  if (!freq_idx_dev || !H_dev || !E_dev || !V_dev) return fail(FPW_EINVAL, "null device pointer");
+  if (k < 1 || k > p->n_freq) return fail(FPW_EINVAL, "k must be in [1, n_freq]");
+  if ((int64_t)p->n_curves * k > INT32_MAX) return fail(FPW_EUNSUPPORTED, "n_curves * k too large");
+  fpw::EntropyArgs a{};
+  a.tau64 = p->tau64.as<double>();
+  a.offsets = p->offsets.as<int64_t>();
+  a.freqs = p->freqs.as<double>();
+  a.freq_idx = freq_idx_dev;
+  a.n_curves = (int32_t)p->n_curves;
+  a.k = k;
+  a.n_freq = (int32_t)p->n_freq;
+  a.n_bins = p->opt.n_bins;
+  a.phase = p->opt.phase;
+  a.H = H_dev;
+  a.E = E_dev;
+  a.V = V_dev;
+  FPW_HIP(fpw::launch_entropy(a, (hipStream_t)stream), "entropy kernel");
+  return FPW_OK;
+}
+
 fpw_status fpw_variant(fpw_plan_t p, int32_t v, int32_t* n_bins, int32_t* offset) {
   g_err.clear();
   if (!p || !n_bins || !offset) return fail(FPW_EINVAL, "NULL argument");

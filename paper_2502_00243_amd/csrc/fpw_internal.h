@@ -127,6 +127,17 @@ struct BinsArgs {
   int32_t* out;
 };
 
+struct EntropyArgs {
+  const double* tau64;
+  const int64_t* offsets;
+  const double* freqs;
+  const int32_t* freq_idx;  // [n_curves * k]
+  int32_t n_curves, k, n_freq, n_bins, phase;
+  float* H;
+  float* E;
+  float* V;
+};
+
 // Launch shapes of the batched kernel.
 struct Shape {
   int freqs_per_lane;   // 1 or 2
@@ -143,6 +154,7 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
 hipError_t launch_fp64(const Fp64Args& a, hipStream_t s);
 hipError_t launch_bins(const BinsArgs& a, hipStream_t s);
+hipError_t launch_entropy(const EntropyArgs& a, hipStream_t s);
 
 // LDS bytes the batched kernel needs per workgroup.
 size_t batched_lds_bytes(const Shape& shape, int n_bins);

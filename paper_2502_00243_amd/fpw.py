@@ -121,6 +121,8 @@ def load(path: str = LIB_PATH):
     lib.fpw_debug_bins.restype = ctypes.c_int
     lib.fpw_pass_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
     lib.fpw_pass_timings.restype = ctypes.c_int
+    lib.fpw_phase_entropy.argtypes = [P, P, i32, P, P, P, P]
+    lib.fpw_phase_entropy.restype = ctypes.c_int
     lib.fpw_variant.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.fpw_variant.restype = ctypes.c_int
     lib.fpw_get_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
@@ -275,6 +277,21 @@ class Plan:
         ms = (ctypes.c_float * 3)()
         _check(load().fpw_pass_timings(self._h, ms))
         return float(ms[0]), float(ms[1]), float(ms[2])
+
+    def phase_entropy(self, freq_idx, stream=None):
+        """(H, E, V) of the phase occupancy at freq_idx (device int32 [n_curves, k]), App. C."""
+        import torch
+
+        assert freq_idx.dtype == torch.int32 and freq_idx.is_cuda and freq_idx.is_contiguous()
+        assert freq_idx.dim() == 2 and freq_idx.shape[0] == self.n_curves
+        k = int(freq_idx.shape[1])
+        H = torch.empty_like(freq_idx, dtype=torch.float32)
+        E = torch.empty_like(H)
+        V = torch.empty_like(H)
+        _check(load().fpw_phase_entropy(self._h, ctypes.c_void_p(freq_idx.data_ptr()), k, ctypes.c_void_p(H.data_ptr()),
+                                        ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                                        _stream_handle(stream)))
+        return H, E, V
 
     def variant(self, v):
         """(bin count, offset) of periodogram variant v."""

@@ -303,3 +303,38 @@ def test_multi_m_variants(M_max, derived, all_offsets, src):
     np.testing.assert_array_equal(i0.cpu().numpy(), idx[0])
     plan.close()
     p0.close()
+
+
+@pytest.mark.parametrize("phase", ["fp64", "fp64_listing"])
+def test_phase_entropy_at_peaks(phase):
+    """App. C: phase entropy of the observation times at each curve's top peaks, with its Hutcheson moments."""
+    _say(f"phase entropy {phase}")
+    b = synth.ztf_batch(40)
+    plan = fpw.Plan.from_batch(b, topk=5, phase=phase)
+    _, idx, _ = plan.eval(store_s=False)
+    idx[3, 2] = -1  # a skipped slot
+    H, E, V = plan.phase_entropy(idx)
+    torch.cuda.synchronize()
+    idx, H, E, V = idx.cpu().numpy(), H.cpu().numpy(), E.cpu().numpy(), V.cpu().numpy()
+    assert np.isnan(H[3, 2]) and np.isnan(E[3, 2]) and np.isnan(V[3, 2])
+    M = b.n_bins
+    for c in range(b.n_curves):
+        t, _, _ = b.curve(c)
+        n = len(t)
+        for r in range(5):
+            k = int(idx[c, r])
+            if k < 0:
+                continue
+            gb = plan.debug_bins(c, k, k + 1).cpu().numpy()[0]
+            ob = oracle.phase_bins(t, b.freqs[k], M)
+            near = oracle.edge_distance(t, b.freqs[k], M) < oracle.EPS_BIN
+            assert not ((gb != ob) & ~near).any()
+            cnt = np.bincount(gb, minlength=M)
+            p = cnt[cnt > 0] / n
+            H_ref = float(-np.sum(p * np.log(p)))
+            if not near.any():
+                assert H_ref == pytest.approx(oracle.phase_entropy(t, b.freqs[k], M), abs=1e-12)
+            assert abs(H[c, r] - H_ref) <= 2e-6 * max(1.0, H_ref)
+            assert E[c, r] == pytest.approx(oracle.entropy_expectation(M, n), rel=1e-6)
+            assert V[c, r] == pytest.approx(oracle.entropy_variance(M, n), rel=1e-6)
+    plan.close()

@@ -471,3 +471,36 @@ def test_variant_offset_zero_equals_direct_fold_off_edge():
     tau = oracle.time_offsets(t, OracleOptions())
     clean = np.array([np.all(oracle.edge_distance(tau, f, 40) > 1e-6) for f in freqs])
     np.testing.assert_allclose(comb[clean], direct[clean], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- phase entropy (App. C)
+
+
+def test_phase_entropy_extremes():
+    """Uniform occupancy gives log M (App. C, with N_m/N_tot = 1/M); one occupied bin gives 0."""
+    for M in (2, 5, 10, 20):
+        n = 7 * M
+        tau = (np.arange(n) + 0.5) / n  # at f = 1 exactly 7 points per bin
+        assert abs(oracle.phase_entropy(tau, 1.0, M) - math.log(M)) < 1e-12
+        assert oracle.phase_entropy(np.full(n, 0.3), 1.0, M) == 0.0
+    # two equal halves: log 2
+    tau = np.concatenate([np.full(5, 0.05), np.full(5, 0.55)])
+    assert abs(oracle.phase_entropy(tau, 1.0, 10) - math.log(2)) < 1e-12
+
+
+@pytest.mark.parametrize("M,N", [(10, 200), (20, 400), (5, 100)])
+def test_hutcheson_moments_match_multinomial_sampling(M, N):
+    """E(H) and Var(H) of App. C against a direct simulation of N equiprobable draws into M bins."""
+    rng = np.random.default_rng(M * 1000 + N)
+    reps = 40000
+    counts = rng.multinomial(N, np.full(M, 1.0 / M), size=reps)
+    p = counts / N
+    with np.errstate(divide="ignore", invalid="ignore"):
+        H = -np.sum(np.where(p > 0, p * np.log(p), 0.0), axis=1)
+    E = oracle.entropy_expectation(M, N)
+    V = oracle.entropy_variance(M, N)
+    se_mean = math.sqrt(V / reps)
+    assert abs(H.mean() - E) < 5 * se_mean + 2 * (M / N) ** 3
+    assert abs(H.var() - V) < 0.05 * V
+    # the leading correction matters: log M alone is off by (M-1)/(2N)
+    assert abs(H.mean() - math.log(M)) > 10 * se_mean
