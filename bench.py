@@ -29,6 +29,7 @@ N_CU = 256
 CLOCK_HZ = 2.4e9
 VALU_PEAK = N_CU * 64 * CLOCK_HZ  # lane-ops/s: 64 lanes per CU per clock (FP64 FMA = 78.6 TFLOP/s / 2)
 LDS_PEAK = N_CU * 128 * CLOCK_HZ  # bytes/s: 128 B per CU per clock
+INT8_PEAK = 5.0e15  # int8 ops/s: dense matrix-core peak of MI355X
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batched_ztf1000.json")
 # sources of the dominant (batched) kernel: its traffic figures are valid only for this exact code
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2502_00243_amd", "csrc", f) for f in ("fpw_batched.hip", "fpw_common.h")]
@@ -108,11 +109,13 @@ def main():
     ap.add_argument("--no-latency", action="store_true", help="skip the single-curve latency run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="ztf1000", choices=["ztf1000", "uneven", "stress", "precision", "sweep"],
+    ap.add_argument("--workload", default="ztf1000",
+                    choices=["ztf1000", "uneven", "stress", "precision", "sweep", "shared"],
                     help="ztf1000: the headline line (default); uneven: 1e5 uneven curves, 2e5 freqs, "
                          "M in {10,20,40}, top-5; stress: 2e4 x 3000-point curves, 1e6 freqs, M=50, top-5; "
                          "precision: phase-arithmetic study on the ztf1000 data; "
-                         "sweep: launch shapes x M on the ztf1000 data")
+                         "sweep: launch shapes x M on the ztf1000 data; "
+                         "shared: 1000 curves at 500 common epochs, 1e5 freqs, M=20, matrix-core vs general kernel")
     ap.add_argument("--curves", type=int, default=0, help="curve count override for uneven/stress")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -127,6 +130,8 @@ def main():
         return bench_precision(args)
     if args.workload == "sweep":
         return bench_sweep(args)
+    if args.workload == "shared":
+        return bench_shared(args)
 
     import numpy as np
 
@@ -307,6 +312,55 @@ def _fp64_rate(plan, evals):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     return {"value": evals / (ms * 1e-3) / 1e9, "unit": "G evals/s", "ms": ms}
+
+
+def bench_shared(args):
+    """One field: 1000 curves observed at the same 500 epochs, 1e5 freqs, M = 20, periodogram + top-5.
+
+    The matrix-core kernel against the general kernel on the same data.  The
+    matrix kernel's roofline counts the int8 operations of the contraction
+    it performs: rows (curve, quantity, digit) = 8 per curve, columns
+    (frequency, bin) = M per frequency, depth = points, i.e. 16 M int8
+    operations per evaluation, against the dense int8 peak.
+    """
+    import numpy as np
+    import torch
+
+    from paper_2502_00243_amd import fpw, synth
+
+    torch.cuda.set_device(0)
+    batch = synth.shared_batch(args.curves or 1000, 500)
+    t, y, dy = batch.as_shared()
+    evals = batch.evals()
+    M = batch.n_bins
+    res = {}
+    for kern in ("matrix", "general"):
+        plan = fpw.Plan.shared(t, y, dy, batch.freqs, M, topk=5, shared_kernel=kern, profile=True)
+        S = torch.empty((batch.n_curves, len(batch.freqs)), dtype=torch.float32, device="cuda")
+        idx = torch.empty((batch.n_curves, 5), dtype=torch.int32, device="cuda")
+        val = torch.empty((batch.n_curves, 5), dtype=torch.float32, device="cuda")
+        wall, kms = _time_passes(plan, args.steps, args.warmup, S_out=S, idx_out=idx, val_out=val)
+        info = plan.info()
+        kernel_ms = float(np.mean(kms[:, 1]))
+        r = {"ms_per_pass": wall * 1e3, "G_evals_per_s": evals / wall / 1e9, "kernel_ms": kernel_ms,
+             "prepare_ms": float(np.mean(kms[:, 0])), "topk_ms": float(np.mean(kms[:, 2])),
+             "grid_groups": info.grid_groups, "lds_bytes": info.lds_bytes}
+        if kern == "matrix":
+            ops = 16.0 * M * evals
+            r["roofline"] = {"bound": "mfma", "achieved": ops / (kernel_ms * 1e-3) / 1e12, "peak": INT8_PEAK / 1e12,
+                             "unit": "T int8 ops/s", "frac": ops / (kernel_ms * 1e-3) / INT8_PEAK,
+                             "ops_per_eval": 16.0 * M, "kernel_ms": kernel_ms}
+        else:
+            r["roofline"] = _roofline(evals, batch.n_curves, len(batch.freqs), M, batch.n_points, kernel_ms)
+        log(f"shared {kern}: {wall * 1e3:.3f} ms/pass, kernel {kernel_ms:.3f} ms, {evals / wall / 1e9:.0f} G evals/s")
+        res[kern] = r
+        plan.close()
+    print(json.dumps({"workload": f"shared: {batch.n_curves} curves x 500 common epochs (one field, ZTF-like cadence "
+                                  f"over 1500 d), {len(batch.freqs)} freqs 0.05-50 /d, M={M}, periodogram + top-5",
+                      "evals": evals, "value": res["matrix"]["G_evals_per_s"], "unit": "G evals/s",
+                      "matrix": res["matrix"], "general": res["general"],
+                      "speedup_matrix_vs_general": res["general"]["ms_per_pass"] / res["matrix"]["ms_per_pass"]}),
+          flush=True)
 
 
 def bench_uneven(args):

@@ -116,7 +116,16 @@ typedef struct {
   int32_t profile;        /* 1: record HIP events around each kernel of fpw_eval_batch
                              (read them with fpw_pass_timings); the pass is then
                              launched kernel by kernel instead of as a graph */
+  int32_t shared_kernel;  /* plans made by fpw_plan_shared: FPW_SHARED_* (ignored otherwise) */
 } fpw_options;
+
+/* Kernel of a shared-timestamp plan (fpw_plan_shared). */
+enum {
+  FPW_SHARED_AUTO = 0,    /* the matrix-core kernel where it applies (n_bins <= 64, phase FP64
+                             or FP64_LISTING, no derived bin counts), else the general one */
+  FPW_SHARED_GENERAL = 1, /* the general batched kernel, as for fpw_plan */
+  FPW_SHARED_MATRIX = 2   /* the matrix-core kernel; FPW_EUNSUPPORTED where it does not apply */
+};
 
 /* Fills *opt with the defaults listed above. */
 void fpw_options_default(fpw_options* opt);
@@ -140,6 +149,31 @@ void fpw_options_default(fpw_options* opt);
 fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, const double* t,
                     const double* y, const double* dy, int64_t n_freq, const double* freqs,
                     const fpw_options* opt, void* stream);
+
+/*
+ * Creates a plan for curves that share their observation times (Sec. 4: the
+ * batch function for light curves with common timestamps; App. C: every
+ * source of one image field).  The phase bins of a time at a frequency are
+ * then the same for all curves, so one fold serves the whole batch and the
+ * per-bin sums of all curves at a frequency form one matrix product over the
+ * observations: sums[curve][bin] = sum_p value[curve][p] * [bin(f, p) == bin].
+ * The default kernel evaluates that product exactly on the int8 matrix cores
+ * (fixed-point values split into base-256 digits, int32 accumulation); see
+ * opt.shared_kernel.  Results have the same definition, layout and tolerance
+ * as for fpw_plan on the equivalent CSR batch (every curve with the same t),
+ * and every other entry point (fpw_eval_fp64, fpw_debug_bins,
+ * fpw_phase_entropy, fpw_topk) accepts the plan as such a batch.
+ *   n_curves   >= 1
+ *   n_points   >= 1 (<= FPW_MAX_CURVE_POINTS): observations per curve
+ *   t          float64 [n_points], HOST: the common times
+ *   y, dy      float64 [n_curves * n_points], HOST, curve-major: fluxes and errors
+ *   n_freq, freqs, opt, stream: as for fpw_plan
+ * With the matrix-core kernel the plan also owns a float32 periodogram
+ * buffer [n_curves * n_freq] used when fpw_eval_batch gets S_dev = NULL.
+ */
+fpw_status fpw_plan_shared(fpw_plan_t* out, int64_t n_curves, int64_t n_points, const double* t, const double* y,
+                           const double* dy, int64_t n_freq, const double* freqs, const fpw_options* opt,
+                           void* stream);
 
 /*
  * One pass of the periodogram over the plan's batch (Eq. 1 for every curve and
@@ -229,6 +263,7 @@ typedef struct {
   int32_t tuned;          /* 1 if the launch shape came from the autotuner or its cache */
   int32_t point_source;   /* 1 scalar loads, 2 vector loads + DPP broadcast */
   int32_t n_variants;     /* periodograms per curve and pass */
+  int32_t kernel;         /* 0 general batched kernel, 1 shared-timestamp matrix-core kernel */
 } fpw_plan_info;
 
 fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);

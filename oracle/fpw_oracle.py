@@ -52,6 +52,7 @@ __all__ = [
     "statistic",
     "prepare_curve",
     "curve_periodogram",
+    "shared_periodogram",
     "curve_bins",
     "periodogram",
     "peak_mask",
@@ -252,6 +253,29 @@ def periodogram(offsets, t, y, dy, freqs, n_bins, opt: OracleOptions | None = No
     for r, c in enumerate(curves):
         a, b = int(offsets[c]), int(offsets[c + 1])
         out[r] = curve_periodogram(t[a:b], y[a:b], dy[a:b], freqs, n_bins, opt)
+    return out
+
+
+def shared_periodogram(t, y, dy, freqs, n_bins, opt: OracleOptions | None = None) -> np.ndarray:
+    """S[c, f] for curves observed at common times t (y, dy: [n_curves, n_points]), FP64.
+
+    Sec. 4 (the batch function for curves sharing timestamps): the bins of
+    the common times are computed once per frequency and reused for every
+    curve; each curve keeps its own weights and centring.
+    """
+    opt = opt or OracleOptions()
+    y = np.asarray(y, dtype=np.float64)
+    dy = np.asarray(dy, dtype=np.float64)
+    n_curves = y.shape[0]
+    prepared = [prepare_curve(t, y[c], dy[c], opt) for c in range(n_curves)]
+    tau = prepared[0][0]  # the same offsets for every curve
+    freqs = np.asarray(freqs, dtype=np.float64)
+    out = np.empty((n_curves, len(freqs)))
+    for r, f in enumerate(freqs):
+        bins = phase_bins(tau, f, n_bins)
+        for c, (_, w, x) in enumerate(prepared):
+            W, Y, _ = bin_sums(bins, w, x, n_bins)
+            out[c, r] = statistic(W, Y, opt.inv_alpha2, opt.stat_scale)
     return out
 
 

@@ -154,6 +154,73 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- prepare, shared timestamps
+// One workgroup per curve of a shared-timestamp batch: inverse variances and
+// centring as above, fixed-point scales with 30-bit ranges (every bin sum of
+// either quantity stays below 2^30 in magnitude), then the four signed
+// base-256 digits of each quantity scattered into the curve's rows of the
+// int8 tiles.
+__device__ __forceinline__ void put_digits(int8_t* tile_row, int32_t v, int q) {
+  // v = d0 + 256 d1 + 65536 d2 + 2^24 d3, each d in [-128, 127] for |v| <= 2^30
+  int32_t r = v;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int32_t d = (int32_t)(int8_t)(r & 0xff);
+    tile_row[(4 * q + i) * 16] = (int8_t)d;
+    r = (r - d) >> 8;
+  }
+  tile_row[(4 * q + 3) * 16] = (int8_t)r;
+}
+
+__global__ __launch_bounds__(kPrepThreads) void prepare_shared_kernel(SharedPrepArgs a) {
+  __shared__ double red[kPrepThreads];
+  const int t = threadIdx.x;
+  const int n = a.n_points;
+  for (int c = blockIdx.x; c < a.n_curves; c += gridDim.x) {
+    const double* y = a.y + (int64_t)c * n;
+    const double* dy = a.dy + (int64_t)c * n;
+    double sw = 0.0, swy = 0.0, sy = 0.0;
+    for (int i = t; i < n; i += kPrepThreads) {
+      const double w = 1.0 / (dy[i] * dy[i]);
+      sw += w;
+      swy += w * y[i];
+      sy += y[i];
+    }
+    sw = block_sum(sw, red);
+    swy = block_sum(swy, red);
+    sy = block_sum(sy, red);
+    const double mu = a.center == 0 ? swy / sw : (a.center == 1 ? sy / (double)n : 0.0);
+    double ay = 0.0;
+    for (int i = t; i < n; i += kPrepThreads) {
+      const double w = 1.0 / (dy[i] * dy[i]);
+      ay += fabs(w * (y[i] - mu));
+    }
+    ay = block_sum(ay, red);
+    const double s_w = (1073741824.0 - 2.0 - 2.0 * (double)n) / sw;
+    const double s_y = ay > 0.0 ? (1073741824.0 - 2.0 - (double)n) / ay : 1.0;
+    const int g = c / kSharedGroupCurves, sub = c % kSharedGroupCurves;
+    for (int i = t; i < n; i += kPrepThreads) {
+      const double w = 1.0 / (dy[i] * dy[i]);
+      const double wx = w * (y[i] - mu);
+      const int32_t wq = (int32_t)fmax(1.0, rint(w * s_w));
+      const int32_t yq = (int32_t)rint(wx * s_y);
+      const int kb = i >> 5, h = (i >> 4) & 1, j = i & 15;
+      int8_t* row0 = a.vals + ((int64_t)g * a.n_kblocks + kb) * kSharedTileBytes + (32 * h + 8 * sub) * 16 + j;
+      put_digits(row0, wq, 0);
+      put_digits(row0, yq, 1);
+    }
+    if (t == 0) {
+      CurveConst k;
+      k.kc = (float)(s_w / (s_y * s_y));
+      k.ia2q = (float)(a.inv_alpha2 * s_w);
+      k.scale = a.stat_scale;
+      k.pad = 0.f;
+      a.cc[c] = k;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- plain FP64 comparator
 // One launch per curve, one lane per frequency, FP64 histograms in LDS
 // ([bin][lane], ds_add_f64), listing-order fold, IEEE division.
@@ -260,6 +327,12 @@ __global__ __launch_bounds__(kEntropyWaves * 64) void entropy_kernel(EntropyArgs
 hipError_t launch_prepare(const PrepArgs& a, hipStream_t s) {
   const int64_t g = a.n_curves < 65536 ? a.n_curves : 65536;
   hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)g), dim3(kPrepThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_shared(const SharedPrepArgs& a, hipStream_t s) {
+  const int g = a.n_curves < 65536 ? a.n_curves : 65536;
+  hipLaunchKernelGGL(prepare_shared_kernel, dim3((unsigned)g), dim3(kPrepThreads), 0, s, a);
   return hipGetLastError();
 }
 

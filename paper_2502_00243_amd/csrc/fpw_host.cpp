@@ -92,6 +92,12 @@ struct fpw_plan_s {
   int32_t* g_idx = nullptr;
   float* g_val = nullptr;
   bool graph_ok = true;
+  // shared-timestamp plans on the matrix cores
+  bool mfma = false;
+  int32_t sh_points = 0, sh_kblocks = 0, sh_chunk = 0, sh_fw = 0, sh_rounds = 0, sh_priv = 0;
+  int sh_grid_x = 0, sh_grid_y = 0;
+  size_t sh_lds = 0;
+  DevBuf sh_tau, sh_vals, sh_cc, sh_S;
   // profiling events: before prepare, after prepare, after batched, after merge
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool ev_recorded = false;
@@ -146,6 +152,7 @@ fpw_status check_options(const fpw_options& o) {
     return fail(FPW_EUNSUPPORTED, "%d periodogram variants exceed FPW_MAX_VARIANTS=%d", nvar, FPW_MAX_VARIANTS);
   if (nvar > 1 && o.freqs_per_lane == 2)
     return fail(FPW_EUNSUPPORTED, "derived bin counts are built for one frequency per lane");
+  if (o.shared_kernel < 0 || o.shared_kernel > 2) return fail(FPW_EINVAL, "shared_kernel must be 0, 1 or 2");
   return FPW_OK;
 }
 
@@ -361,8 +368,68 @@ fpw::MergeArgs merge_args(const fpw_plan_s* p, int32_t* idx, float* val) {
   return m;
 }
 
+fpw::SharedPrepArgs shared_prep_args(const fpw_plan_s* p) {
+  fpw::SharedPrepArgs a{};
+  a.y = p->y.as<double>();
+  a.dy = p->dy.as<double>();
+  a.n_curves = (int32_t)p->n_curves;
+  a.n_points = p->sh_points;
+  a.n_kblocks = p->sh_kblocks;
+  a.center = p->opt.center;
+  a.inv_alpha2 = p->opt.inv_alpha2;
+  a.stat_scale = p->opt.stat_scale == FPW_STAT_LISTING_HALF ? 0.5f : 1.0f;
+  a.vals = p->sh_vals.as<int8_t>();
+  a.cc = p->sh_cc.as<fpw::CurveConst>();
+  return a;
+}
+
+fpw::SharedArgs shared_args(const fpw_plan_s* p, float* S) {
+  fpw::SharedArgs a{};
+  a.tau = p->sh_tau.as<double>();
+  a.vals = p->sh_vals.as<int8_t>();
+  a.cc = p->sh_cc.as<fpw::CurveConst>();
+  a.freqs = p->freqs.as<double>();
+  a.n_curves = (int32_t)p->n_curves;
+  a.n_freq = (int32_t)p->n_freq;
+  a.n_bins = p->opt.n_bins;
+  a.n_kblocks = p->sh_kblocks;
+  a.chunk_kblocks = p->sh_chunk;
+  a.fw = p->sh_fw;
+  a.rounds = p->sh_rounds;
+  a.priv_bytes = p->sh_priv;
+  a.S = S;
+  return a;
+}
+
+// A pass of a shared-timestamp plan on the matrix cores: digits, products,
+// then peaks over the stored periodogram.
+fpw_status enqueue_shared_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipStream_t s) {
+  const bool prof = p->opt.profile != 0;
+  float* Sd = S ? S : p->sh_S.as<float>();
+  if (prof) FPW_HIP(hipEventRecord(p->ev[0], s), "event record");
+  FPW_HIP(fpw::launch_prepare_shared(shared_prep_args(p), s), "shared prepare kernel");
+  if (prof) FPW_HIP(hipEventRecord(p->ev[1], s), "event record");
+  FPW_HIP(fpw::launch_shared(shared_args(p, Sd), p->opt.phase, 4, p->sh_grid_x, p->sh_grid_y, p->sh_lds, s),
+          "shared kernel");
+  if (prof) FPW_HIP(hipEventRecord(p->ev[2], s), "event record");
+  if (idx != nullptr) {
+    fpw::TopkArgs a{};
+    a.S = Sd;
+    a.n_curves = (int32_t)p->n_curves;
+    a.n_freq = (int32_t)p->n_freq;
+    a.k = p->opt.topk;
+    a.out_idx = idx;
+    a.out_val = val;
+    FPW_HIP(fpw::launch_topk(a, s), "top-k kernel");
+  }
+  if (prof) FPW_HIP(hipEventRecord(p->ev[3], s), "event record");
+  p->ev_merge = idx != nullptr;
+  return FPW_OK;
+}
+
 // One full pass: prepare, fold/bin/accumulate/reduce (+ fused peaks), merge.
 fpw_status enqueue_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipStream_t s) {
+  if (p->mfma) return enqueue_shared_pass(p, S, idx, val, s);
   const bool prof = p->opt.profile != 0;
   if (prof) FPW_HIP(hipEventRecord(p->ev[0], s), "event record");
   FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
@@ -616,6 +683,81 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
   }
 }
 
+fpw_status fpw_plan_shared(fpw_plan_t* out, int64_t n_curves, int64_t n_points, const double* t, const double* y,
+                           const double* dy, int64_t n_freq, const double* freqs, const fpw_options* opt,
+                           void* stream) {
+  g_err.clear();
+  if (!out) return fail(FPW_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!t || !y || !dy || !freqs) return fail(FPW_EINVAL, "null input pointer");
+  if (n_curves < 1) return fail(FPW_EINVAL, "n_curves must be >= 1");
+  if (n_points < 1) return fail(FPW_EINVAL, "n_points must be >= 1");
+  if (n_points > FPW_MAX_CURVE_POINTS) return fail(FPW_EUNSUPPORTED, "n_points %lld > %d", (long long)n_points, FPW_MAX_CURVE_POINTS);
+  if (n_curves > (int64_t)INT32_MAX / n_points) return fail(FPW_EUNSUPPORTED, "n_curves * n_points too large");
+  fpw_options o;
+  fpw_options_default(&o);
+  if (opt) o = *opt;
+  fpw_status st = check_options(o);
+  if (st != FPW_OK) return st;
+  const bool fits = o.n_bins <= fpw::kSharedMaxBins && (o.phase == FPW_PHASE_FP64 || o.phase == FPW_PHASE_FP64_LISTING) &&
+                    o.derived_bins[0] == 0 && (n_curves + 15) / 16 <= 65535;
+  if (o.shared_kernel == FPW_SHARED_MATRIX && !fits)
+    return fail(FPW_EUNSUPPORTED, "the matrix-core kernel needs n_bins <= %d, phase FP64 or FP64_LISTING, no derived bin "
+                "counts and at most 1048560 curves", fpw::kSharedMaxBins);
+  const bool mfma = fits && o.shared_kernel != FPW_SHARED_GENERAL;
+  try {
+    // the equivalent CSR batch: every curve holds the common times
+    std::vector<int64_t> offs((size_t)n_curves + 1);
+    for (int64_t c = 0; c <= n_curves; ++c) offs[(size_t)c] = c * n_points;
+    std::vector<double> tt((size_t)(n_curves * n_points));
+    for (int64_t c = 0; c < n_curves; ++c) std::memcpy(&tt[(size_t)(c * n_points)], t, (size_t)n_points * sizeof(double));
+    fpw_plan_t raw = nullptr;
+    st = fpw_plan(&raw, n_curves, offs.data(), tt.data(), y, dy, n_freq, freqs, &o, stream);
+    if (st != FPW_OK) return st;
+    std::unique_ptr<fpw_plan_s> guard(raw);
+    fpw_plan_s* p = raw;
+    if (mfma) {
+      hipStream_t s = (hipStream_t)stream;
+      const int M = o.n_bins;
+      p->mfma = true;
+      p->sh_points = (int32_t)n_points;
+      p->sh_kblocks = (int32_t)((n_points + 31) / 32);
+      p->sh_chunk = std::min(p->sh_kblocks, 16);
+      p->sh_fw = std::min(8, fpw::kSharedMaxBins / M);
+      const int term_bytes = 4 * 4 * 65 * (int)sizeof(float);
+      p->sh_priv = round_up(std::max(p->sh_fw * p->sh_chunk * 32, term_bytes), 16);
+      p->sh_lds = (size_t)4 * p->sh_chunk * fpw::kSharedTileBytes + (size_t)fpw::kSharedWaves * p->sh_priv;
+      const int64_t nfb = (n_freq + p->sh_fw - 1) / p->sh_fw;        // frequency blocks
+      const int64_t wrounds = (nfb + fpw::kSharedWaves - 1) / fpw::kSharedWaves;
+      p->sh_grid_y = (int)((n_curves + 15) / 16);
+      p->sh_rounds = (int)std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)p->sh_grid_y * wrounds / 2048));
+      p->sh_grid_x = (int)((wrounds + p->sh_rounds - 1) / p->sh_rounds);
+      const int64_t groups = (int64_t)p->sh_grid_y * 4;
+      // the common time offsets, formed once in FP64 as for every curve
+      double tmin = t[0];
+      for (int64_t i = 1; i < n_points; ++i) tmin = std::min(tmin, t[i]);
+      const double tref = o.tref_mode == FPW_TREF_ZERO ? 0.0 : (o.tref_mode == FPW_TREF_FIRST ? tmin : o.t_ref);
+      std::vector<double> tau((size_t)p->sh_kblocks * 32, 0.0);
+      for (int64_t i = 0; i < n_points; ++i) tau[(size_t)i] = t[i] - tref;
+      st = upload(p->sh_tau, tau.data(), tau.size(), s, "upload shared tau");
+      if (st != FPW_OK) return st;
+      const size_t vbytes = (size_t)groups * p->sh_kblocks * fpw::kSharedTileBytes;
+      FPW_HIP(p->sh_vals.alloc(vbytes), "alloc digit tiles");
+      FPW_HIP(hipMemsetAsync(p->sh_vals.p, 0, vbytes, s), "clear digit tiles");
+      FPW_HIP(p->sh_cc.alloc((size_t)groups * 4 * sizeof(fpw::CurveConst)), "alloc shared constants");
+      FPW_HIP(hipMemsetAsync(p->sh_cc.p, 0, p->sh_cc.bytes, s), "clear shared constants");
+      FPW_HIP(p->sh_S.alloc((size_t)n_curves * (size_t)n_freq * sizeof(float)), "alloc shared periodogram");
+      FPW_HIP(hipStreamSynchronize(s), "shared plan sync");
+    }
+    *out = guard.release();
+    return FPW_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FPW_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(FPW_EHIP, "unexpected exception");
+  }
+}
+
 fpw_status fpw_eval_batch(fpw_plan_t p, float* S_dev, int32_t* topk_idx, float* topk_val, void* stream) {
   g_err.clear();
   if (!p) return fail(FPW_EINVAL, "plan is NULL");
@@ -797,6 +939,16 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   info->tuned = p->tuned ? 1 : 0;
   info->point_source = p->shape.point_source + 1;
   info->n_variants = p->var.n;
+  info->kernel = p->mfma ? 1 : 0;
+  if (p->mfma) {
+    info->grid_groups = p->sh_grid_x * p->sh_grid_y;
+    info->work_items = p->sh_grid_x * p->sh_grid_y * p->sh_rounds * fpw::kSharedWaves;
+    info->lds_bytes = (int32_t)p->sh_lds;
+    info->chunk_freqs = p->sh_fw;
+    info->waves_per_group = fpw::kSharedWaves;
+    info->freqs_per_lane = 0;
+    info->point_source = 0;
+  }
   return FPW_OK;
 }
 

@@ -138,6 +138,43 @@ struct EntropyArgs {
   float* V;
 };
 
+// Shared-timestamp batches (every curve observed at the same times).  Per
+// curve and point, the fixed-point weight and weighted residual (30-bit
+// ranges) are split into four signed base-256 digits each; the digits sit in
+// 1 KB tiles laid out as the A operand of the 32x32x32 int8 matrix product:
+// tile (group g of 4 curves, K-block kb of 32 points), lane l = 32h + r reads
+// bytes [16 l, 16 l + 16): row r = 8 s + 4 q + i is digit i of quantity q
+// (0 weight, 1 residual) of curve 4g + s, byte j is point 32 kb + 16 h + j.
+constexpr int kSharedGroupCurves = 4;   // curves per A tile
+constexpr int kSharedTileBytes = 1024;  // one tile: 32 rows x 32 points
+constexpr int kSharedMaxBins = 64;      // one-hot columns of one wave
+constexpr int kSharedWaves = 8;         // waves per workgroup of the shared kernel
+
+struct SharedPrepArgs {
+  const double* y;         // [n_curves * n_points], curve-major
+  const double* dy;
+  int32_t n_curves, n_points, n_kblocks;
+  int center;              // FPW_CENTER_*
+  double inv_alpha2;
+  float stat_scale;
+  int8_t* vals;            // [n_groups * n_kblocks * 1024]; padding stays zero
+  CurveConst* cc;          // [n_curves padded]
+};
+
+struct SharedArgs {
+  const double* tau;       // [n_kblocks * 32] shared time offsets, zero-padded
+  const int8_t* vals;      // digit tiles, see above
+  const CurveConst* cc;    // [n_curves padded]
+  const double* freqs;     // [n_freq]
+  int32_t n_curves, n_freq, n_bins;
+  int32_t n_kblocks;       // K-blocks of 32 points
+  int32_t chunk_kblocks;   // K-blocks staged in LDS at a time
+  int32_t fw;              // frequencies per wave per round (fw * n_bins <= 64)
+  int32_t rounds;          // rounds per workgroup (8 waves x fw frequencies each)
+  int32_t priv_bytes;      // LDS bytes private to each wave
+  float* S;                // [n_curves * n_freq]
+};
+
 // Launch shapes of the batched kernel.
 struct Shape {
   int freqs_per_lane;   // 1 or 2
@@ -155,6 +192,10 @@ hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
 hipError_t launch_fp64(const Fp64Args& a, hipStream_t s);
 hipError_t launch_bins(const BinsArgs& a, hipStream_t s);
 hipError_t launch_entropy(const EntropyArgs& a, hipStream_t s);
+hipError_t launch_prepare_shared(const SharedPrepArgs& a, hipStream_t s);
+// curve_groups: A tiles (of 4 curves) per workgroup; 4 is the one built
+hipError_t launch_shared(const SharedArgs& a, int phase, int curve_groups, int grid_x, int grid_y, size_t lds_bytes,
+                         hipStream_t s);
 
 // LDS bytes the batched kernel needs per workgroup.
 size_t batched_lds_bytes(const Shape& shape, int n_bins);

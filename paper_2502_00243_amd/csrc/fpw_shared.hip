@@ -1,0 +1,197 @@
+// Shared-timestamp batches on the matrix cores.
+//
+// When many curves are observed at the same times (Sec. 4: the batch function
+// for light curves that share timestamps; App. C: all sources of one image
+// field), the bin of an observation depends only on (frequency, time), so one
+// fold serves every curve.  For a fixed frequency f the per-bin sums of all
+// curves are then one matrix product,
+//
+//     [W | Y]_{(curve), m} = sum over points p of V[(curve, quantity), p] * [bin(f, p) == m],
+//
+// a dense contraction over the points.  Here it runs exactly on the int8
+// matrix cores: V holds the four signed base-256 digits of each point's
+// fixed-point weight and weighted residual (rows of the A operand), the
+// one-hot indicator of the bins is the B operand (columns = (frequency, bin)
+// pairs), and v_mfma_i32_32x32x32_i8 accumulates in int32 without rounding.
+// The digit sums are recombined (two's-complement wrap is exact because
+// every bin sum lies within 30 bits), and the statistic of Eq. 1 is formed
+// as in the general kernel.
+//
+// Workgroup: 8 waves sharing one block of curves (CG tiles of 4 curves).  The
+// curves' digit tiles are staged in LDS (in chunks of up to 512 points); each
+// wave owns fw frequencies per round (fw * M <= 64 columns, two B tiles),
+// folds the chunk's points at those frequencies into bytes in its private
+// LDS, builds the one-hot operand from them and issues CG * 2 products per 32
+// points.
+#include "fpw_common.h"
+
+namespace fpw {
+namespace {
+
+using namespace dev;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kNB = 2;             // B tiles (32 columns each) per wave
+constexpr int kTermStride = 65;    // floats per curve row of the term table (odd: no bank conflicts)
+
+// Bytes of `bins` equal to m become 1, the others 0.  Every byte of bins and
+// of m is below 64, so x = bins ^ m has bytes in [0, 63] and
+// (x ^ 0x7f) + 1 = 0x80 - x per byte with no carry between bytes; its bit 7
+// is set exactly where x == 0.  mmx = (m * 0x01010101) ^ 0x7f7f7f7f.
+__device__ __forceinline__ int one_hot4(uint32_t bins, uint32_t mmx) {
+  return (int)((((bins ^ mmx) + 0x01010101u) >> 7) & 0x01010101u);
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int PH, int CG>
+__global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_per_eu(1, 2))) void shared_kernel(SharedArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int n = lane & 31, h = lane >> 5;
+  const int M = a.n_bins;
+  const int KCB = a.chunk_kblocks, KC = KCB * 32;
+  unsigned char* vals = lds;
+  unsigned char* priv = lds + (size_t)CG * KCB * kSharedTileBytes + (size_t)wave * a.priv_bytes;
+  uint32_t* binw = reinterpret_cast<uint32_t*>(priv);  // [fw][KC] bytes, 4 per word
+  float* terms = reinterpret_cast<float*>(priv);       // [4 CG][kTermStride], after the products
+  const int g0 = blockIdx.y * CG;                      // first curve group of the block
+  const int n_chunks = (a.n_kblocks + KCB - 1) / KCB;
+
+  // column (frequency slot, bin) of each B tile; padding columns match nothing
+  int colf[kNB];
+  uint32_t colm[kNB];
+#pragma unroll
+  for (int b = 0; b < kNB; ++b) {
+    const int col = 32 * b + n;
+    int m = 127;
+    colf[b] = 0;
+    if (col < a.fw * M) {
+      colf[b] = col / M;
+      m = col - colf[b] * M;
+    }
+    colm[b] = ((uint32_t)m * 0x01010101u) ^ 0x7f7f7f7fu;
+  }
+
+  for (int r = 0; r < a.rounds; ++r) {
+    const int f0 = ((blockIdx.x * a.rounds + r) * kSharedWaves + wave) * a.fw;
+    v16i acc[CG][kNB];
+#pragma unroll
+    for (int ai = 0; ai < CG; ++ai)
+#pragma unroll
+      for (int b = 0; b < kNB; ++b) acc[ai][b] = (v16i){};
+
+    for (int ch = 0; ch < n_chunks; ++ch) {
+      const int kb0 = ch * KCB;
+      const int kbn = min(KCB, a.n_kblocks - kb0);
+      if (n_chunks > 1 || r == 0) {
+        __syncthreads();  // every wave is done with the previous chunk
+        const int pieces = CG * kbn * (kSharedTileBytes / 16);
+        for (int i = tid; i < pieces; i += kSharedWaves * kWave) {
+          const int t = i >> 6, piece = i & 63;
+          const int ai = t / kbn, kbl = t - ai * kbn;
+          const v4i v = *reinterpret_cast<const v4i*>(
+              a.vals + ((int64_t)(g0 + ai) * a.n_kblocks + kb0 + kbl) * kSharedTileBytes + piece * 16);
+          *reinterpret_cast<v4i*>(vals + (size_t)(ai * KCB + kbl) * kSharedTileBytes + piece * 16) = v;
+        }
+        __syncthreads();
+      }
+      // this wave's bins of the chunk's points, one byte each
+      for (int fl = 0; fl < a.fw; ++fl) {
+        Folder<PH> fo;
+        fo.init(a.freqs[min(f0 + fl, a.n_freq - 1)], M);
+        for (int d = lane; d < kbn * 8; d += kWave) {
+          const double* tp = a.tau + (int64_t)kb0 * 32 + d * 4;
+          uint32_t word = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            int bin = fo.bin((uint64_t)__double_as_longlong(tp[q]));
+            bin = bin >= M ? bin - M : bin;  // the fused FP64 fold reports bin 0 as M
+            word |= (uint32_t)bin << (8 * q);
+          }
+          binw[fl * (KC / 4) + d] = word;
+        }
+      }
+      wave_lds_fence();
+      for (int kb = 0; kb < kbn; ++kb) {
+        v4i av[CG];
+#pragma unroll
+        for (int ai = 0; ai < CG; ++ai)
+          av[ai] = *reinterpret_cast<const v4i*>(vals + (size_t)(ai * KCB + kb) * kSharedTileBytes + lane * 16);
+        v4i bv[kNB];
+#pragma unroll
+        for (int b = 0; b < kNB; ++b) {
+          const v4i bins = *reinterpret_cast<const v4i*>(priv + colf[b] * KC + kb * 32 + h * 16);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)bins[i], colm[b]);
+        }
+#pragma unroll
+        for (int ai = 0; ai < CG; ++ai)
+#pragma unroll
+          for (int b = 0; b < kNB; ++b) acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
+      }
+    }
+
+    // Epilogue.  Lane (n, h) of product (ai, b) holds column 32 b + n and, in
+    // register 4 s + i, digit i of quantity h of curve 4 ai + s.
+    wave_lds_fence();
+#pragma unroll
+    for (int ai = 0; ai < CG; ++ai) {
+#pragma unroll
+      for (int b = 0; b < kNB; ++b) {
+#pragma unroll
+        for (int sc = 0; sc < 4; ++sc) {
+          const v16i& c = acc[ai][b];
+          const int v = (int)((uint32_t)c[4 * sc] + ((uint32_t)c[4 * sc + 1] << 8) + ((uint32_t)c[4 * sc + 2] << 16) +
+                              ((uint32_t)c[4 * sc + 3] << 24));
+          const int o = __shfl_xor(v, 32);
+          if (h == 0) {
+            const int cl = 4 * ai + sc;
+            const float ia2q = a.cc[(int64_t)(g0 * kSharedGroupCurves + cl)].ia2q;
+            const float d = fmaxf((float)(uint32_t)v + ia2q, 0.5f);
+            const float yf = (float)o;
+            terms[cl * kTermStride + 32 * b + n] = yf * (yf * __builtin_amdgcn_rcpf(d));
+          }
+        }
+      }
+    }
+    wave_lds_fence();
+    for (int pi = lane; pi < a.fw * 4 * CG; pi += kWave) {
+      const int fl = pi / (4 * CG), cl = pi - fl * (4 * CG);
+      const float* tr = terms + cl * kTermStride + fl * M;
+      float s = 0.f;
+      for (int m = 0; m < M; ++m) s += tr[m];
+      const int c = g0 * kSharedGroupCurves + cl, k = f0 + fl;
+      if (c < a.n_curves && k < a.n_freq) {
+        const CurveConst cc = a.cc[c];
+        a.S[(int64_t)c * a.n_freq + k] = s * cc.kc * cc.scale;
+      }
+    }
+    wave_lds_fence();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_shared(const SharedArgs& a, int phase, int curve_groups, int grid_x, int grid_y, size_t lds_bytes,
+                         hipStream_t s) {
+  if (curve_groups != 4) return hipErrorInvalidValue;
+  const void* fn = phase == PH_LISTING ? (const void*)shared_kernel<PH_LISTING, 4> : (const void*)shared_kernel<PH_FP64, 4>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)grid_x, (unsigned)grid_y), block(kSharedWaves * kWave);
+  if (phase == PH_LISTING)
+    hipLaunchKernelGGL((shared_kernel<PH_LISTING, 4>), grid, block, lds_bytes, s, a);
+  else
+    hipLaunchKernelGGL((shared_kernel<PH_FP64, 4>), grid, block, lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fpw

@@ -25,6 +25,7 @@ CENTER = {"weighted": 0, "mean": 1, "none": 2}
 TREF = {"zero": 0, "first": 1, "given": 2}
 PHASE = {"fp64": 0, "fp64_listing": 1, "df32": 2, "fp32": 3}
 STAT = {"eq1": 0, "listing_half": 1}
+SHARED_KERNEL = {"auto": 0, "general": 1, "matrix": 2}
 MAX_BINS = 255
 MAX_TOPK = 16
 
@@ -55,6 +56,7 @@ class Options(ctypes.Structure):
         ("derived_bins", ctypes.c_int32 * 4),
         ("all_offsets", ctypes.c_int32),
         ("profile", ctypes.c_int32),
+        ("shared_kernel", ctypes.c_int32),
     ]
 
 
@@ -76,6 +78,7 @@ class PlanInfo(ctypes.Structure):
         ("tuned", ctypes.c_int32),
         ("point_source", ctypes.c_int32),
         ("n_variants", ctypes.c_int32),
+        ("kernel", ctypes.c_int32),
     ]
 
 
@@ -111,6 +114,8 @@ def load(path: str = LIB_PATH):
     lib.fpw_options_default.restype = None
     lib.fpw_plan.argtypes = [ctypes.POINTER(P), i64, ctypes.POINTER(i64), dp, dp, dp, i64, dp, ctypes.POINTER(Options), P]
     lib.fpw_plan.restype = ctypes.c_int
+    lib.fpw_plan_shared.argtypes = [ctypes.POINTER(P), i64, i64, dp, dp, dp, i64, dp, ctypes.POINTER(Options), P]
+    lib.fpw_plan_shared.restype = ctypes.c_int
     lib.fpw_eval_batch.argtypes = [P, P, P, P, P]
     lib.fpw_eval_batch.restype = ctypes.c_int
     lib.fpw_topk.argtypes = [P, P, i32, P, P, P]
@@ -150,7 +155,8 @@ def default_options() -> Options:
 
 def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="fp64", stat_scale="eq1", topk=0,
                  inv_alpha2=0.0, autotune=False, use_graph=True, freqs_per_lane=0, waves_per_group=0, chunk_freqs=0,
-                 tune_cache=None, profile=False, point_source=0, derived_bins=(), all_offsets=False) -> Options:
+                 tune_cache=None, profile=False, point_source=0, derived_bins=(), all_offsets=False,
+                 shared_kernel=0) -> Options:
     o = default_options()
     o.n_bins = int(n_bins)
     o.center = CENTER[center] if isinstance(center, str) else int(center)
@@ -173,6 +179,7 @@ def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="
     for i in range(4):
         o.derived_bins[i] = int(derived_bins[i]) if i < len(derived_bins) else 0
     o.all_offsets = int(bool(all_offsets))
+    o.shared_kernel = SHARED_KERNEL[shared_kernel] if isinstance(shared_kernel, str) else int(shared_kernel)
     return o
 
 
@@ -210,6 +217,31 @@ class Plan:
         _check(st)
         self._h = h
         self.n_variants = self.info().n_variants
+
+    @classmethod
+    def shared(cls, t, y, dy, freqs, n_bins, stream=None, **opts):
+        """A plan for curves observed at common times: t [n_points], y and dy [n_curves, n_points]."""
+        lib = load()
+        self = cls.__new__(cls)
+        self._t = _f64(t)
+        y2, dy2 = np.asarray(y, dtype=np.float64), np.asarray(dy, dtype=np.float64)
+        if y2.ndim != 2 or y2.shape != dy2.shape or y2.shape[1] != len(self._t):
+            raise ValueError("y and dy must be [n_curves, n_points] with n_points = len(t)")
+        self._y, self._dy, self._freqs = _f64(y2), _f64(dy2), _f64(freqs)
+        self.options = make_options(n_bins, **opts)
+        self.n_curves = int(y2.shape[0])
+        self.n_freq = len(self._freqs)
+        self.n_bins = int(n_bins)
+        self.topk_k = int(opts.get("topk", 0))
+        self._offsets = np.arange(self.n_curves + 1, dtype=np.int64) * len(self._t)
+        h = ctypes.c_void_p()
+        st = lib.fpw_plan_shared(ctypes.byref(h), self.n_curves, len(self._t), _ptr(self._t, ctypes.c_double),
+                                 _ptr(self._y, ctypes.c_double), _ptr(self._dy, ctypes.c_double), self.n_freq,
+                                 _ptr(self._freqs, ctypes.c_double), ctypes.byref(self.options), _stream_handle(stream))
+        _check(st)
+        self._h = h
+        self.n_variants = self.info().n_variants
+        return self
 
     @classmethod
     def from_batch(cls, batch, stream=None, **opts):
@@ -333,6 +365,24 @@ def plan_status(offsets, t, y, dy, freqs, n_bins, **opts):
     st = lib.fpw_plan(ctypes.byref(h), len(offsets) - 1, _ptr(offsets, ctypes.c_int64), _ptr(t, ctypes.c_double),
                       _ptr(y, ctypes.c_double), _ptr(dy, ctypes.c_double), len(freqs), _ptr(freqs, ctypes.c_double),
                       ctypes.byref(o), ctypes.c_void_p(0))
+    msg = lib.fpw_last_error().decode()
+    if st == OK and h:
+        lib.fpw_plan_destroy(h)
+    return st, msg
+
+
+def plan_shared_status(t, y, dy, freqs, n_bins, **opts):
+    """Calls fpw_plan_shared and returns (status, message) without raising (for argument-check tests)."""
+    lib = load()
+    t, y, dy, freqs = _f64(t), _f64(y), _f64(dy), _f64(freqs)
+    if y.ndim != 2 or y.shape != dy.shape or y.shape[1] != len(t):
+        raise ValueError("y and dy must be [n_curves, n_points] with n_points = len(t)")
+    n_curves = y.shape[0]
+    o = make_options(n_bins, **opts)
+    h = ctypes.c_void_p()
+    st = lib.fpw_plan_shared(ctypes.byref(h), n_curves, len(t), _ptr(t, ctypes.c_double), _ptr(y, ctypes.c_double),
+                             _ptr(dy, ctypes.c_double), len(freqs), _ptr(freqs, ctypes.c_double), ctypes.byref(o),
+                             ctypes.c_void_p(0))
     msg = lib.fpw_last_error().decode()
     if st == OK and h:
         lib.fpw_plan_destroy(h)

@@ -26,7 +26,9 @@ __all__ = [
     "ztf_batch",
     "uneven_batch",
     "stress_batch",
+    "shared_batch",
     "random_batch",
+    "random_shared_batch",
     "GRIDS",
 ]
 
@@ -39,7 +41,7 @@ GRIDS = {
 }
 BINS = {"single": 10, "ztf": 20, "uneven": 20, "stress": 50}
 # independent seed streams per workload
-_SEED_ID = {"single": 1, "ztf": 2, "uneven": 4, "stress": 5}
+_SEED_ID = {"single": 1, "ztf": 2, "uneven": 4, "stress": 5, "shared": 6}
 
 _KINDS = ("noise", "sinusoid", "eclipse", "sawtooth", "double")
 
@@ -70,6 +72,16 @@ class Batch:
     def curve(self, c: int):
         a, b = int(self.offsets[c]), int(self.offsets[c + 1])
         return self.t[a:b], self.y[a:b], self.dy[a:b]
+
+    def as_shared(self):
+        """(t [n_points], y [n_curves, n_points], dy [n_curves, n_points]) when every curve has the same times."""
+        n = self.lengths
+        if not np.all(n == n[0]):
+            raise ValueError("curves differ in length")
+        t = self.t.reshape(self.n_curves, int(n[0]))
+        if not np.array_equal(t, np.broadcast_to(t[0], t.shape)):
+            raise ValueError("curves differ in their times")
+        return t[0].copy(), self.y.reshape(t.shape).copy(), self.dy.reshape(t.shape).copy()
 
     def evals(self) -> int:
         """Observation x frequency evaluations one periodogram pass performs."""
@@ -247,6 +259,41 @@ def stress_batch(n_curves: int = 20_000) -> Batch:
     return _assemble(curves, _grid("stress"), BINS["stress"], labels, "stress_batch")
 
 
+def _ztf_signal(rng, t, dy):
+    """80% noise, 10% sinusoids, 10% box eclipses, as in the ZTF-like batch."""
+    n = len(t)
+    y = dy * rng.standard_normal(n)
+    u = rng.random()
+    if u < 0.1:
+        amp = _log_uniform(rng, 0.01, 0.1)
+        f0 = _log_uniform(rng, 0.1, 20.0)
+        y += amp * np.sin(2.0 * np.pi * (f0 * t + rng.random()))
+        return y, dict(kind="sinusoid", f0=f0, amp=amp)
+    if u < 0.2:
+        depth = rng.uniform(0.1, 0.5)
+        f0 = _log_uniform(rng, 0.1, 20.0)
+        y += depth * _waveform("eclipse", np.mod(f0 * t + rng.random(), 1.0), 0.05)
+        return y, dict(kind="eclipse", f0=f0, amp=depth, duty=0.05)
+    return y, dict(kind="noise", f0=0.0, amp=0.0)
+
+
+def shared_batch(n_curves: int = 1000, n_points: int = 500) -> Batch:
+    """One image field: n_curves sources observed at the same n_points ZTF-like epochs over 1500 d.
+
+    Each source has its own lognormal errors and signal (ZTF-like mix); M = 20,
+    1e5 frequencies 0.05-50 /d.
+    """
+    rngs = _seed("shared", n_curves + 1)
+    t = _nightly_times(rngs[0], _observable_nights(1500.0), n_points, replace=False)
+    curves, labels = [], []
+    for rng in rngs[1:]:
+        dy = _ztf_sigma(rng, n_points)
+        y, lab = _ztf_signal(rng, t, dy)
+        curves.append((t, y, dy))
+        labels.append(lab)
+    return _assemble(curves, _grid("ztf"), BINS["ztf"], labels, "shared_batch")
+
+
 def workload(name: str, n_curves: int | None = None) -> Batch:
     """Workload by name: single, ztf (1000 curves), uneven (1e5), stress (2e4)."""
     if name == "single":
@@ -257,6 +304,8 @@ def workload(name: str, n_curves: int | None = None) -> Batch:
         return uneven_batch(100_000 if n_curves is None else n_curves)
     if name == "stress":
         return stress_batch(20_000 if n_curves is None else n_curves)
+    if name == "shared":
+        return shared_batch(1000 if n_curves is None else n_curves)
     raise ValueError(name)
 
 
@@ -281,3 +330,18 @@ def random_batch(
         curves.append((t, s + dy * rng.standard_normal(n), dy))
         labels.append(lab)
     return _assemble(curves, np.asarray(freqs, dtype=np.float64), n_bins, labels, f"random{seed}")
+
+
+def random_shared_batch(seed: int, n_curves: int, n_points: int, freqs: np.ndarray, n_bins: int,
+                        t_max: float = 1500.0) -> Batch:
+    """Small shared-timestamp batches for parity tests: one set of uniform times, per-curve errors and signals."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([2502, 243, 2000 + seed])))
+    t = np.sort(rng.uniform(0.0, t_max, n_points))
+    curves, labels = [], []
+    for _ in range(n_curves):
+        dy = _ztf_sigma(rng, n_points)
+        f0 = _log_uniform(rng, 0.1, 20.0)
+        s, lab = _mixed_waveform_curve(rng, t, dy, f0) if n_points > 1 else (np.zeros(n_points), dict(kind="noise", f0=0.0))
+        curves.append((t, s + dy * rng.standard_normal(n_points), dy))
+        labels.append(lab)
+    return _assemble(curves, np.asarray(freqs, dtype=np.float64), n_bins, labels, f"random_shared{seed}")

@@ -115,3 +115,52 @@ def test_valid_plan_without_gpu_reports_hip_error():
     off, t, y, dy, f = _good()
     st, msg = fpw.plan_status(off, t, y, dy, f, 4)
     assert st == fpw.EHIP and msg
+
+
+# ---------------------------------------------------------------- shared-timestamp plans
+
+
+def _good_shared():
+    t = np.array([0.1, 2.0, 7.5, 9.0])
+    y = np.array([[1.0, 2.0, 1.5, 0.0], [0.3, 0.1, -0.2, 0.0], [0.0, 0.5, 0.5, 0.1]])
+    dy = np.full(y.shape, 0.1)
+    f = np.linspace(0.1, 3.0, 40)
+    return t, y, dy, f
+
+
+SHARED_CASES = [
+    ("nan y", dict(y=lambda y: np.where(y == 2.0, np.nan, y)), {}, fpw.EINVAL),
+    ("dy = 0", dict(dy=lambda d: np.where(np.arange(d.size).reshape(d.shape) == 5, 0.0, d)), {}, fpw.EINVAL),
+    ("negative t", dict(t=lambda t: t - 1.0), {}, fpw.EINVAL),
+    ("f = 0", dict(f=lambda f: np.concatenate([[0.0], f])), {}, fpw.EINVAL),
+    ("M too large for the matrix kernel", {}, dict(n_bins=65, shared_kernel="matrix"), fpw.EUNSUPPORTED),
+    ("df32 on the matrix kernel", {}, dict(phase="df32", shared_kernel="matrix"), fpw.EUNSUPPORTED),
+    ("variants on the matrix kernel", {}, dict(n_bins=20, derived_bins=(10,), shared_kernel="matrix"), fpw.EUNSUPPORTED),
+    ("bad kernel choice", {}, dict(shared_kernel=3), fpw.EINVAL),
+]
+
+
+@pytest.mark.parametrize("name,change,opts,expect", SHARED_CASES, ids=[c[0] for c in SHARED_CASES])
+def test_shared_plan_rejects_bad_arguments_on_host(name, change, opts, expect):
+    t, y, dy, f = _good_shared()
+    arrs = dict(t=t, y=y, dy=dy, f=f)
+    for k, fn in change.items():
+        arrs[k] = fn(arrs[k])
+    opts = dict(opts)
+    n_bins = opts.pop("n_bins", 4)
+    st, msg = fpw.plan_shared_status(arrs["t"], arrs["y"], arrs["dy"], arrs["f"], n_bins, **opts)
+    assert st == expect, (name, st, msg)
+    assert msg
+
+
+def test_shared_plan_null_and_empty_arguments():
+    lib = fpw.load()
+    h = ctypes.c_void_p()
+    assert lib.fpw_plan_shared(ctypes.byref(h), 1, 1, None, None, None, 1, None, None, None) == fpw.EINVAL
+    t, y, dy, f = _good_shared()
+    P = ctypes.POINTER(ctypes.c_double)
+    args = [t.ctypes.data_as(P), y.ctypes.data_as(P), dy.ctypes.data_as(P), len(f), f.ctypes.data_as(P), None, None]
+    assert lib.fpw_plan_shared(ctypes.byref(h), 0, 4, *args) == fpw.EINVAL
+    assert lib.fpw_plan_shared(ctypes.byref(h), 3, 0, *args) == fpw.EINVAL
+    with pytest.raises(ValueError):
+        fpw.plan_shared_status(t, y[:, :3], dy, f, 4)

@@ -504,3 +504,24 @@ def test_hutcheson_moments_match_multinomial_sampling(M, N):
     assert abs(H.var() - V) < 0.05 * V
     # the leading correction matters: log M alone is off by (M-1)/(2N)
     assert abs(H.mean() - math.log(M)) > 10 * se_mean
+
+
+# ---------------------------------------------------------------- shared timestamps (Sec. 4 batch function)
+
+
+def test_shared_periodogram_equals_per_curve_definition():
+    """Reusing the bins of the common times for every curve gives each curve's own Eq. 1 periodogram."""
+    rng = np.random.default_rng(77)
+    n, C = 150, 5
+    t = np.sort(rng.uniform(0, 1200, n))
+    dy = rng.uniform(0.01, 0.05, (C, n))
+    freqs = np.linspace(0.05, 5, 120)
+    f_inj = freqs[50]
+    y = dy * rng.standard_normal((C, n)) + 0.03 * np.sin(2 * np.pi * f_inj * t)
+    for opt in (OracleOptions(), OracleOptions(center="mean", inv_alpha2=3.0), OracleOptions(tref="first")):
+        S = oracle.shared_periodogram(t, y, dy, freqs, 12, opt)
+        for c in range(C):
+            np.testing.assert_array_equal(S[c], oracle.curve_periodogram(t, y[c], dy[c], freqs, 12, opt))
+    # the injected common signal (on a grid frequency) is the highest point of every curve's periodogram
+    S = oracle.shared_periodogram(t, y, dy, freqs, 12)
+    assert np.all(np.argmax(S, axis=1) == 50)
