@@ -46,21 +46,38 @@ __global__ __launch_bounds__(256) void merge_kernel(MergeArgs a) {
 }
 
 // ---------------------------------------------------------------- top-k over a stored periodogram
+// One workgroup of 8 waves per curve: the waves stride over the curve's
+// periodogram (coalesced), each keeps per-lane lists and selects its best k,
+// and the first wave selects the curve's k from the 8 x k candidates.
+constexpr int kTopkWaves = 8;
+
 template <int K>
-__global__ __launch_bounds__(256) void topk_kernel(TopkArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (c >= a.n_curves) return;  // wave-uniform
+__global__ __launch_bounds__(kTopkWaves * kWave) void topk_kernel(TopkArgs a) {
+  __shared__ float cand_v[kTopkWaves * K];
+  __shared__ int32_t cand_i[kTopkWaves * K];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int c = blockIdx.x;
   const float* S = a.S + (int64_t)c * a.n_freq;
   TopList<K> l;
   l.init();
-  for (int k = lane; k < a.n_freq; k += kWave) {
+  for (int k = threadIdx.x; k < a.n_freq; k += kTopkWaves * kWave) {
     const float s = S[k];
     const float left = k > 0 ? S[k - 1] : -INFINITY;
     const float right = k + 1 < a.n_freq ? S[k + 1] : -INFINITY;
     l.insert(s, k, s > left && s >= right);
   }
-  wave_select<K>(l, a.k, a.out_val + (int64_t)c * a.k, a.out_idx + (int64_t)c * a.k, lane);
+  wave_select<K>(l, a.k, cand_v + wave * K, cand_i + wave * K, lane);
+  __syncthreads();
+  if (wave == 0) {
+    TopList<K> m;
+    m.init();
+    for (int q = lane; q < kTopkWaves * a.k; q += kWave) {
+      const int w = q / a.k, r = q - w * a.k;
+      const int ci = cand_i[w * K + r];
+      m.insert(cand_v[w * K + r], ci, ci >= 0);
+    }
+    wave_select<K>(m, a.k, a.out_val + (int64_t)c * a.k, a.out_idx + (int64_t)c * a.k, lane);
+  }
 }
 
 // ---------------------------------------------------------------- prepare
@@ -160,16 +177,17 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepArgs a) {
 // either quantity stays below 2^30 in magnitude), then the four signed
 // base-256 digits of each quantity scattered into the curve's rows of the
 // int8 tiles.
-__device__ __forceinline__ void put_digits(int8_t* tile_row, int32_t v, int q) {
+// Writes the digits of v to four consecutive tile rows (16 bytes apart).
+__device__ __forceinline__ void put_digits(int8_t* tile_row, int32_t v, int) {
   // v = d0 + 256 d1 + 65536 d2 + 2^24 d3, each d in [-128, 127] for |v| <= 2^30
   int32_t r = v;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int32_t d = (int32_t)(int8_t)(r & 0xff);
-    tile_row[(4 * q + i) * 16] = (int8_t)d;
+    tile_row[i * 16] = (int8_t)d;
     r = (r - d) >> 8;
   }
-  tile_row[(4 * q + 3) * 16] = (int8_t)r;
+  tile_row[3 * 16] = (int8_t)r;
 }
 
 __global__ __launch_bounds__(kPrepThreads) void prepare_shared_kernel(SharedPrepArgs a) {
@@ -198,16 +216,18 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_shared_kernel(SharedPrep
     ay = block_sum(ay, red);
     const double s_w = (1073741824.0 - 2.0 - 2.0 * (double)n) / sw;
     const double s_y = ay > 0.0 ? (1073741824.0 - 2.0 - (double)n) / ay : 1.0;
+    // rows of curve `sub` of its group: 8 (2 (sub / 2) + q) + 4 (sub % 2) + digit
     const int g = c / kSharedGroupCurves, sub = c % kSharedGroupCurves;
+    const int row0 = 16 * (sub >> 1) + 4 * (sub & 1);
     for (int i = t; i < n; i += kPrepThreads) {
       const double w = 1.0 / (dy[i] * dy[i]);
       const double wx = w * (y[i] - mu);
       const int32_t wq = (int32_t)fmax(1.0, rint(w * s_w));
       const int32_t yq = (int32_t)rint(wx * s_y);
       const int kb = i >> 5, h = (i >> 4) & 1, j = i & 15;
-      int8_t* row0 = a.vals + ((int64_t)g * a.n_kblocks + kb) * kSharedTileBytes + (32 * h + 8 * sub) * 16 + j;
-      put_digits(row0, wq, 0);
-      put_digits(row0, yq, 1);
+      int8_t* base = a.vals + ((int64_t)g * a.n_kblocks + kb) * kSharedTileBytes + (32 * h + row0) * 16 + j;
+      put_digits(base, wq, 0);
+      put_digits(base + 8 * 16, yq, 0);
     }
     if (t == 0) {
       CurveConst k;
@@ -346,11 +366,11 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s) {
-  const int blocks = (a.n_curves + 3) / 4;
+  const dim3 grid((unsigned)a.n_curves), block(kTopkWaves * kWave);
   if (a.k <= 8)
-    hipLaunchKernelGGL(topk_kernel<8>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(topk_kernel<8>, grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL(topk_kernel<16>, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(topk_kernel<16>, grid, block, 0, s, a);
   return hipGetLastError();
 }
 

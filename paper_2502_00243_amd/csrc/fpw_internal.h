@@ -143,8 +143,10 @@ struct EntropyArgs {
 // ranges) are split into four signed base-256 digits each; the digits sit in
 // 1 KB tiles laid out as the A operand of the 32x32x32 int8 matrix product:
 // tile (group g of 4 curves, K-block kb of 32 points), lane l = 32h + r reads
-// bytes [16 l, 16 l + 16): row r = 8 s + 4 q + i is digit i of quantity q
-// (0 weight, 1 residual) of curve 4g + s, byte j is point 32 kb + 16 h + j.
+// bytes [16 l, 16 l + 16), byte j is point 32 kb + 16 h + j.  Row
+// r = 8 (2 u + q) + 4 v + i holds digit i of quantity q (0 weight, 1
+// residual) of curve 4g + 2u + v, so that the product's lanes of half v
+// receive both quantities of curves 4g + v and 4g + 2 + v.
 constexpr int kSharedGroupCurves = 4;   // curves per A tile
 constexpr int kSharedTileBytes = 1024;  // one tile: 32 rows x 32 points
 constexpr int kSharedMaxBins = 64;      // one-hot columns of one wave

@@ -79,6 +79,12 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
     }
     colm[b] = ((uint32_t)m * 0x01010101u) ^ 0x7f7f7f7fu;
   }
+  // prior term of the two curves per A tile this lane finishes: 4 ai + 2 u + h
+  float ia2q[CG][2];
+#pragma unroll
+  for (int ai = 0; ai < CG; ++ai)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) ia2q[ai][u] = a.cc[(int64_t)(g0 + ai) * kSharedGroupCurves + 2 * u + h].ia2q;
 
   for (int r = 0; r < a.rounds; ++r) {
     const int f0 = ((blockIdx.x * a.rounds + r) * kSharedWaves + wave) * a.fw;
@@ -103,62 +109,84 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
         }
         __syncthreads();
       }
-      // this wave's bins of the chunk's points, one byte each
+      // This wave's bins of the chunk's points, one byte each.  A lane owns
+      // the words d = lane and lane + 64 (four points each; KC <= 512) and
+      // folds their times at every frequency of the wave.
+      const int nd = kbn * 8;
+      double tv[2][4];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int d = min(lane + kWave * j, nd - 1);
+        const double* tp = a.tau + (int64_t)kb0 * 32 + d * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tv[j][q] = tp[q];
+      }
       for (int fl = 0; fl < a.fw; ++fl) {
         Folder<PH> fo;
         fo.init(a.freqs[min(f0 + fl, a.n_freq - 1)], M);
-        for (int d = lane; d < kbn * 8; d += kWave) {
-          const double* tp = a.tau + (int64_t)kb0 * 32 + d * 4;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int d = lane + kWave * j;
           uint32_t word = 0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            int bin = fo.bin((uint64_t)__double_as_longlong(tp[q]));
-            bin = bin >= M ? bin - M : bin;  // the fused FP64 fold reports bin 0 as M
-            word |= (uint32_t)bin << (8 * q);
+            const uint32_t bin = (uint32_t)fo.bin((uint64_t)__double_as_longlong(tv[j][q]));
+            // the fused FP64 fold reports bin 0 as M: min(bin, bin - M) folds it back
+            word |= min(bin, bin - (uint32_t)M) << (8 * q);
           }
-          binw[fl * (KC / 4) + d] = word;
+          if (d < nd) binw[fl * (KC / 4) + d] = word;
         }
       }
       wave_lds_fence();
-      for (int kb = 0; kb < kbn; ++kb) {
-        v4i av[CG];
+      // products, with the operands of the next 32 points read ahead
+      v4i av[CG], bins[kNB];
 #pragma unroll
-        for (int ai = 0; ai < CG; ++ai)
-          av[ai] = *reinterpret_cast<const v4i*>(vals + (size_t)(ai * KCB + kb) * kSharedTileBytes + lane * 16);
+      for (int ai = 0; ai < CG; ++ai)
+        av[ai] = *reinterpret_cast<const v4i*>(vals + (size_t)(ai * KCB) * kSharedTileBytes + lane * 16);
+#pragma unroll
+      for (int b = 0; b < kNB; ++b) bins[b] = *reinterpret_cast<const v4i*>(priv + colf[b] * KC + h * 16);
+      for (int kb = 0; kb < kbn; ++kb) {
         v4i bv[kNB];
 #pragma unroll
-        for (int b = 0; b < kNB; ++b) {
-          const v4i bins = *reinterpret_cast<const v4i*>(priv + colf[b] * KC + kb * 32 + h * 16);
+        for (int b = 0; b < kNB; ++b)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)bins[i], colm[b]);
-        }
+          for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)bins[b][i], colm[b]);
+        v4i avn[CG], binsn[kNB];
+        const int kn = kb + 1 < kbn ? kb + 1 : kb;
+#pragma unroll
+        for (int ai = 0; ai < CG; ++ai)
+          avn[ai] = *reinterpret_cast<const v4i*>(vals + (size_t)(ai * KCB + kn) * kSharedTileBytes + lane * 16);
+#pragma unroll
+        for (int b = 0; b < kNB; ++b) binsn[b] = *reinterpret_cast<const v4i*>(priv + colf[b] * KC + kn * 32 + h * 16);
 #pragma unroll
         for (int ai = 0; ai < CG; ++ai)
 #pragma unroll
           for (int b = 0; b < kNB; ++b) acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
+#pragma unroll
+        for (int ai = 0; ai < CG; ++ai) av[ai] = avn[ai];
+#pragma unroll
+        for (int b = 0; b < kNB; ++b) bins[b] = binsn[b];
       }
     }
 
     // Epilogue.  Lane (n, h) of product (ai, b) holds column 32 b + n and, in
-    // register 4 s + i, digit i of quantity h of curve 4 ai + s.
+    // registers 8 u + 4 q + i, digit i of quantity q of curve 4 ai + 2 u + h.
     wave_lds_fence();
 #pragma unroll
     for (int ai = 0; ai < CG; ++ai) {
 #pragma unroll
       for (int b = 0; b < kNB; ++b) {
+        const v16i& c = acc[ai][b];
 #pragma unroll
-        for (int sc = 0; sc < 4; ++sc) {
-          const v16i& c = acc[ai][b];
-          const int v = (int)((uint32_t)c[4 * sc] + ((uint32_t)c[4 * sc + 1] << 8) + ((uint32_t)c[4 * sc + 2] << 16) +
-                              ((uint32_t)c[4 * sc + 3] << 24));
-          const int o = __shfl_xor(v, 32);
-          if (h == 0) {
-            const int cl = 4 * ai + sc;
-            const float ia2q = a.cc[(int64_t)(g0 * kSharedGroupCurves + cl)].ia2q;
-            const float d = fmaxf((float)(uint32_t)v + ia2q, 0.5f);
-            const float yf = (float)o;
-            terms[cl * kTermStride + 32 * b + n] = yf * (yf * __builtin_amdgcn_rcpf(d));
-          }
+        for (int u = 0; u < 2; ++u) {
+          const int e = 8 * u;
+          const uint32_t wq = (uint32_t)c[e] + ((uint32_t)c[e + 1] << 8) + ((uint32_t)c[e + 2] << 16) +
+                              ((uint32_t)c[e + 3] << 24);
+          const int yq = (int)((uint32_t)c[e + 4] + ((uint32_t)c[e + 5] << 8) + ((uint32_t)c[e + 6] << 16) +
+                               ((uint32_t)c[e + 7] << 24));
+          const float d = fmaxf((float)wq + ia2q[ai][u], 0.5f);
+          const float yf = (float)yq;
+          terms[(4 * ai + 2 * u + h) * kTermStride + 32 * b + n] = yf * (yf * __builtin_amdgcn_rcpf(d));
         }
       }
     }
