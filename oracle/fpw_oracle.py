@@ -53,6 +53,9 @@ __all__ = [
     "prepare_curve",
     "curve_periodogram",
     "shared_periodogram",
+    "chebyshev_basis",
+    "bm_statistic_dense",
+    "bm_periodogram",
     "curve_bins",
     "periodogram",
     "peak_mask",
@@ -365,3 +368,84 @@ def entropy_variance(n_bins: int, n_obs: int) -> float:
     """App. C (Hutcheson): Var(H) for equiprobable bins, to order 1/N^3."""
     M, N = float(n_bins), float(n_obs)
     return (M - 1.0) / (2.0 * N * N) + (M * M - 1.0) / (6.0 * N * N * N)
+
+
+# ---------------------------------------------------------------- baseline-marginalised FPW (App. A, general case)
+
+
+def chebyshev_basis(t, n_terms: int, scale: float = 1.0) -> np.ndarray:
+    """Baseline basis B [N, K] of App. A: column k is scale * T_k(s) at s = 2 (t - t_min) / (t_max - t_min) - 1.
+
+    App. A suggests a Chebyshev polynomial basis for the drift without fixing
+    its domain or amplitude: the curve's own time span is mapped to [-1, 1]
+    (s = 0 for a single epoch) and the prior covariance is C_B = B B^T, so
+    each coefficient has prior standard deviation ``scale`` in flux units.
+    """
+    t = np.asarray(t, dtype=np.float64)
+    span = float(np.max(t) - np.min(t)) if len(t) else 0.0
+    s = 2.0 * (t - np.min(t)) / span - 1.0 if span > 0 else np.zeros_like(t)
+    B = np.empty((len(t), n_terms))
+    for k in range(n_terms):
+        if k == 0:
+            B[:, k] = 1.0
+        elif k == 1:
+            B[:, k] = s
+        else:
+            B[:, k] = 2.0 * s * B[:, k - 1] - B[:, k - 2]
+    return scale * B
+
+
+def bm_statistic_dense(x, w, bins, n_bins: int, B, inv_alpha2: float) -> float:
+    """App. A definition with dense matrices (finite alpha):
+
+    S = X^T (C_B + C_sigma)^-1 X - X^T (C_B + C_P + C_sigma)^-1 X,
+    C_sigma = diag(1/w), C_B = B B^T, C_P = P P^T with P = alpha * one-hot(bins).
+    (App. A writes the change of chi-square with the opposite sign; S is the
+    non-negative decrease.)
+    """
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    E = np.zeros((n, n_bins))
+    E[np.arange(n), np.asarray(bins)] = 1.0
+    C0 = np.diag(1.0 / np.asarray(w, dtype=np.float64)) + B @ B.T
+    C1 = C0 + (1.0 / inv_alpha2) * (E @ E.T)
+    return float(x @ np.linalg.solve(C0, x) - x @ np.linalg.solve(C1, x))
+
+
+def bm_periodogram(t, y, dy, freqs, n_bins: int, n_terms: int, scale: float = 1.0,
+                   opt: OracleOptions | None = None) -> np.ndarray:
+    """Baseline-marginalised S(f) for one curve (App. A, general case), FP64.
+
+    Follows App. A's steps: the frequency-independent inverse
+    C_Bsigma^-1 = (C_B + C_sigma)^-1 is formed once (Woodbury on the low-rank
+    C_B), then for each frequency the products with the one-hot P reduce to
+    bin sums: u = E^T C_Bsigma^-1 X (bin sums of C_Bsigma^-1 X) and
+    G = E^T C_Bsigma^-1 E (block sums of C_Bsigma^-1), and
+    S = u^T (alpha^-2 I + G)^-1 u over the occupied bins (an empty bin has
+    u_m = 0 and a zero row of G, so it adds nothing for any alpha).
+    ``n_terms = 0`` is the plain statistic of Eq. 1.
+    """
+    opt = opt or OracleOptions()
+    tau, w, x = prepare_curve(t, y, dy, opt)
+    n = len(x)
+    D = np.diag(w)
+    if n_terms > 0:
+        B = chebyshev_basis(t, n_terms, scale)
+        H = np.eye(n_terms) + B.T @ D @ B
+        Cinv = D - D @ B @ np.linalg.solve(H, B.T @ D)
+    else:
+        Cinv = D
+    CX = Cinv @ x
+    freqs = np.asarray(freqs, dtype=np.float64)
+    out = np.empty(len(freqs))
+    for r, f in enumerate(freqs):
+        b = phase_bins(tau, f, n_bins)
+        occ = np.unique(b)
+        idx = np.searchsorted(occ, b)
+        u = np.bincount(idx, weights=CX, minlength=len(occ))
+        G = np.zeros((len(occ), len(occ)))
+        np.add.at(G, (idx[:, None], idx[None, :]), Cinv)
+        A = G + opt.inv_alpha2 * np.eye(len(occ))
+        val = float(u @ np.linalg.solve(A, u))
+        out[r] = 0.5 * val if opt.stat_scale == "listing_half" else val
+    return out

@@ -525,3 +525,80 @@ def test_shared_periodogram_equals_per_curve_definition():
     # the injected common signal (on a grid frequency) is the highest point of every curve's periodogram
     S = oracle.shared_periodogram(t, y, dy, freqs, 12)
     assert np.all(np.argmax(S, axis=1) == 50)
+
+
+# ---------------------------------------------------------------- baseline-marginalised FPW (App. A, general case)
+
+
+def test_chebyshev_basis_closed_form():
+    """Columns are T_k(s) with s spanning [-1, 1]: T_k(cos th) = cos(k th)."""
+    th = np.linspace(0.0, np.pi, 37)
+    t = 500.0 * (np.cos(th[::-1]) + 1.0)  # s = cos(th) after mapping [0, 1000] to [-1, 1]
+    B = oracle.chebyshev_basis(t, 4, scale=2.5)
+    s = 2.0 * t / 1000.0 - 1.0
+    ths = np.arccos(np.clip(s, -1, 1))
+    for k in range(4):
+        np.testing.assert_allclose(B[:, k], 2.5 * np.cos(k * ths), atol=1e-12)
+    assert np.all(oracle.chebyshev_basis(np.full(3, 7.0), 3)[:, 1:] == [[0.0, -1.0]] * 3)
+
+
+def _bm_curve(rng, n=90, T=900.0):
+    t = np.sort(rng.uniform(0, T, n))
+    dy = rng.uniform(0.01, 0.05, n)
+    return t, dy * rng.standard_normal(n), dy
+
+
+@pytest.mark.parametrize("inv_alpha2", [0.0, 40.0])
+def test_bm_without_baseline_is_eq1(inv_alpha2):
+    rng = np.random.default_rng(101)
+    t, y, dy = _bm_curve(rng)
+    freqs = np.linspace(0.05, 4, 60)
+    opt = OracleOptions(inv_alpha2=inv_alpha2)
+    np.testing.assert_allclose(oracle.bm_periodogram(t, y, dy, freqs, 9, 0, opt=opt),
+                               oracle.curve_periodogram(t, y, dy, freqs, 9, opt), rtol=1e-12)
+    # a vanishing baseline prior gives Eq. 1 as well
+    np.testing.assert_allclose(oracle.bm_periodogram(t, y, dy, freqs, 9, 3, scale=1e-9, opt=opt),
+                               oracle.curve_periodogram(t, y, dy, freqs, 9, opt), rtol=1e-9)
+
+
+@pytest.mark.parametrize("K,scale,ia2", [(1, 1.0, 30.0), (2, 0.3, 5.0), (3, 1.0, 80.0), (3, 10.0, 1.0)])
+def test_bm_matches_dense_definition(K, scale, ia2):
+    """The step-by-step form equals the two dense inverses of the App. A definition (finite alpha)."""
+    rng = np.random.default_rng(200 + K)
+    t, y, dy = _bm_curve(rng, n=70)
+    y = y + 0.05 * (t / 900.0) ** 2
+    opt = OracleOptions(inv_alpha2=ia2)
+    tau, w, x = oracle.prepare_curve(t, y, dy, opt)
+    B = oracle.chebyshev_basis(t, K, scale)
+    freqs = np.linspace(0.05, 4, 12)
+    S = oracle.bm_periodogram(t, y, dy, freqs, 8, K, scale, opt)
+    ref = [oracle.bm_statistic_dense(x, w, oracle.phase_bins(tau, f, 8), 8, B, ia2) for f in freqs]
+    np.testing.assert_allclose(S, ref, rtol=1e-7)
+
+
+def test_bm_removes_polynomial_drifts():
+    """With a broad baseline prior, adding a polynomial of degree < K leaves S unchanged."""
+    rng = np.random.default_rng(303)
+    t, y, dy = _bm_curve(rng)
+    freqs = np.linspace(0.05, 3, 40)
+    s = 2 * (t - t.min()) / (t.max() - t.min()) - 1
+    drift = 0.3 - 0.8 * s + 0.5 * (2 * s * s - 1)
+    S0 = oracle.bm_periodogram(t, y, dy, freqs, 10, 3, scale=1e3)
+    S1 = oracle.bm_periodogram(t, y + drift, dy, freqs, 10, 3, scale=1e3)
+    np.testing.assert_allclose(S1, S0, rtol=1e-6)
+    # the plain statistic is not protected
+    P1 = oracle.curve_periodogram(t, y + drift, dy, freqs, 10)
+    assert np.median(P1) > 20 * np.median(S0)
+
+
+def test_bm_noise_is_chi2_with_M_minus_1_dof():
+    """Broad baseline prior, alpha -> inf: the drop in chi-square from adding M bin levels to a
+    degree-(K-1) baseline is chi-square with M - 1 degrees of freedom on pure noise."""
+    rng = np.random.default_rng(404)
+    n, M = 80, 8
+    t = np.sort(rng.uniform(0, 900, n))
+    dy = rng.uniform(0.01, 0.05, n)
+    S = np.array([oracle.bm_periodogram(t, dy * rng.standard_normal(n), dy, [1.37], M, 3, scale=1e3)[0]
+                  for _ in range(1500)])
+    assert abs(S.mean() - (M - 1)) < 5 * math.sqrt(2 * (M - 1) / len(S))
+    assert abs(S.var() - 2 * (M - 1)) < 0.2 * 2 * (M - 1)
