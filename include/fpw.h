@@ -86,6 +86,8 @@ enum {
 #define FPW_MAX_VARIANTS 8    /* periodograms per pass: (M, offset) variants */
 #define FPW_MAX_TOPK 16       /* largest k for peak selection */
 #define FPW_MAX_CURVE_POINTS (1 << 24)
+#define FPW_MAX_BASELINE_TERMS 3  /* Chebyshev terms of the marginalised baseline */
+#define FPW_MAX_BASELINE_BINS 64  /* largest M with a marginalised baseline (LDS) */
 
 typedef struct {
   int32_t n_bins;      /* M >= 1; > FPW_MAX_BINS -> FPW_EUNSUPPORTED.  Default 10. */
@@ -117,6 +119,16 @@ typedef struct {
                              (read them with fpw_pass_timings); the pass is then
                              launched kernel by kernel instead of as a graph */
   int32_t shared_kernel;  /* plans made by fpw_plan_shared: FPW_SHARED_* (ignored otherwise) */
+  int32_t baseline_terms; /* App. A general case: marginalise a baseline drift of K Chebyshev
+                             terms T_0..T_{K-1} of the curve's time span mapped to [-1, 1],
+                             0 <= K <= FPW_MAX_BASELINE_TERMS; 0 (default) = Eq. 1.  The
+                             statistic becomes S = X^T C^-1 P (I + P^T C^-1 P)^-1 P^T C^-1 X
+                             with C = C_B + C_sigma, C_B = B B^T (columns of B: baseline_scale
+                             * T_k), C_sigma = diag(dy^2), P = alpha * one-hot(bins); empty
+                             bins add nothing.  K > 0 needs the FP64 phase modes, n_bins <=
+                             FPW_MAX_BASELINE_BINS and no derived bin counts. */
+  double baseline_scale;  /* prior standard deviation of each baseline coefficient, in flux
+                             units (> 0, finite; default 1) */
 } fpw_options;
 
 /* Kernel of a shared-timestamp plan (fpw_plan_shared). */
@@ -209,7 +221,8 @@ fpw_status fpw_topk(fpw_plan_t plan, const float* S_dev, int32_t k, int32_t* idx
 /*
  * The plain per-curve FP64 comparator: one launch per curve, listing-order FP64
  * fold, FP64 per-bin sums and FP64 statistic (App. D "runFPW", re-designed as a
- * GPU kernel).  S_dev: DEVICE float64 [n_curves * n_freq].
+ * GPU kernel).  S_dev: DEVICE float64 [n_curves * n_freq].  Eq. 1 only:
+ * FPW_EUNSUPPORTED for plans with baseline terms.
  */
 fpw_status fpw_eval_fp64(fpw_plan_t plan, double* S_dev, void* stream);
 
@@ -263,7 +276,8 @@ typedef struct {
   int32_t tuned;          /* 1 if the launch shape came from the autotuner or its cache */
   int32_t point_source;   /* 1 scalar loads, 2 vector loads + DPP broadcast */
   int32_t n_variants;     /* periodograms per curve and pass */
-  int32_t kernel;         /* 0 general batched kernel, 1 shared-timestamp matrix-core kernel */
+  int32_t kernel;         /* 0 general batched kernel, 1 shared-timestamp matrix-core kernel,
+                             2 baseline-marginalised kernel */
 } fpw_plan_info;
 
 fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);

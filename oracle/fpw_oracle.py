@@ -413,7 +413,7 @@ def bm_statistic_dense(x, w, bins, n_bins: int, B, inv_alpha2: float) -> float:
 
 
 def bm_periodogram(t, y, dy, freqs, n_bins: int, n_terms: int, scale: float = 1.0,
-                   opt: OracleOptions | None = None) -> np.ndarray:
+                   opt: OracleOptions | None = None, bins=None) -> np.ndarray:
     """Baseline-marginalised S(f) for one curve (App. A, general case), FP64.
 
     Follows App. A's steps: the frequency-independent inverse
@@ -423,7 +423,9 @@ def bm_periodogram(t, y, dy, freqs, n_bins: int, n_terms: int, scale: float = 1.
     G = E^T C_Bsigma^-1 E (block sums of C_Bsigma^-1), and
     S = u^T (alpha^-2 I + G)^-1 u over the occupied bins (an empty bin has
     u_m = 0 and a zero row of G, so it adds nothing for any alpha).
-    ``n_terms = 0`` is the plain statistic of Eq. 1.
+    ``n_terms = 0`` is the plain statistic of Eq. 1.  ``bins`` ([n_freq, N])
+    replaces the fold's bins (a point within rounding of an edge may sit in
+    either neighbour).
     """
     opt = opt or OracleOptions()
     tau, w, x = prepare_curve(t, y, dy, opt)
@@ -439,12 +441,13 @@ def bm_periodogram(t, y, dy, freqs, n_bins: int, n_terms: int, scale: float = 1.
     freqs = np.asarray(freqs, dtype=np.float64)
     out = np.empty(len(freqs))
     for r, f in enumerate(freqs):
-        b = phase_bins(tau, f, n_bins)
+        b = phase_bins(tau, f, n_bins) if bins is None else np.asarray(bins[r], dtype=np.int64)
         occ = np.unique(b)
         idx = np.searchsorted(occ, b)
-        u = np.bincount(idx, weights=CX, minlength=len(occ))
-        G = np.zeros((len(occ), len(occ)))
-        np.add.at(G, (idx[:, None], idx[None, :]), Cinv)
+        no = len(occ)
+        u = np.bincount(idx, weights=CX, minlength=no)
+        G = np.bincount((idx[:, None] * no + idx[None, :]).ravel(), weights=Cinv.ravel(), minlength=no * no)
+        G = G.reshape(no, no)
         A = G + opt.inv_alpha2 * np.eye(len(occ))
         val = float(u @ np.linalg.solve(A, u))
         out[r] = 0.5 * val if opt.stat_scale == "listing_half" else val

@@ -241,6 +241,123 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_shared_kernel(SharedPrep
   }
 }
 
+// ---------------------------------------------------------------- prepare, marginalised baseline
+// One workgroup per curve: weights, centring and time offsets as above;
+// Chebyshev terms T_1 = s, T_2 = 2 s^2 - 1 of s = 2 (t - t_min)/(t_max - t_min) - 1;
+// fixed-point weight, residual and w T_k; then the per-curve constants from
+// the rounded values: H = I + beta^2 [sum a_k a_l / w~] (a_0 = w~) and
+// g = H^-1 beta [sum a_k y~ / w~], solved in FP64.
+
+// x = Q^-1 b for a symmetric positive definite 3x3 Q (upper triangle q00 q01 q02 q11 q12 q22),
+// by elimination without pivoting.
+__device__ __forceinline__ void spd3_solve(const double* q, const double* b, double* x) {
+  const double a00 = q[0], a01 = q[1], a02 = q[2];
+  const double l1 = a01 / a00, l2 = a02 / a00;
+  const double a11 = q[3] - l1 * a01, a12 = q[4] - l1 * a02, a22 = q[5] - l2 * a02;
+  const double m2 = a12 / a11;
+  const double c22 = a22 - m2 * a12;
+  const double y0 = b[0], y1 = b[1] - l1 * y0, y2 = b[2] - l2 * y0 - m2 * (b[1] - l1 * y0);
+  x[2] = y2 / c22;
+  x[1] = (y1 - a12 * x[2]) / a11;
+  x[0] = (y0 - a01 * x[1] - a02 * x[2]) / a00;
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) { return -block_min(-v, red); }
+
+__global__ __launch_bounds__(kPrepThreads) void bm_prepare_kernel(BmPrepArgs a) {
+  __shared__ double red[kPrepThreads];
+  const int t = threadIdx.x;
+  for (int64_t c = blockIdx.x; c < a.n_curves; c += gridDim.x) {
+    const int64_t p0 = a.offsets[c];
+    const int n = (int)(a.offsets[c + 1] - p0);
+    double sw = 0.0, swy = 0.0, sy = 0.0, tmin = INFINITY, tmax = -INFINITY;
+    for (int i = t; i < n; i += kPrepThreads) {
+      const double d = a.dy[p0 + i];
+      const double w = 1.0 / (d * d);
+      const double yy = a.y[p0 + i];
+      sw += w;
+      swy += w * yy;
+      sy += yy;
+      tmin = fmin(tmin, a.t[p0 + i]);
+      tmax = fmax(tmax, a.t[p0 + i]);
+    }
+    sw = block_sum(sw, red);
+    swy = block_sum(swy, red);
+    sy = block_sum(sy, red);
+    tmin = block_min(tmin, red);
+    tmax = block_max(tmax, red);
+    const double mu = a.center == 0 ? swy / sw : (a.center == 1 ? sy / (double)n : 0.0);
+    const double tref = a.tref_mode == 0 ? 0.0 : (a.tref_mode == 1 ? tmin : a.t_ref);
+    const double span = tmax - tmin;
+    double ay = 0.0;
+    for (int i = t; i < n; i += kPrepThreads) {
+      const double d = a.dy[p0 + i];
+      const double w = 1.0 / (d * d);
+      ay += fabs(w * (a.y[p0 + i] - mu));
+    }
+    ay = block_sum(ay, red);
+    const double s_w = (4294967296.0 - 2.0 - 2.0 * (double)n) / sw;
+    const double s_y = ay > 0.0 ? (2147483648.0 - 2.0 - (double)n) / ay : 1.0;
+    const double s_z = (2147483648.0 - 2.0 - (double)n) / sw;  // |w T_k| <= w
+    // sums of the rounded values: h[0..5] (upper triangle of sum a_k a_l / w~), z[0..2]
+    double h[6] = {0, 0, 0, 0, 0, 0}, z[3] = {0, 0, 0};
+    for (int i = t; i < n; i += kPrepThreads) {
+      const int64_t p = p0 + i;
+      const double d = a.dy[p];
+      const double w = 1.0 / (d * d);
+      const double wx = w * (a.y[p] - mu);
+      const double sc = span > 0.0 ? 2.0 * (a.t[p] - tmin) / span - 1.0 : 0.0;
+      const double T1 = a.n_terms >= 2 ? sc : 0.0;
+      const double T2 = a.n_terms >= 3 ? 2.0 * sc * sc - 1.0 : 0.0;
+      const double wqd = fmax(1.0, rint(w * s_w));
+      const int64_t yq = (int64_t)rint(wx * s_y);
+      const int64_t z1 = (int64_t)rint(w * T1 * s_z);
+      const int64_t z2 = (int64_t)rint(w * T2 * s_z);
+      RecB r;
+      r.tau_bits = (uint64_t)__double_as_longlong(a.t[p] - tref);
+      r.pk = ((uint64_t)wqd << 32) + (uint64_t)yq;
+      r.pz = (uint64_t)(z2 * 4294967296LL + z1);
+      r.pad = 0;
+      a.rec[p] = r;
+      const double wt = wqd / s_w, yt = (double)yq / s_y, a1 = (double)z1 / s_z, a2 = (double)z2 / s_z;
+      h[0] += wt;
+      h[1] += a1;
+      h[2] += a2;
+      h[3] += a1 * a1 / wt;
+      h[4] += a1 * a2 / wt;
+      h[5] += a2 * a2 / wt;
+      z[0] += yt;
+      z[1] += a1 * yt / wt;
+      z[2] += a2 * yt / wt;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) h[q] = block_sum(h[q], red);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) z[q] = block_sum(z[q], red);
+    if (t == 0) {
+      BaseConst b;
+      const double b2 = a.beta * a.beta;
+      // rows of absent terms are the identity, so they leave g and S unchanged
+      b.H[0] = 1.0 + b2 * h[0];
+      b.H[1] = b2 * h[1];
+      b.H[2] = b2 * h[2];
+      b.H[3] = 1.0 + b2 * h[3];
+      b.H[4] = b2 * h[4];
+      b.H[5] = 1.0 + b2 * h[5];
+      const double zb[3] = {a.beta * z[0], a.beta * z[1], a.beta * z[2]};
+      spd3_solve(b.H, zb, b.g);
+      b.inv_sw = 1.0 / s_w;
+      b.inv_sy = 1.0 / s_y;
+      b.inv_sz = 1.0 / s_z;
+      b.beta = a.beta;
+      b.ia2 = a.inv_alpha2;
+      b.scale = a.stat_scale;
+      a.bc[c] = b;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- plain FP64 comparator
 // One launch per curve, one lane per frequency, FP64 histograms in LDS
 // ([bin][lane], ds_add_f64), listing-order fold, IEEE division.
@@ -353,6 +470,12 @@ hipError_t launch_prepare(const PrepArgs& a, hipStream_t s) {
 hipError_t launch_prepare_shared(const SharedPrepArgs& a, hipStream_t s) {
   const int g = a.n_curves < 65536 ? a.n_curves : 65536;
   hipLaunchKernelGGL(prepare_shared_kernel, dim3((unsigned)g), dim3(kPrepThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bm_prepare(const BmPrepArgs& a, hipStream_t s) {
+  const int64_t g = a.n_curves < 65536 ? a.n_curves : 65536;
+  hipLaunchKernelGGL(bm_prepare_kernel, dim3((unsigned)g), dim3(kPrepThreads), 0, s, a);
   return hipGetLastError();
 }
 

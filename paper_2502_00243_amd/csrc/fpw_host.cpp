@@ -98,6 +98,10 @@ struct fpw_plan_s {
   int sh_grid_x = 0, sh_grid_y = 0;
   size_t sh_lds = 0;
   DevBuf sh_tau, sh_vals, sh_cc, sh_S;
+  // marginalised baseline (App. A general case)
+  bool bm = false;
+  int bm_grid = 0;
+  DevBuf bm_rec, bm_const, bm_S;
   // profiling events: before prepare, after prepare, after batched, after merge
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool ev_recorded = false;
@@ -153,6 +157,18 @@ fpw_status check_options(const fpw_options& o) {
   if (nvar > 1 && o.freqs_per_lane == 2)
     return fail(FPW_EUNSUPPORTED, "derived bin counts are built for one frequency per lane");
   if (o.shared_kernel < 0 || o.shared_kernel > 2) return fail(FPW_EINVAL, "shared_kernel must be 0, 1 or 2");
+  if (o.baseline_terms < 0) return fail(FPW_EINVAL, "baseline_terms must be >= 0");
+  if (o.baseline_terms > FPW_MAX_BASELINE_TERMS)
+    return fail(FPW_EUNSUPPORTED, "baseline_terms %d exceeds FPW_MAX_BASELINE_TERMS=%d", o.baseline_terms, FPW_MAX_BASELINE_TERMS);
+  if (o.baseline_terms > 0) {
+    if (!finite(o.baseline_scale) || !(o.baseline_scale > 0))
+      return fail(FPW_EINVAL, "baseline_scale must be finite and > 0");
+    if (o.phase != FPW_PHASE_FP64 && o.phase != FPW_PHASE_FP64_LISTING)
+      return fail(FPW_EUNSUPPORTED, "a marginalised baseline is built for the FP64 phase modes");
+    if (o.n_bins > FPW_MAX_BASELINE_BINS)
+      return fail(FPW_EUNSUPPORTED, "n_bins %d exceeds FPW_MAX_BASELINE_BINS=%d", o.n_bins, FPW_MAX_BASELINE_BINS);
+    if (nvar > 1) return fail(FPW_EUNSUPPORTED, "derived bin counts are not built with a marginalised baseline");
+  }
   return FPW_OK;
 }
 
@@ -427,9 +443,61 @@ fpw_status enqueue_shared_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val
   return FPW_OK;
 }
 
+// A pass with a marginalised baseline: records and constants, the two-sum
+// kernel with its FP64 epilogue, then peaks over the stored periodogram.
+fpw_status enqueue_bm_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipStream_t s) {
+  const bool prof = p->opt.profile != 0;
+  float* Sd = S ? S : p->bm_S.as<float>();
+  if (prof) FPW_HIP(hipEventRecord(p->ev[0], s), "event record");
+  fpw::BmPrepArgs pa{};
+  pa.t = p->t.as<double>();
+  pa.y = p->y.as<double>();
+  pa.dy = p->dy.as<double>();
+  pa.offsets = p->offsets.as<int64_t>();
+  pa.n_curves = p->n_curves;
+  pa.center = p->opt.center;
+  pa.tref_mode = p->opt.tref_mode;
+  pa.n_terms = p->opt.baseline_terms;
+  pa.t_ref = p->opt.t_ref;
+  pa.inv_alpha2 = p->opt.inv_alpha2;
+  pa.beta = p->opt.baseline_scale;
+  pa.stat_scale = p->opt.stat_scale == FPW_STAT_LISTING_HALF ? 0.5 : 1.0;
+  pa.rec = p->bm_rec.as<fpw::RecB>();
+  pa.bc = p->bm_const.as<fpw::BaseConst>();
+  FPW_HIP(fpw::launch_bm_prepare(pa, s), "baseline prepare kernel");
+  if (prof) FPW_HIP(hipEventRecord(p->ev[1], s), "event record");
+  fpw::BmArgs a{};
+  a.rec = p->bm_rec.as<fpw::RecB>();
+  a.offsets = p->offsets.as<int64_t>();
+  a.bc = p->bm_const.as<fpw::BaseConst>();
+  a.freqs = p->freqs.as<double>();
+  a.items = p->items.as<fpw::Item>();
+  a.n_items = p->n_items;
+  a.n_freq = (int32_t)p->n_freq;
+  a.n_bins = p->opt.n_bins;
+  a.S = Sd;
+  a.queue = p->queue.as<uint32_t>();
+  FPW_HIP(fpw::launch_bm(a, p->opt.phase, p->bm_grid, s), "baseline kernel");
+  if (prof) FPW_HIP(hipEventRecord(p->ev[2], s), "event record");
+  if (idx != nullptr) {
+    fpw::TopkArgs t{};
+    t.S = Sd;
+    t.n_curves = (int32_t)p->n_curves;
+    t.n_freq = (int32_t)p->n_freq;
+    t.k = p->opt.topk;
+    t.out_idx = idx;
+    t.out_val = val;
+    FPW_HIP(fpw::launch_topk(t, s), "top-k kernel");
+  }
+  if (prof) FPW_HIP(hipEventRecord(p->ev[3], s), "event record");
+  p->ev_merge = idx != nullptr;
+  return FPW_OK;
+}
+
 // One full pass: prepare, fold/bin/accumulate/reduce (+ fused peaks), merge.
 fpw_status enqueue_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipStream_t s) {
   if (p->mfma) return enqueue_shared_pass(p, S, idx, val, s);
+  if (p->bm) return enqueue_bm_pass(p, S, idx, val, s);
   const bool prof = p->opt.profile != 0;
   if (prof) FPW_HIP(hipEventRecord(p->ev[0], s), "event record");
   FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
@@ -597,6 +665,8 @@ void fpw_options_default(fpw_options* o) {
   o->autotune = 0;
   o->use_graph = 1;
   o->tune_cache = nullptr;
+  o->baseline_terms = 0;
+  o->baseline_scale = 1.0;
 }
 
 const char* fpw_last_error(void) { return g_err.c_str(); }
@@ -673,6 +743,15 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     if (st != FPW_OK) return st;
     st = upload_items(p);
     if (st != FPW_OK) return st;
+    if (o.baseline_terms > 0) {
+      p->bm = true;
+      FPW_HIP(p->bm_rec.alloc(np * sizeof(fpw::RecB)), "alloc baseline records");
+      FPW_HIP(p->bm_const.alloc((size_t)n_curves * sizeof(fpw::BaseConst)), "alloc baseline constants");
+      FPW_HIP(p->bm_S.alloc((size_t)n_curves * (size_t)n_freq * sizeof(float)), "alloc baseline periodogram");
+      int per_cu = 0;
+      FPW_HIP(fpw::bm_groups_per_cu(o.phase, o.n_bins, &per_cu), "baseline kernel occupancy");
+      p->bm_grid = std::max(1, std::min(std::max(1, per_cu) * p->n_cu, p->n_items));
+    }
     FPW_HIP(hipStreamSynchronize(s), "plan sync");
     *out = guard.release();
     return FPW_OK;
@@ -700,10 +779,10 @@ fpw_status fpw_plan_shared(fpw_plan_t* out, int64_t n_curves, int64_t n_points, 
   fpw_status st = check_options(o);
   if (st != FPW_OK) return st;
   const bool fits = o.n_bins <= fpw::kSharedMaxBins && (o.phase == FPW_PHASE_FP64 || o.phase == FPW_PHASE_FP64_LISTING) &&
-                    o.derived_bins[0] == 0 && (n_curves + 15) / 16 <= 65535;
+                    o.derived_bins[0] == 0 && o.baseline_terms == 0 && (n_curves + 15) / 16 <= 65535;
   if (o.shared_kernel == FPW_SHARED_MATRIX && !fits)
     return fail(FPW_EUNSUPPORTED, "the matrix-core kernel needs n_bins <= %d, phase FP64 or FP64_LISTING, no derived bin "
-                "counts and at most 1048560 curves", fpw::kSharedMaxBins);
+                "counts, no baseline terms and at most 1048560 curves", fpw::kSharedMaxBins);
   const bool mfma = fits && o.shared_kernel != FPW_SHARED_GENERAL;
   try {
     // the equivalent CSR batch: every curve holds the common times
@@ -826,6 +905,7 @@ fpw_status fpw_eval_fp64(fpw_plan_t p, double* S_dev, void* stream) {
   g_err.clear();
   if (!p) return fail(FPW_EINVAL, "plan is NULL");
   if (!S_dev) return fail(FPW_EINVAL, "S_dev is NULL");
+  if (p->bm) return fail(FPW_EUNSUPPORTED, "the FP64 comparator evaluates Eq. 1 only (the plan has baseline terms)");
   if ((size_t)2 * p->opt.n_bins * kWave * sizeof(double) > 160 * 1024)
     return fail(FPW_EUNSUPPORTED, "the FP64 comparator holds 2*M doubles per lane in LDS: M <= 160");
   hipStream_t s = (hipStream_t)stream;
@@ -939,7 +1019,14 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   info->tuned = p->tuned ? 1 : 0;
   info->point_source = p->shape.point_source + 1;
   info->n_variants = p->var.n;
-  info->kernel = p->mfma ? 1 : 0;
+  info->kernel = p->mfma ? 1 : (p->bm ? 2 : 0);
+  if (p->bm) {
+    info->grid_groups = p->bm_grid;
+    info->waves_per_group = 1;
+    info->freqs_per_lane = 1;
+    info->point_source = 1;
+    info->lds_bytes = (int32_t)fpw::bm_lds_bytes(p->opt.n_bins);
+  }
   if (p->mfma) {
     info->grid_groups = p->sh_grid_x * p->sh_grid_y;
     info->work_items = p->sh_grid_x * p->sh_grid_y * p->sh_rounds * fpw::kSharedWaves;

@@ -177,6 +177,55 @@ struct SharedArgs {
   float* S;                // [n_curves * n_freq]
 };
 
+// Baseline-marginalised statistic (App. A, general case).  Every quantity
+// the statistic needs is a per-bin sum of fixed-point integers, so the bin
+// sums are exact; the per-curve constants are formed from the same rounded
+// per-point values, which keeps S = v^T L^-1 v + r^T Q^-1 r consistent with
+// one exactly solved (rounded) problem.
+struct alignas(16) RecB {
+  uint64_t tau_bits;  // FP64 time offset
+  uint64_t pk;        // (weight, weighted residual), packed as in Rec
+  uint64_t pz;        // (w T_1(s), w T_2(s)) in fixed point: T_2 * 2^32 + T_1, two's complement
+  uint64_t pad;
+};
+
+struct BaseConst {
+  double g[3];      // H^-1 z: the best-fitting baseline coefficients
+  double H[6];      // I + B^T C_sigma^-1 B, upper triangle 00 01 02 11 12 22
+  double inv_sw, inv_sy, inv_sz;  // fixed-point units of weight, residual and w T_k
+  double beta;      // baseline prior scale
+  double ia2;       // 1 / alpha^2
+  double scale;     // 0.5 for the listing's half scale, else 1
+};
+
+struct BmPrepArgs {
+  const double* t;
+  const double* y;
+  const double* dy;
+  const int64_t* offsets;
+  int64_t n_curves;
+  int center, tref_mode, n_terms;
+  double t_ref, inv_alpha2, beta, stat_scale;
+  RecB* rec;        // [n_points]
+  BaseConst* bc;    // [n_curves]
+};
+
+struct BmArgs {
+  const RecB* rec;
+  const int64_t* offsets;
+  const BaseConst* bc;
+  const double* freqs;
+  const Item* items;
+  int32_t n_items, n_freq, n_bins;
+  float* S;          // [n_curves * n_freq]
+  uint32_t* queue;   // [2], self-resetting as for the batched kernel
+};
+
+hipError_t launch_bm_prepare(const BmPrepArgs& a, hipStream_t s);
+hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s);
+hipError_t bm_groups_per_cu(int phase, int n_bins, int* out);
+size_t bm_lds_bytes(int n_bins);
+
 // Launch shapes of the batched kernel.
 struct Shape {
   int freqs_per_lane;   // 1 or 2

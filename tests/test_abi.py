@@ -164,3 +164,29 @@ def test_shared_plan_null_and_empty_arguments():
     assert lib.fpw_plan_shared(ctypes.byref(h), 3, 0, *args) == fpw.EINVAL
     with pytest.raises(ValueError):
         fpw.plan_shared_status(t, y[:, :3], dy, f, 4)
+
+
+BASELINE_CASES = [
+    ("negative terms", dict(baseline_terms=-1), fpw.EINVAL),
+    ("too many terms", dict(baseline_terms=4), fpw.EUNSUPPORTED),
+    ("zero scale", dict(baseline_terms=2, baseline_scale=0.0), fpw.EINVAL),
+    ("nan scale", dict(baseline_terms=2, baseline_scale=float("nan")), fpw.EINVAL),
+    ("df32 phase", dict(baseline_terms=2, phase="df32"), fpw.EUNSUPPORTED),
+    ("M too large", dict(baseline_terms=1, n_bins=65), fpw.EUNSUPPORTED),
+    ("with derived bins", dict(baseline_terms=1, n_bins=12, derived_bins=(6,)), fpw.EUNSUPPORTED),
+]
+
+
+@pytest.mark.parametrize("name,opts,expect", BASELINE_CASES, ids=[c[0] for c in BASELINE_CASES])
+def test_baseline_options_checked_on_host(name, opts, expect):
+    off, t, y, dy, f = _good()
+    opts = dict(opts)
+    n_bins = opts.pop("n_bins", 4)
+    st, msg = fpw.plan_status(off, t, y, dy, f, n_bins, **opts)
+    assert st == expect, (name, st, msg)
+    assert msg
+
+
+def test_baseline_defaults():
+    o = fpw.default_options()
+    assert o.baseline_terms == 0 and o.baseline_scale == 1.0 and o.shared_kernel == 0
