@@ -15,6 +15,8 @@
 // runs in FP64: the bin sums are exact integers and the constants were formed
 // from the same rounded values (the constant direction of Q is then exactly
 // the prior's 1, not a difference of two large sums).
+#include <type_traits>
+
 #include "fpw_common.h"
 
 namespace fpw {
@@ -22,10 +24,38 @@ namespace {
 
 using namespace dev;
 
-constexpr int kBmBatch = 4;
+// Observations reach the lanes as in the general kernel's vector source: the
+// lanes of each row of 16 load 16 consecutive records (one coalesced load),
+// and each record is then broadcast to its row with 64-bit DPP row_newbcast
+// moves.  Only vector-memory counters are waited on, so the LDS atomics of
+// earlier points stay in flight.
+constexpr int kGroup = 16;
 
-// slots per lane: M (weight, residual) words, then M (Z_1, Z_2) words
-template <int PH>
+template <int Q>
+__device__ __forceinline__ uint64_t row_bcast(uint64_t v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + Q, 0xf, 0xf, true);
+}
+
+template <int Q, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (Q < N) {
+    f(std::integral_constant<int, Q>{});
+    static_for<Q + 1, N>(f);
+  }
+}
+
+// One point q of the current group: fold, bin, and the one or two 64-bit sums.
+template <int PH, int NZ, int Q>
+__device__ __forceinline__ void bm_point(const RecB& cur, const Folder<PH>& fo, uint32_t M, uint64_t* hw, uint64_t* hz) {
+  const uint32_t b0 = (uint32_t)fo.bin(row_bcast<Q>(cur.tau_bits));
+  const uint32_t b = min(b0, b0 - M);  // the fused fold reports bin 0 as M
+  lds_add(hw + b * kWave, row_bcast<Q>(cur.pk));
+  if (NZ) lds_add(hz + b * kWave, row_bcast<Q>(cur.pz));
+}
+
+// slots per lane: M (weight, residual) words, then M (Z_1, Z_2) words (NZ = 1;
+// with one baseline term, Z_0 = beta W needs no sum of its own, NZ = 0)
+template <int PH, int NZ>
 __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restrict__ rec,
                                                    const int64_t* __restrict__ offsets,
                                                    const BaseConst* __restrict__ bcs,
@@ -34,12 +64,13 @@ __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restr
   extern __shared__ __align__(16) uint64_t lds[];
   const int lane = threadIdx.x;
   const int M = a.n_bins;
-  uint64_t* hw = lds + lane;                  // [m][lane]: weight and residual
+  uint64_t* hw = lds + lane;                      // [m][lane]: weight and residual
   uint64_t* hz = lds + (size_t)M * kWave + lane;  // [m][lane]: w T_1 and w T_2
   for (int m = 0; m < M; ++m) {
     hw[m * kWave] = 0;
-    hz[m * kWave] = 0;
+    if (NZ) hz[m * kWave] = 0;
   }
+  const int sub = lane & (kGroup - 1);
   for (;;) {
     int it = 0;
     if (lane == 0) it = (int)atomicAdd(a.queue, 1u);
@@ -55,34 +86,26 @@ __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restr
       const int k = kt + lane;
       Folder<PH> fo;
       fo.init(freqs[k < k1 ? k : k1 - 1], M);
-      // records are read four at a time through the scalar cache before any
-      // is used, so one wait covers the batch
-      int p = 0;
-      for (; p + kBmBatch <= n; p += kBmBatch) {
-        RecB r[kBmBatch];
-#pragma unroll
-        for (int q = 0; q < kBmBatch; ++q) r[q] = rc[p + q];
-#pragma unroll
-        for (int q = 0; q < kBmBatch; ++q) {
-          const uint32_t b0 = (uint32_t)fo.bin(r[q].tau_bits);
-          const uint32_t b = min(b0, b0 - (uint32_t)M);  // the fused fold reports bin 0 as M
-          lds_add(hw + b * kWave, uniform_to_vgpr(r[q].pk));
-          lds_add(hz + b * kWave, uniform_to_vgpr(r[q].pz));
+      RecB cur = rc[sub < n ? sub : n - 1];
+      for (int g = 0; g < n; g += kGroup) {
+        const int nxt = g + kGroup + sub;
+        const RecB next = rc[nxt < n ? nxt : n - 1];  // prefetch (clamped, in bounds)
+        const int cnt = n - g;                         // wave-uniform
+        if (cnt >= kGroup) {
+          static_for<0, kGroup>([&](auto qc) { bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz); });
+        } else {
+          static_for<0, kGroup>([&](auto qc) {
+            if (decltype(qc)::value < cnt) bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz);
+          });
         }
-      }
-      for (; p < n; ++p) {
-        const RecB r = rc[p];
-        const uint32_t b0 = (uint32_t)fo.bin(r.tau_bits);
-        const uint32_t b = min(b0, b0 - (uint32_t)M);
-        lds_add(hw + b * kWave, uniform_to_vgpr(r.pk));
-        lds_add(hz + b * kWave, uniform_to_vgpr(r.pz));
+        cur = next;
       }
       // FP64 epilogue: v^T L^-1 v and the 3x3 correction
       double s1 = 0.0, r0 = 0.0, r1 = 0.0, r2 = 0.0;
       double p00 = 0.0, p01 = 0.0, p02 = 0.0, p11 = 0.0, p12 = 0.0, p22 = 0.0;
       for (int m = 0; m < M; ++m) {
         const uint64_t vw = lds_take(hw + m * kWave);
-        const uint64_t vz = lds_take(hz + m * kWave);
+        const uint64_t vz = NZ ? lds_take(hz + m * kWave) : (uint64_t)0;
         const uint32_t lw = lo32(vw), lz = lo32(vz);
         const uint32_t wq = hi32(vw) + (lw >> 31);
         const int32_t yq = (int32_t)lw;
@@ -133,18 +156,28 @@ __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restr
 
 }  // namespace
 
-size_t bm_lds_bytes(int n_bins) { return (size_t)2 * n_bins * kWave * sizeof(uint64_t); }
+size_t bm_lds_bytes(int n_bins, int n_terms) {
+  return (size_t)(n_terms >= 2 ? 2 : 1) * n_bins * kWave * sizeof(uint64_t);
+}
 
-hipError_t bm_groups_per_cu(int phase, int n_bins, int* out) {
-  const void* fn = phase == PH_LISTING ? (const void*)bm_kernel<PH_LISTING> : (const void*)bm_kernel<PH_FP64>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bm_lds_bytes(n_bins));
+namespace {
+const void* bm_fn(int phase, int nz) {
+  if (phase == PH_LISTING) return nz ? (const void*)bm_kernel<PH_LISTING, 1> : (const void*)bm_kernel<PH_LISTING, 0>;
+  return nz ? (const void*)bm_kernel<PH_FP64, 1> : (const void*)bm_kernel<PH_FP64, 0>;
+}
+}  // namespace
+
+hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int* out) {
+  const void* fn = bm_fn(phase, n_terms >= 2);
+  const size_t lds = bm_lds_bytes(n_bins, n_terms);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, kWave, bm_lds_bytes(n_bins));
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, kWave, lds);
 }
 
 hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s) {
-  const void* fn = phase == PH_LISTING ? (const void*)bm_kernel<PH_LISTING> : (const void*)bm_kernel<PH_FP64>;
-  const size_t lds = bm_lds_bytes(a.n_bins);
+  const void* fn = bm_fn(phase, a.n_terms >= 2);
+  const size_t lds = bm_lds_bytes(a.n_bins, a.n_terms);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   BmArgs args = a;

@@ -475,6 +475,7 @@ fpw_status enqueue_bm_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hi
   a.n_items = p->n_items;
   a.n_freq = (int32_t)p->n_freq;
   a.n_bins = p->opt.n_bins;
+  a.n_terms = p->opt.baseline_terms;
   a.S = Sd;
   a.queue = p->queue.as<uint32_t>();
   FPW_HIP(fpw::launch_bm(a, p->opt.phase, p->bm_grid, s), "baseline kernel");
@@ -749,7 +750,7 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
       FPW_HIP(p->bm_const.alloc((size_t)n_curves * sizeof(fpw::BaseConst)), "alloc baseline constants");
       FPW_HIP(p->bm_S.alloc((size_t)n_curves * (size_t)n_freq * sizeof(float)), "alloc baseline periodogram");
       int per_cu = 0;
-      FPW_HIP(fpw::bm_groups_per_cu(o.phase, o.n_bins, &per_cu), "baseline kernel occupancy");
+      FPW_HIP(fpw::bm_groups_per_cu(o.phase, o.n_bins, o.baseline_terms, &per_cu), "baseline kernel occupancy");
       p->bm_grid = std::max(1, std::min(std::max(1, per_cu) * p->n_cu, p->n_items));
     }
     FPW_HIP(hipStreamSynchronize(s), "plan sync");
@@ -1025,7 +1026,7 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
     info->waves_per_group = 1;
     info->freqs_per_lane = 1;
     info->point_source = 1;
-    info->lds_bytes = (int32_t)fpw::bm_lds_bytes(p->opt.n_bins);
+    info->lds_bytes = (int32_t)fpw::bm_lds_bytes(p->opt.n_bins, p->opt.baseline_terms);
   }
   if (p->mfma) {
     info->grid_groups = p->sh_grid_x * p->sh_grid_y;

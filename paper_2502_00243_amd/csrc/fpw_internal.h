@@ -217,14 +217,15 @@ struct BmArgs {
   const double* freqs;
   const Item* items;
   int32_t n_items, n_freq, n_bins;
+  int32_t n_terms;   // baseline terms K (1..3); K = 1 needs no second sum
   float* S;          // [n_curves * n_freq]
   uint32_t* queue;   // [2], self-resetting as for the batched kernel
 };
 
 hipError_t launch_bm_prepare(const BmPrepArgs& a, hipStream_t s);
 hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s);
-hipError_t bm_groups_per_cu(int phase, int n_bins, int* out);
-size_t bm_lds_bytes(int n_bins);
+hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int* out);
+size_t bm_lds_bytes(int n_bins, int n_terms);
 
 // Launch shapes of the batched kernel.
 struct Shape {
