@@ -94,7 +94,7 @@ struct fpw_plan_s {
   bool graph_ok = true;
   // shared-timestamp plans on the matrix cores
   bool mfma = false;
-  int32_t sh_points = 0, sh_kblocks = 0, sh_chunk = 0, sh_fw = 0, sh_rounds = 0, sh_priv = 0;
+  int32_t sh_points = 0, sh_kblocks = 0, sh_chunk = 0, sh_fw = 0, sh_nb = 2, sh_rounds = 0, sh_priv = 0;
   int sh_grid_x = 0, sh_grid_y = 0;
   size_t sh_lds = 0;
   DevBuf sh_tau, sh_vals, sh_cc, sh_S;
@@ -425,7 +425,7 @@ fpw_status enqueue_shared_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val
   if (prof) FPW_HIP(hipEventRecord(p->ev[0], s), "event record");
   FPW_HIP(fpw::launch_prepare_shared(shared_prep_args(p), s), "shared prepare kernel");
   if (prof) FPW_HIP(hipEventRecord(p->ev[1], s), "event record");
-  FPW_HIP(fpw::launch_shared(shared_args(p, Sd), p->opt.phase, 4, p->sh_grid_x, p->sh_grid_y, p->sh_lds, s),
+  FPW_HIP(fpw::launch_shared(shared_args(p, Sd), p->opt.phase, 4, p->sh_nb, p->sh_grid_x, p->sh_grid_y, p->sh_lds, s),
           "shared kernel");
   if (prof) FPW_HIP(hipEventRecord(p->ev[2], s), "event record");
   if (idx != nullptr) {
@@ -803,8 +803,8 @@ fpw_status fpw_plan_shared(fpw_plan_t* out, int64_t n_curves, int64_t n_points, 
       p->sh_points = (int32_t)n_points;
       p->sh_kblocks = (int32_t)((n_points + 31) / 32);
       p->sh_chunk = std::min(p->sh_kblocks, 16);
-      p->sh_fw = std::min(8, fpw::kSharedMaxBins / M);
-      const int term_bytes = 4 * 4 * 65 * (int)sizeof(float);
+      fpw::shared_shape(M, &p->sh_nb, &p->sh_fw);
+      const int term_bytes = 4 * 4 * (32 * p->sh_nb + 1) * (int)sizeof(float);
       p->sh_priv = round_up(std::max(p->sh_fw * p->sh_chunk * 32, term_bytes), 16);
       p->sh_lds = (size_t)4 * p->sh_chunk * fpw::kSharedTileBytes + (size_t)fpw::kSharedWaves * p->sh_priv;
       const int64_t nfb = (n_freq + p->sh_fw - 1) / p->sh_fw;        // frequency blocks

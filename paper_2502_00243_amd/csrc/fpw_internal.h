@@ -149,7 +149,8 @@ struct EntropyArgs {
 // receive both quantities of curves 4g + v and 4g + 2 + v.
 constexpr int kSharedGroupCurves = 4;   // curves per A tile
 constexpr int kSharedTileBytes = 1024;  // one tile: 32 rows x 32 points
-constexpr int kSharedMaxBins = 64;      // one-hot columns of one wave
+constexpr int kSharedMaxBins = 64;      // largest M of the matrix-core kernel
+constexpr int kSharedMaxFw = 12;        // frequencies per wave and round, at most
 constexpr int kSharedWaves = 8;         // waves per workgroup of the shared kernel
 
 struct SharedPrepArgs {
@@ -171,7 +172,7 @@ struct SharedArgs {
   int32_t n_curves, n_freq, n_bins;
   int32_t n_kblocks;       // K-blocks of 32 points
   int32_t chunk_kblocks;   // K-blocks staged in LDS at a time
-  int32_t fw;              // frequencies per wave per round (fw * n_bins <= 64)
+  int32_t fw;              // frequencies per wave per round (fw * n_bins <= 32 * B tiles)
   int32_t rounds;          // rounds per workgroup (8 waves x fw frequencies each)
   int32_t priv_bytes;      // LDS bytes private to each wave
   float* S;                // [n_curves * n_freq]
@@ -245,9 +246,12 @@ hipError_t launch_fp64(const Fp64Args& a, hipStream_t s);
 hipError_t launch_bins(const BinsArgs& a, hipStream_t s);
 hipError_t launch_entropy(const EntropyArgs& a, hipStream_t s);
 hipError_t launch_prepare_shared(const SharedPrepArgs& a, hipStream_t s);
-// curve_groups: A tiles (of 4 curves) per workgroup; 4 is the one built
-hipError_t launch_shared(const SharedArgs& a, int phase, int curve_groups, int grid_x, int grid_y, size_t lds_bytes,
-                         hipStream_t s);
+// curve_groups: A tiles (of 4 curves) per workgroup, 4 is the one built;
+// nb: one-hot B tiles (32 columns) per wave, 2 or 3
+hipError_t launch_shared(const SharedArgs& a, int phase, int curve_groups, int nb, int grid_x, int grid_y,
+                         size_t lds_bytes, hipStream_t s);
+// B tiles and frequencies per wave for M bins: the choice with the best column use
+void shared_shape(int n_bins, int* nb, int* fw);
 
 // LDS bytes the batched kernel needs per workgroup.
 size_t batched_lds_bytes(const Shape& shape, int n_bins);

@@ -19,10 +19,12 @@
 //
 // Workgroup: 8 waves sharing one block of curves (CG tiles of 4 curves).  The
 // curves' digit tiles are staged in LDS (in chunks of up to 512 points); each
-// wave owns fw frequencies per round (fw * M <= 64 columns, two B tiles),
-// folds the chunk's points at those frequencies into bytes in its private
-// LDS, builds the one-hot operand from them and issues CG * 2 products per 32
-// points.
+// wave owns fw frequencies per round (fw * M <= 32 NB columns, NB = 2 or 3
+// B tiles), folds the chunk's points at those frequencies into bytes in its
+// private LDS, builds the one-hot operand from them and issues CG * NB
+// products per 32 points.
+#include <algorithm>
+
 #include "fpw_common.h"
 
 namespace fpw {
@@ -33,8 +35,6 @@ using namespace dev;
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kNB = 2;             // B tiles (32 columns each) per wave
-constexpr int kTermStride = 65;    // floats per curve row of the term table (odd: no bank conflicts)
 
 // Bytes of `bins` equal to m become 1, the others 0.  Every byte of bins and
 // of m is below 64, so x = bins ^ m has bytes in [0, 63] and
@@ -50,8 +50,11 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int PH, int CG>
+// NB: B tiles (32 columns each) per wave.
+template <int PH, int CG, int NB>
 __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_per_eu(1, 2))) void shared_kernel(SharedArgs a) {
+  constexpr int kNB = NB;
+  constexpr int kTermStride = 32 * NB + 1;  // floats per curve row of the term table (odd: no bank conflicts)
   extern __shared__ __align__(16) unsigned char lds[];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -208,18 +211,31 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
 
 }  // namespace
 
-hipError_t launch_shared(const SharedArgs& a, int phase, int curve_groups, int grid_x, int grid_y, size_t lds_bytes,
-                         hipStream_t s) {
-  if (curve_groups != 4) return hipErrorInvalidValue;
-  const void* fn = phase == PH_LISTING ? (const void*)shared_kernel<PH_LISTING, 4> : (const void*)shared_kernel<PH_FP64, 4>;
+void shared_shape(int n_bins, int* nb, int* fw) {
+  // column use of nb tiles: fw M / (32 nb); three tiles read each A operand
+  // once for three products instead of two, so they win ties
+  const int f2 = std::min(kSharedMaxFw, 64 / n_bins), f3 = std::min(kSharedMaxFw, 96 / n_bins);
+  const double u2 = f2 * n_bins / 64.0, u3 = f3 * n_bins / 96.0;
+  if (u3 >= u2 - 0.01) {
+    *nb = 3;
+    *fw = f3;
+  } else {
+    *nb = 2;
+    *fw = f2;
+  }
+}
+
+hipError_t launch_shared(const SharedArgs& a, int phase, int curve_groups, int nb, int grid_x, int grid_y,
+                         size_t lds_bytes, hipStream_t s) {
+  if (curve_groups != 4 || (nb != 2 && nb != 3)) return hipErrorInvalidValue;
+  const bool lst = phase == PH_LISTING;
+  const void* fn = nb == 3 ? (lst ? (const void*)shared_kernel<PH_LISTING, 4, 3> : (const void*)shared_kernel<PH_FP64, 4, 3>)
+                           : (lst ? (const void*)shared_kernel<PH_LISTING, 4, 2> : (const void*)shared_kernel<PH_FP64, 4, 2>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)grid_x, (unsigned)grid_y), block(kSharedWaves * kWave);
-  if (phase == PH_LISTING)
-    hipLaunchKernelGGL((shared_kernel<PH_LISTING, 4>), grid, block, lds_bytes, s, a);
-  else
-    hipLaunchKernelGGL((shared_kernel<PH_FP64, 4>), grid, block, lds_bytes, s, a);
-  return hipGetLastError();
+  SharedArgs args = a;
+  void* params[] = {&args};
+  return hipLaunchKernel(fn, dim3((unsigned)grid_x, (unsigned)grid_y), dim3(kSharedWaves * kWave), params, lds_bytes, s);
 }
 
 }  // namespace fpw
