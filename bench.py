@@ -253,7 +253,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 phase, i64 fixed-point bin sums, f32 statistic" if args.phase == "fp64" else args.phase,
+        "dtype": {"fp64": "f64", "fp64_listing": "f64", "df32": "f32x2", "fp32": "f32"}[args.phase],
+        "dtype_detail": f"{args.phase} fold and bin, 64-bit integer fixed-point bin sums, f32 statistic",
         "data": "synthetic",
         "config": {
             "workload": "1000 ZTF-like light curves (N~U(100,1000), 1500 d, seasonal gaps), "
