@@ -780,10 +780,11 @@ fpw_status fpw_plan_shared(fpw_plan_t* out, int64_t n_curves, int64_t n_points, 
   fpw_status st = check_options(o);
   if (st != FPW_OK) return st;
   const bool fits = o.n_bins <= fpw::kSharedMaxBins && (o.phase == FPW_PHASE_FP64 || o.phase == FPW_PHASE_FP64_LISTING) &&
-                    o.derived_bins[0] == 0 && o.baseline_terms == 0 && (n_curves + 15) / 16 <= 65535;
+                    o.derived_bins[0] == 0 && o.baseline_terms == 0 && (n_curves + 15) / 16 <= 65535 &&
+                    n_points <= fpw::kSharedMaxPoints;
   if (o.shared_kernel == FPW_SHARED_MATRIX && !fits)
     return fail(FPW_EUNSUPPORTED, "the matrix-core kernel needs n_bins <= %d, phase FP64 or FP64_LISTING, no derived bin "
-                "counts, no baseline terms and at most 1048560 curves", fpw::kSharedMaxBins);
+                "counts, no baseline terms, at most 1048560 curves and %d points", fpw::kSharedMaxBins, fpw::kSharedMaxPoints);
   const bool mfma = fits && o.shared_kernel != FPW_SHARED_GENERAL;
   try {
     // the equivalent CSR batch: every curve holds the common times

@@ -151,6 +151,8 @@ constexpr int kSharedGroupCurves = 4;   // curves per A tile
 constexpr int kSharedTileBytes = 1024;  // one tile: 32 rows x 32 points
 constexpr int kSharedMaxBins = 64;      // largest M of the matrix-core kernel
 constexpr int kSharedMaxFw = 12;        // frequencies per wave and round, at most
+// points per curve: the products accumulate 64 x (digit sums), |64 * 128 * N| < 2^31
+constexpr int kSharedMaxPoints = 262112;
 constexpr int kSharedWaves = 8;         // waves per workgroup of the shared kernel
 
 struct SharedPrepArgs {

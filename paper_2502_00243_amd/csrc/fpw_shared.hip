@@ -36,12 +36,23 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 
-// Bytes of `bins` equal to m become 1, the others 0.  Every byte of bins and
-// of m is below 64, so x = bins ^ m has bytes in [0, 63] and
-// (x ^ 0x7f) + 1 = 0x80 - x per byte with no carry between bytes; its bit 7
-// is set exactly where x == 0.  mmx = (m * 0x01010101) ^ 0x7f7f7f7f.
+// Bytes of `bins` equal to m become 64, the others 0.  Every bin and every
+// column's m is below 64 (padding columns use m = 63 > any bin, or there is
+// no padding when M = 64), so x = bins ^ m has bytes in [0, 63] and
+// (x ^ 0x3f) + 1 = 0x40 - x per byte with no borrow between bytes; its bit 6
+// is set exactly where x == 0.  mmx = (m * 0x01010101) ^ 0x3f3f3f3f.  Two
+// instructions per four bytes; the products then carry a factor 64, which
+// the epilogue removes exactly.
 __device__ __forceinline__ int one_hot4(uint32_t bins, uint32_t mmx) {
-  return (int)((((bins ^ mmx) + 0x01010101u) >> 7) & 0x01010101u);
+  return (int)(((bins ^ mmx) + 0x01010101u) & 0x40404040u);
+}
+
+// Digit sums of one quantity (registers e .. e+3 of a product, each 64 times
+// the true sum) recombined to the exact 32-bit value: digit 0 is divided by
+// 64, digit i > 0 is scaled by 2^(8 i - 6); the wrap-around of the sum is
+// exact because the true value fits in 30 bits.
+__device__ __forceinline__ uint32_t recombine64(const v16i& c, int e) {
+  return ((uint32_t)(c[e] >> 6)) + ((uint32_t)c[e + 1] << 2) + ((uint32_t)c[e + 2] << 10) + ((uint32_t)c[e + 3] << 18);
 }
 
 __device__ __forceinline__ void wave_lds_fence() {
@@ -74,13 +85,13 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
 #pragma unroll
   for (int b = 0; b < kNB; ++b) {
     const int col = 32 * b + n;
-    int m = 127;
+    int m = 63;
     colf[b] = 0;
     if (col < a.fw * M) {
       colf[b] = col / M;
       m = col - colf[b] * M;
     }
-    colm[b] = ((uint32_t)m * 0x01010101u) ^ 0x7f7f7f7fu;
+    colm[b] = ((uint32_t)m * 0x01010101u) ^ 0x3f3f3f3fu;
   }
   // prior term of the two curves per A tile this lane finishes: 4 ai + 2 u + h
   float ia2q[CG][2];
@@ -108,7 +119,7 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
           const int ai = t / kbn, kbl = t - ai * kbn;
           const v4i v = *reinterpret_cast<const v4i*>(
               a.vals + ((int64_t)(g0 + ai) * a.n_kblocks + kb0 + kbl) * kSharedTileBytes + piece * 16);
-          *reinterpret_cast<v4i*>(vals + (size_t)(ai * KCB + kbl) * kSharedTileBytes + piece * 16) = v;
+          *reinterpret_cast<v4i*>(vals + (size_t)(kbl * CG + ai) * kSharedTileBytes + piece * 16) = v;
         }
         __syncthreads();
       }
@@ -141,34 +152,34 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
         }
       }
       wave_lds_fence();
-      // products, with the operands of the next 32 points read ahead
-      v4i av[CG], bins[kNB];
+      // Products, four K-blocks per step: the chunk's tiles sit in LDS as
+      // [K-block][curve group], so within a step every read is an immediate
+      // offset from one base pointer per operand.
+      for (int kb4 = 0; kb4 < kbn; kb4 += 4) {
+        const unsigned char* abase = vals + (size_t)kb4 * CG * kSharedTileBytes + lane * 16;
+        const unsigned char* bbase[kNB];
 #pragma unroll
-      for (int ai = 0; ai < CG; ++ai)
-        av[ai] = *reinterpret_cast<const v4i*>(vals + (size_t)(ai * KCB) * kSharedTileBytes + lane * 16);
+        for (int b = 0; b < kNB; ++b) bbase[b] = priv + colf[b] * KC + kb4 * 32 + h * 16;
 #pragma unroll
-      for (int b = 0; b < kNB; ++b) bins[b] = *reinterpret_cast<const v4i*>(priv + colf[b] * KC + h * 16);
-      for (int kb = 0; kb < kbn; ++kb) {
-        v4i bv[kNB];
+        for (int j = 0; j < 4; ++j) {
+          if (kb4 + j < kbn) {
+            v4i av[CG], bv[kNB];
 #pragma unroll
-        for (int b = 0; b < kNB; ++b)
+            for (int ai = 0; ai < CG; ++ai)
+              av[ai] = *reinterpret_cast<const v4i*>(abase + (j * CG + ai) * kSharedTileBytes);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)bins[b][i], colm[b]);
-        v4i avn[CG], binsn[kNB];
-        const int kn = kb + 1 < kbn ? kb + 1 : kb;
+            for (int b = 0; b < kNB; ++b) {
+              const v4i bins = *reinterpret_cast<const v4i*>(bbase[b] + j * 32);
 #pragma unroll
-        for (int ai = 0; ai < CG; ++ai)
-          avn[ai] = *reinterpret_cast<const v4i*>(vals + (size_t)(ai * KCB + kn) * kSharedTileBytes + lane * 16);
+              for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)bins[i], colm[b]);
+            }
 #pragma unroll
-        for (int b = 0; b < kNB; ++b) binsn[b] = *reinterpret_cast<const v4i*>(priv + colf[b] * KC + kn * 32 + h * 16);
+            for (int ai = 0; ai < CG; ++ai)
 #pragma unroll
-        for (int ai = 0; ai < CG; ++ai)
-#pragma unroll
-          for (int b = 0; b < kNB; ++b) acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
-#pragma unroll
-        for (int ai = 0; ai < CG; ++ai) av[ai] = avn[ai];
-#pragma unroll
-        for (int b = 0; b < kNB; ++b) bins[b] = binsn[b];
+              for (int b = 0; b < kNB; ++b)
+                acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
+          }
+        }
       }
     }
 
@@ -182,11 +193,8 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
         const v16i& c = acc[ai][b];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const int e = 8 * u;
-          const uint32_t wq = (uint32_t)c[e] + ((uint32_t)c[e + 1] << 8) + ((uint32_t)c[e + 2] << 16) +
-                              ((uint32_t)c[e + 3] << 24);
-          const int yq = (int)((uint32_t)c[e + 4] + ((uint32_t)c[e + 5] << 8) + ((uint32_t)c[e + 6] << 16) +
-                               ((uint32_t)c[e + 7] << 24));
+          const uint32_t wq = recombine64(c, 8 * u);
+          const int yq = (int)recombine64(c, 8 * u + 4);
           const float d = fmaxf((float)wq + ia2q[ai][u], 0.5f);
           const float yf = (float)yq;
           terms[(4 * ai + 2 * u + h) * kTermStride + 32 * b + n] = yf * (yf * __builtin_amdgcn_rcpf(d));
@@ -216,7 +224,9 @@ void shared_shape(int n_bins, int* nb, int* fw) {
   // once for three products instead of two, so they win ties
   const int f2 = std::min(kSharedMaxFw, 64 / n_bins), f3 = std::min(kSharedMaxFw, 96 / n_bins);
   const double u2 = f2 * n_bins / 64.0, u3 = f3 * n_bins / 96.0;
-  if (u3 >= u2 - 0.01) {
+  // (with M = 64 two tiles hold exactly one frequency: no padding column,
+  // which the one-hot form relies on)
+  if (u3 >= u2 - 0.01 && n_bins < 64) {
     *nb = 3;
     *fw = f3;
   } else {
