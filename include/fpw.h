@@ -180,7 +180,9 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
  *   t          float64 [n_points], HOST: the common times
  *   y, dy      float64 [n_curves * n_points], HOST, curve-major: fluxes and errors
  *   n_freq, freqs, opt, stream: as for fpw_plan
- * With the matrix-core kernel the plan also owns a float32 periodogram
+ * The plan holds the equivalent CSR batch as well (about 64 bytes of device
+ * memory per curve and point) for the general kernel and the other entry
+ * points.  With the matrix-core kernel it also owns a float32 periodogram
  * buffer [n_curves * n_freq] used when fpw_eval_batch gets S_dev = NULL.
  */
 fpw_status fpw_plan_shared(fpw_plan_t* out, int64_t n_curves, int64_t n_points, const double* t, const double* y,

@@ -292,6 +292,10 @@ fpw_status configure_shape(fpw_plan_s* p, fpw::Shape s) {
 }
 
 fpw_status upload_items(fpw_plan_s* p) {
+  const int64_t per_curve = (p->n_freq + p->shape.chunk_freqs - 1) / p->shape.chunk_freqs;
+  if (per_curve * p->n_curves > (int64_t)INT32_MAX)
+    return fail(FPW_EUNSUPPORTED, "%lld work items exceed the 32-bit item index (raise chunk_freqs)",
+                (long long)(per_curve * p->n_curves));
   std::vector<fpw::Item> nat;
   std::vector<int32_t> slot_k0, curve_slot;
   build_items(p, p->shape.chunk_freqs, &nat, &slot_k0, &curve_slot);
