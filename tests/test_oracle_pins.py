@@ -533,9 +533,9 @@ def test_shared_periodogram_equals_per_curve_definition():
 def test_chebyshev_basis_closed_form():
     """Columns are T_k(s) with s spanning [-1, 1]: T_k(cos th) = cos(k th)."""
     th = np.linspace(0.0, np.pi, 37)
-    t = 500.0 * (np.cos(th[::-1]) + 1.0)  # s = cos(th) after mapping [0, 1000] to [-1, 1]
+    t = 250.0 + 500.0 * (np.cos(th[::-1]) + 1.0)  # s = cos(th) after mapping [250, 1250] to [-1, 1]
     B = oracle.chebyshev_basis(t, 4, scale=2.5)
-    s = 2.0 * t / 1000.0 - 1.0
+    s = 2.0 * (t - 250.0) / 1000.0 - 1.0
     ths = np.arccos(np.clip(s, -1, 1))
     for k in range(4):
         np.testing.assert_allclose(B[:, k], 2.5 * np.cos(k * ths), atol=1e-12)
