@@ -15,8 +15,6 @@
 // runs in FP64: the bin sums are exact integers and the constants were formed
 // from the same rounded values (the constant direction of Q is then exactly
 // the prior's 1, not a difference of two large sums).
-#include <type_traits>
-
 #include "fpw_common.h"
 
 namespace fpw {
@@ -30,19 +28,6 @@ using namespace dev;
 // moves.  Only vector-memory counters are waited on, so the LDS atomics of
 // earlier points stay in flight.
 constexpr int kGroup = 16;
-
-template <int Q>
-__device__ __forceinline__ uint64_t row_bcast(uint64_t v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x150 + Q, 0xf, 0xf, true);
-}
-
-template <int Q, int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (Q < N) {
-    f(std::integral_constant<int, Q>{});
-    static_for<Q + 1, N>(f);
-  }
-}
 
 // One point q of the current group: fold, bin, and the one or two 64-bit sums.
 template <int PH, int NZ, int Q>

@@ -23,8 +23,6 @@
 //  * work is a queue of (curve, frequency chunk) items, longest curves first,
 //    popped by persistent waves with one atomic each; the peak selection is
 //    fused so that large periodograms never reach HBM.
-#include <type_traits>
-
 #include "fpw_common.h"
 
 namespace fpw {
@@ -54,21 +52,6 @@ struct RO {
 //    flight; this suits large M, where the histograms leave room for few
 //    waves per CU.
 enum { SRC_SCALAR = 0, SRC_DPP = 1 };
-
-// Lane Q of each row of 16 lanes, broadcast to its row (64-bit DPP row_newbcast).
-template <int Q>
-__device__ __forceinline__ uint64_t row_bcast(uint64_t v) {
-  // every lane reads an existing lane, so the "old" operand is never used
-  return __builtin_amdgcn_update_dpp(v, v, 0x150 + Q, 0xf, 0xf, true);
-}
-
-template <int Q, int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (Q < N) {
-    f(std::integral_constant<int, Q>{});
-    static_for<Q + 1, N>(f);
-  }
-}
 
 template <int PH, int FL, int SRC>
 __device__ __forceinline__ void accumulate(const Rec* __restrict__ rc, int n, const Folder<PH> (&fo)[FL],
@@ -134,38 +117,41 @@ __device__ __forceinline__ void accumulate(const Rec* __restrict__ rc, int n, co
 
 // Reduces one lane's fine histogram for every variant: variant v sums k[v]
 // consecutive fine bins (from fine bin o[v], cyclically) into each coarse
-// bin, exactly, then adds the Eq. 1 terms.  Two straight passes over the
-// lane's slots, with LDS traffic pipelined in blocks of eight:
-//  1. read the fine sums and write back the inclusive prefix sums
-//     P(m+1) = F(0) + ... + F(m) into slot m;
-//  2. for each variant, the coarse sum of window [s, e) is P(e) - P(s), with
-//     the prefix extended periodically, P(M + x) = P(M) + P(x), for the window
-//     that wraps around the end.  Variant 0 (the fine bins themselves) reads
-//     every slot; it goes last and clears each slot as it reads it, leaving
-//     the histogram zeroed for the next sweep.
+// bin, exactly, then adds the Eq. 1 terms.
+//  1. One pass over the fine bins in order, read and cleared eight at a time:
+//     variant 0 (the fine bins themselves) takes its terms directly, and the
+//     running prefix P(m+1) = F(0) + ... + F(m) is written back only to the
+//     slots some derived variant reads (its window ends).
+//  2. Each derived variant forms the coarse sum of window [s, e) as
+//     P(e) - P(s), with the prefix extended periodically, P(M + x) =
+//     P(M) + P(x), for the window that wraps around the end.  The last
+//     variant clears the slots it reads; a final pass clears the others.
 template <int PH, int NV>
 __device__ __forceinline__ void reduce_variants(uint64_t* h, int M, float ia2q, const Variants& vs, float (&out)[NV]) {
   const uint64_t wrap = take_wrap_slot<PH>(h, M);
   uint64_t run = 0;
+  float fine = 0.f;
   for (int m0 = 0; m0 < M; m0 += kReduceBlock) {
     uint64_t f[kReduceBlock];
-#pragma unroll
-    for (int q = 0; q < kReduceBlock; ++q) f[q] = h[min(m0 + q, M) * kWave];
+    take_block<PH>(h, M, m0, f);
     if (m0 == 0) f[0] += wrap;
 #pragma unroll
     for (int q = 0; q < kReduceBlock; ++q) {
-      if (m0 + q < M) {
+      const int m = m0 + q;
+      if (m < M) {
         run += f[q];
-        h[(m0 + q) * kWave] = run;
+        fine = add_bin_term(fine, f[q], ia2q);
+        if ((vs.need[m >> 5] >> (m & 31)) & 1u) h[m * kWave] = run;
       }
     }
   }
   const uint64_t total = run;  // P(M)
+  out[0] = fine;
 #pragma unroll
-  for (int vi = 0; vi < NV; ++vi) {
-    const int v = (vi + 1) % NV;  // 1, 2, ..., NV-1, then 0
+  for (int v = 1; v < NV; ++v) {
     out[v] = 0.f;
     if (v < vs.n) {
+      const bool clears = v == vs.n - 1;
       const int k = vs.k[v], o = vs.o[v], mv = M / k;
       uint64_t prev = o == 0 ? (uint64_t)0 : h[(o - 1) * kWave];  // P(o)
       for (int c0 = 0; c0 < mv; c0 += kReduceBlock) {
@@ -175,7 +161,7 @@ __device__ __forceinline__ void reduce_variants(uint64_t* h, int M, float ia2q, 
           // end of window c0+q: e = o + (c0+q+1) k, clamped past the last window
           const int e = min(o + (c0 + q + 1) * k, M + o);
           const int x = e > M ? e - M : e;  // 1 <= x <= M
-          pe[q] = v == 0 ? lds_take(h + (x - 1) * kWave) : h[(x - 1) * kWave];
+          pe[q] = clears ? lds_take(h + (x - 1) * kWave) : h[(x - 1) * kWave];
           if (e > M) pe[q] += total;
         }
 #pragma unroll
@@ -186,6 +172,14 @@ __device__ __forceinline__ void reduce_variants(uint64_t* h, int M, float ia2q, 
           }
         }
       }
+    }
+  }
+  for (int w = 0; w * 32 < M; ++w) {
+    uint32_t bits = vs.rest[w];
+    while (bits) {
+      const int b = __builtin_ctz(bits);
+      bits &= bits - 1;
+      h[(w * 32 + b) * kWave] = 0;
     }
   }
 }

@@ -7,6 +7,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "fpw_internal.h"
 
 namespace fpw {
@@ -127,6 +129,24 @@ struct Folder<PH_FP32> {
     return b < m - 1 ? b : m - 1;
   }
 };
+
+// ---------------------------------------------------------------- DPP helpers
+// Lane Q of each row of 16 lanes, broadcast to its row (64-bit DPP
+// row_newbcast).  Every lane reads an existing lane, so the "old" operand is
+// never used.
+template <int Q>
+__device__ __forceinline__ uint64_t row_bcast(uint64_t v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + Q, 0xf, 0xf, true);
+}
+
+// f(integral_constant<int, q>) for q = Q .. N-1: DPP controls must be constants.
+template <int Q, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (Q < N) {
+    f(std::integral_constant<int, Q>{});
+    static_for<Q + 1, N>(f);
+  }
+}
 
 // ---------------------------------------------------------------- LDS histograms
 __device__ __forceinline__ void lds_add(uint64_t* p, uint64_t v) {

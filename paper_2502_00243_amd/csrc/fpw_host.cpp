@@ -714,6 +714,17 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
         ++p->var.n;
       }
     }
+    // prefix slots the derived variants read: window ends x - 1 (and o - 1)
+    for (int v = 1; v < p->var.n; ++v) {
+      const int k = p->var.k[v], off = p->var.o[v], M = o.n_bins;
+      for (int c = 0; c < M / k; ++c) {
+        const int e = off + (c + 1) * k;
+        const int slot = (e > M ? e - M : e) - 1;
+        p->var.need[slot >> 5] |= 1u << (slot & 31);
+        if (v == p->var.n - 1) p->var.rest[slot >> 5] |= 1u << (slot & 31);  // read (and cleared) by the last
+      }
+    }
+    for (int w = 0; w < 8; ++w) p->var.rest[w] = p->var.need[w] & ~p->var.rest[w];
     hipStream_t s = (hipStream_t)stream;
     FPW_HIP(hipGetDevice(&p->device), "hipGetDevice");
     FPW_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device), "CU count");

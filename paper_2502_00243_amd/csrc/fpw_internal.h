@@ -57,6 +57,11 @@ struct Variants {
   int32_t n;
   int32_t k[kMaxVariants];
   int32_t o[kMaxVariants];
+  // bit m of need: slot m must hold the prefix sum P(m+1) because a derived
+  // variant reads it; bit m of rest: such a slot that the last variant does
+  // not read (and so does not clear)
+  uint32_t need[8];
+  uint32_t rest[8];
 };
 
 struct BatchArgs {
