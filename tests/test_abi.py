@@ -190,3 +190,29 @@ def test_baseline_options_checked_on_host(name, opts, expect):
 def test_baseline_defaults():
     o = fpw.default_options()
     assert o.baseline_terms == 0 and o.baseline_scale == 1.0 and o.shared_kernel == 0
+
+
+def _build_c_client(tmp_path):
+    import shutil
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    here = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(here)
+    libdir = os.path.dirname(LIB)
+    exe = str(tmp_path / "abi_check")
+    cmd = [cc, "-std=c99", "-Wall", "-Werror", "-O1", os.path.join(here, "c", "abi_check.c"), "-I", os.path.join(root, "include"),
+           "-L", libdir, "-l:libfpw.so", f"-Wl,-rpath,{libdir}", "-L/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,/opt/rocm/lib", "-lm", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def test_c_client_compiles_links_and_checks_arguments(tmp_path):
+    """The header is plain C; a C program links libfpw and sees the host-side checks."""
+    exe = _build_c_client(tmp_path)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "C ABI checks ok" in r.stdout

@@ -93,3 +93,16 @@ def test_phase_entropy_on_shared_and_baseline_plans():
     _, idx, _ = pb.eval()
     _entropy_check(pb, lambda c: b.curve(c)[0], 10, idx, b.freqs)
     pb.close()
+
+
+def test_c_client_runs_a_pass(tmp_path):
+    """A plain-C program plans, runs a pass through the C ABI and finds the injected period."""
+    _say("C client pass")
+    import subprocess
+
+    from tests.test_abi import _build_c_client
+
+    exe = _build_c_client(tmp_path)
+    r = subprocess.run([exe, "gpu"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "gpu pass ok" in r.stdout
