@@ -565,6 +565,19 @@ def bench_sweep(args):
                               "roofline_frac": _roofline(evals, batch.n_curves, len(batch.freqs), M, batch.n_points, k)["frac"]}),
                   flush=True)
             plan.close()
+    # launch shapes of the headline configuration (M = 20, scalar source)
+    for fl in (1, 2):
+        for wpg in (1, 2, 4):
+            for chunk in (0, 1024, 4096):
+                plan = fpw.Plan.from_batch(batch, topk=5, point_source="scalar", freqs_per_lane=fl, waves_per_group=wpg,
+                                           chunk_freqs=chunk, profile=True)
+                info = plan.info()
+                _, kms = _time_passes(plan, 4, 1, S_out=S, idx_out=idx, val_out=val)
+                k = float(np.median(kms[:, 1]))
+                print(json.dumps({"M": 20, "freqs_per_lane": fl, "waves_per_group": wpg, "chunk_freqs": info.chunk_freqs,
+                                  "grid_groups": info.grid_groups, "kernel_ms": k,
+                                  "G_evals_per_s": evals / (k * 1e-3) / 1e9}), flush=True)
+                plan.close()
 
 
 if __name__ == "__main__":
