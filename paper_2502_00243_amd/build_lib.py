@@ -34,25 +34,32 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the FPW library needs ROCm's hipcc to build")
 
 
+def _compile_cmd(src: str, obj: str) -> list:
+    cmd = [hipcc(), *COMMON_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".hip"):
+        cmd[1:1] = ["-x", "hip", *DEVICE_FLAGS]
+    else:
+        cmd[1:1] = ["-D__HIP_PLATFORM_AMD__"]
+    return cmd
+
+
 def build(verbose: bool = False) -> str:
-    """Compiles every source and links libfpw.so next to this file; returns its path."""
+    """Compiles every source (in parallel) and links libfpw.so next to this file; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
+
     build_dir = os.path.join(CSRC, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        obj = os.path.join(build_dir, src + ".o")
-        cmd = [hipcc(), *COMMON_FLAGS, "-c", path, "-o", obj]
-        if src.endswith(".hip"):
-            cmd[1:1] = ["-x", "hip", *DEVICE_FLAGS]
-        else:
-            cmd[1:1] = ["-D__HIP_PLATFORM_AMD__"]
-        if verbose:
+    objs = [os.path.join(build_dir, src + ".o") for src in SOURCES]
+    cmds = [_compile_cmd(src, obj) for src, obj in zip(SOURCES, objs)]
+    if verbose:
+        for cmd in cmds:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        results = list(ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
+    for src, r in zip(SOURCES, results):
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
-        objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]
     if verbose:
