@@ -391,7 +391,7 @@ def bench_baseline(args):
              "prepare_ms": float(np.mean(kms[:, 0])), "peaks_ms": float(np.mean(kms[:, 2])),
              "grid_groups": plan.info().grid_groups}
         if K > 0:
-            nbytes = 16 if K >= 2 else 8  # ds_add_u64 per evaluation: the second carries (w T_1, w T_2)
+            nbytes = {1: 8, 2: 12, 3: 16}[K]  # LDS bytes added per evaluation: (w, w x), then w T_1 (and w T_2)
             r["lds"] = {"bytes_per_eval": nbytes, "achieved_TBps": evals * nbytes / (kernel_ms * 1e-3) / 1e12,
                         "peak_TBps": LDS_PEAK / 1e12, "frac": evals * nbytes / (kernel_ms * 1e-3) / LDS_PEAK}
         log(f"baseline K={K}: {wall * 1e3:.3f} ms/pass, kernel {kernel_ms:.3f} ms, {evals / wall / 1e9:.0f} G evals/s")

@@ -29,17 +29,34 @@ using namespace dev;
 // earlier points stay in flight.
 constexpr int kGroup = 16;
 
-// One point q of the current group: fold, bin, and the one or two 64-bit sums.
+// Extra sums per bin: none with one baseline term (Z_0 = beta W needs no sum
+// of its own), one 32-bit word (w T_1) with two, one 64-bit word (w T_1,
+// w T_2) with three.
+enum { NZ_NONE = 0, NZ_PAIR = 1, NZ_ONE = 2 };
+
+template <int Q>
+__device__ __forceinline__ uint32_t row_bcast32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x150 + Q, 0xf, 0xf, true);
+}
+__device__ __forceinline__ void lds_add32(uint32_t* p, uint32_t v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t lds_take32(uint32_t* p) {
+  return __hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One point q of the current group: fold, bin, and the sums.
 template <int PH, int NZ, int Q>
-__device__ __forceinline__ void bm_point(const RecB& cur, const Folder<PH>& fo, uint32_t M, uint64_t* hw, uint64_t* hz) {
+__device__ __forceinline__ void bm_point(const RecB& cur, const Folder<PH>& fo, uint32_t M, uint64_t* hw, uint64_t* hz,
+                                         uint32_t* hz32) {
   const uint32_t b0 = (uint32_t)fo.bin(row_bcast<Q>(cur.tau_bits));
   const uint32_t b = min(b0, b0 - M);  // the fused fold reports bin 0 as M
   lds_add(hw + b * kWave, row_bcast<Q>(cur.pk));
-  if (NZ) lds_add(hz + b * kWave, row_bcast<Q>(cur.pz));
+  if (NZ == NZ_PAIR) lds_add(hz + b * kWave, row_bcast<Q>(cur.pz));
+  if (NZ == NZ_ONE) lds_add32(hz32 + b * kWave, row_bcast32<Q>(lo32(cur.pz)));
 }
 
-// slots per lane: M (weight, residual) words, then M (Z_1, Z_2) words (NZ = 1;
-// with one baseline term, Z_0 = beta W needs no sum of its own, NZ = 0)
+// Slots per lane: M (weight, residual) words, then M extra words ([m][lane]).
 template <int PH, int NZ>
 __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restrict__ rec,
                                                    const int64_t* __restrict__ offsets,
@@ -50,10 +67,12 @@ __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restr
   const int lane = threadIdx.x;
   const int M = a.n_bins;
   uint64_t* hw = lds + lane;                      // [m][lane]: weight and residual
-  uint64_t* hz = lds + (size_t)M * kWave + lane;  // [m][lane]: w T_1 and w T_2
+  uint64_t* hz = lds + (size_t)M * kWave + lane;  // [m][lane]: w T_1 and w T_2 (64-bit pair)
+  uint32_t* hz32 = reinterpret_cast<uint32_t*>(lds + (size_t)M * kWave) + lane;  // [m][lane]: w T_1 alone
   for (int m = 0; m < M; ++m) {
     hw[m * kWave] = 0;
-    if (NZ) hz[m * kWave] = 0;
+    if (NZ == NZ_PAIR) hz[m * kWave] = 0;
+    if (NZ == NZ_ONE) hz32[m * kWave] = 0;
   }
   const int sub = lane & (kGroup - 1);
   for (;;) {
@@ -77,10 +96,10 @@ __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restr
         const RecB next = rc[nxt < n ? nxt : n - 1];  // prefetch (clamped, in bounds)
         const int cnt = n - g;                         // wave-uniform
         if (cnt >= kGroup) {
-          static_for<0, kGroup>([&](auto qc) { bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz); });
+          static_for<0, kGroup>([&](auto qc) { bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz, hz32); });
         } else {
           static_for<0, kGroup>([&](auto qc) {
-            if (decltype(qc)::value < cnt) bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz);
+            if (decltype(qc)::value < cnt) bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz, hz32);
           });
         }
         cur = next;
@@ -90,7 +109,8 @@ __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restr
       double p00 = 0.0, p01 = 0.0, p02 = 0.0, p11 = 0.0, p12 = 0.0, p22 = 0.0;
       for (int m = 0; m < M; ++m) {
         const uint64_t vw = lds_take(hw + m * kWave);
-        const uint64_t vz = NZ ? lds_take(hz + m * kWave) : (uint64_t)0;
+        const uint64_t vz = NZ == NZ_PAIR ? lds_take(hz + m * kWave)
+                            : (NZ == NZ_ONE ? (uint64_t)(int64_t)(int32_t)lds_take32(hz32 + m * kWave) : (uint64_t)0);
         const uint32_t lw = lo32(vw), lz = lo32(vz);
         const uint32_t wq = hi32(vw) + (lw >> 31);
         const int32_t yq = (int32_t)lw;
@@ -142,18 +162,21 @@ __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restr
 }  // namespace
 
 size_t bm_lds_bytes(int n_bins, int n_terms) {
-  return (size_t)(n_terms >= 2 ? 2 : 1) * n_bins * kWave * sizeof(uint64_t);
+  const size_t per_slot = n_terms >= 3 ? 16 : (n_terms == 2 ? 12 : 8);
+  return per_slot * n_bins * kWave;
 }
 
 namespace {
-const void* bm_fn(int phase, int nz) {
-  if (phase == PH_LISTING) return nz ? (const void*)bm_kernel<PH_LISTING, 1> : (const void*)bm_kernel<PH_LISTING, 0>;
-  return nz ? (const void*)bm_kernel<PH_FP64, 1> : (const void*)bm_kernel<PH_FP64, 0>;
+const void* bm_fn(int phase, int n_terms) {
+  const bool lst = phase == PH_LISTING;
+  if (n_terms >= 3) return lst ? (const void*)bm_kernel<PH_LISTING, NZ_PAIR> : (const void*)bm_kernel<PH_FP64, NZ_PAIR>;
+  if (n_terms == 2) return lst ? (const void*)bm_kernel<PH_LISTING, NZ_ONE> : (const void*)bm_kernel<PH_FP64, NZ_ONE>;
+  return lst ? (const void*)bm_kernel<PH_LISTING, NZ_NONE> : (const void*)bm_kernel<PH_FP64, NZ_NONE>;
 }
 }  // namespace
 
 hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int* out) {
-  const void* fn = bm_fn(phase, n_terms >= 2);
+  const void* fn = bm_fn(phase, n_terms);
   const size_t lds = bm_lds_bytes(n_bins, n_terms);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -161,7 +184,7 @@ hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int* out) {
 }
 
 hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s) {
-  const void* fn = bm_fn(phase, a.n_terms >= 2);
+  const void* fn = bm_fn(phase, a.n_terms);
   const size_t lds = bm_lds_bytes(a.n_bins, a.n_terms);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
