@@ -85,13 +85,29 @@ struct fpw_plan_s {
   int n_items = 0;
   bool tuned = false;
   // graph of one eval pass
+  // Captured passes, one per set of output pointers (a few kept, least
+  // recently used dropped): callers that alternate between output buffers,
+  // as a caching allocator does, replay without re-capturing.
+  struct Graph {
+    float* S;
+    int32_t* idx;
+    float* val;
+    hipGraph_t g;
+    hipGraphExec_t x;
+    uint64_t used;
+  };
+  static constexpr size_t kMaxGraphs = 4;
+  std::vector<Graph> graphs;
+  uint64_t graph_clock = 0;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
-  float* g_S = nullptr;
-  int32_t* g_idx = nullptr;
-  float* g_val = nullptr;
   bool graph_ok = true;
+  void drop_graphs() {
+    for (Graph& e : graphs) {
+      if (e.x) (void)hipGraphExecDestroy(e.x);
+      if (e.g) (void)hipGraphDestroy(e.g);
+    }
+    graphs.clear();
+  }
   // shared-timestamp plans on the matrix cores
   bool mfma = false;
   int32_t sh_points = 0, sh_kblocks = 0, sh_chunk = 0, sh_fw = 0, sh_nb = 2, sh_rounds = 0, sh_priv = 0;
@@ -109,8 +125,7 @@ struct fpw_plan_s {
   ~fpw_plan_s() {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
@@ -315,11 +330,8 @@ fpw_status upload_items(fpw_plan_s* p) {
     FPW_HIP(p->cand_idx.alloc(ns * p->opt.topk * sizeof(int32_t)), "alloc cand_idx");
     FPW_HIP(p->edge.alloc(ns * 4 * sizeof(float)), "alloc edge");
   }
-  // the graph holds the old buffers: drop it
-  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
-  p->graph_exec = nullptr;
-  p->graph = nullptr;
+  // captured passes hold the old buffers: drop them
+  p->drop_graphs();
   return FPW_OK;
 }
 
@@ -864,32 +876,38 @@ fpw_status fpw_eval_batch(fpw_plan_t p, float* S_dev, int32_t* topk_idx, float* 
     // Profiling records plain stream events, so a profiled pass is launched
     // directly rather than replayed from the graph.
     if (p->opt.use_graph && p->graph_ok && !p->opt.profile) {
-      if (!p->graph_exec || p->g_S != S_dev || p->g_idx != topk_idx || p->g_val != topk_val) {
-        if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-        if (p->graph) (void)hipGraphDestroy(p->graph);
-        p->graph_exec = nullptr;
-        p->graph = nullptr;
+      fpw_plan_s::Graph* hit = nullptr;
+      for (fpw_plan_s::Graph& e : p->graphs)
+        if (e.S == S_dev && e.idx == topk_idx && e.val == topk_val) hit = &e;
+      if (!hit) {
+        if (p->graphs.size() >= fpw_plan_s::kMaxGraphs) {
+          auto lru = p->graphs.begin();
+          for (auto it = p->graphs.begin(); it != p->graphs.end(); ++it)
+            if (it->used < lru->used) lru = it;
+          (void)hipGraphExecDestroy(lru->x);
+          (void)hipGraphDestroy(lru->g);
+          p->graphs.erase(lru);
+        }
         if (!p->cap_stream) FPW_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "capture stream");
         bool ok = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         fpw_status st = FPW_OK;
         if (ok) st = enqueue_pass(p, S_dev, topk_idx, topk_val, p->cap_stream);
         hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
         const bool ended = ok && hipStreamEndCapture(p->cap_stream, &g) == hipSuccess && g != nullptr;
-        if (ended && st == FPW_OK && hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0) == hipSuccess) {
-          p->graph = g;
-          p->g_S = S_dev;
-          p->g_idx = topk_idx;
-          p->g_val = topk_val;
+        if (ended && st == FPW_OK && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) {
+          p->graphs.push_back({S_dev, topk_idx, topk_val, g, x, 0});
+          hit = &p->graphs.back();
         } else {
           if (g) (void)hipGraphDestroy(g);
-          p->graph_exec = nullptr;
           p->graph_ok = false;  // fall back to direct launches from now on
           (void)hipGetLastError();
         }
       }
-      if (p->graph_exec) {
-        FPW_HIP(hipGraphLaunch(p->graph_exec, s), "graph launch");
-        p->ev_recorded = p->opt.profile != 0;
+      if (hit) {
+        hit->used = ++p->graph_clock;
+        FPW_HIP(hipGraphLaunch(hit->x, s), "graph launch");
+        p->ev_recorded = false;
         return FPW_OK;
       }
     }

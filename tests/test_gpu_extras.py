@@ -106,3 +106,29 @@ def test_c_client_runs_a_pass(tmp_path):
     r = subprocess.run([exe, "gpu"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "gpu pass ok" in r.stdout
+
+
+def test_graph_cache_with_alternating_and_many_output_buffers():
+    """Captured passes are kept per output buffer set (a few, least recently used dropped):
+    replays into alternating and into more buffer sets than are kept all match a direct pass."""
+    _say("graph cache")
+    b = synth.random_batch(75, 30, 20, 300, FREQS, 16)
+    ref_plan = fpw.Plan.from_batch(b, topk=3, use_graph=False)
+    S0, i0, v0 = ref_plan.eval()
+    torch.cuda.synchronize()
+    S0, i0, v0 = S0.cpu().numpy(), i0.cpu().numpy(), v0.cpu().numpy()
+    plan = fpw.Plan.from_batch(b, topk=3)
+    bufs = [(torch.empty_like(torch.from_numpy(S0)).cuda(), torch.empty((b.n_curves, 3), dtype=torch.int32, device="cuda"),
+             torch.empty((b.n_curves, 3), dtype=torch.float32, device="cuda")) for _ in range(6)]
+    order = [0, 1, 0, 1, 2, 3, 4, 5, 0, 5, 1]
+    for j in order:
+        S, idx, val = bufs[j]
+        S.fill_(-1.0)
+        plan.eval(S_out=S, idx_out=idx, val_out=val)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(S.cpu().numpy(), S0)
+        np.testing.assert_array_equal(idx.cpu().numpy(), i0)
+        np.testing.assert_array_equal(val.cpu().numpy(), v0)
+        torch.ones(100, device="cuda").sum().item()  # eager work between replays
+    plan.close()
+    ref_plan.close()
