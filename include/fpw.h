@@ -256,7 +256,8 @@ fpw_status fpw_pass_timings(fpw_plan_t plan, float ms[3]);
  * of the sampling rather than from the source.  Bins follow the plan's phase
  * mode, as in fpw_eval_batch.
  *   freq_idx_dev  DEVICE int32 [n_curves * k]: frequency index for each (curve, slot),
- *                 e.g. fpw_eval_batch's top-k output; slots with index < 0 are skipped
+ *                 e.g. fpw_eval_batch's top-k output; slots whose index is outside
+ *                 [0, n_freq) are skipped
  *   H_dev, E_dev, V_dev  DEVICE float32 [n_curves * k]; NaN in skipped slots
  *   k             1 <= k <= n_freq
  */

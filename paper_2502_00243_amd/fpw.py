@@ -195,6 +195,13 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
+def _check_out(t, dtype, numel, name):
+    """Output buffers the kernels write: device, contiguous, of the plan's dtype and size."""
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name} must be a contiguous device tensor of {numel} {dtype} elements "
+                         f"(got {tuple(t.shape)} {t.dtype} on {t.device})")
+
+
 def _stream_handle(stream=None):
     import torch
 
@@ -262,13 +269,17 @@ class Plan:
         S = S_out
         nv = self.n_variants
         lead = (nv,) if nv > 1 else ()
-        if store_s and S is None:
+        if S is not None:
+            _check_out(S, torch.float32, nv * self.n_curves * self.n_freq, "S_out")
+        elif store_s:
             S = torch.empty(lead + (self.n_curves, self.n_freq), dtype=torch.float32, device="cuda")
         idx = val = None
         if topk:
             shp = lead + (self.n_curves, self.topk_k)
             idx = idx_out if idx_out is not None else torch.empty(shp, dtype=torch.int32, device="cuda")
             val = val_out if val_out is not None else torch.empty(shp, dtype=torch.float32, device="cuda")
+            _check_out(idx, torch.int32, nv * self.n_curves * self.topk_k, "idx_out")
+            _check_out(val, torch.float32, nv * self.n_curves * self.topk_k, "val_out")
         _check(load().fpw_eval_batch(self._h, ctypes.c_void_p(S.data_ptr() if S is not None else 0),
                                      ctypes.c_void_p(idx.data_ptr() if idx is not None else 0),
                                      ctypes.c_void_p(val.data_ptr() if val is not None else 0), _stream_handle(stream)))
