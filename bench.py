@@ -57,20 +57,24 @@ def _oracle_curve(args):
     return float(np.sum(S)), len(t) * len(freqs)
 
 
-def cpu_baseline(batch, target_s: float = 15.0):
-    """The FP64 oracle on the host cores over a bounded sample of the same workload."""
+def cpu_baseline(batch, target_s: float = 15.0, freq_stride: int = 1):
+    """The FP64 oracle on the host cores over a bounded sample of the same workload:
+    the first curves (as many as fill about target_s of wall time) at every
+    freq_stride-th frequency of the grid."""
     import multiprocessing as mp
 
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
     os.environ["OMP_NUM_THREADS"] = "1"
+    freqs = batch.freqs[::freq_stride]
     t0 = time.perf_counter()
-    _oracle_curve((*batch.curve(0), batch.freqs, batch.n_bins))
+    _oracle_curve((*batch.curve(0), freqs[: max(1, min(len(freqs), 2000))], batch.n_bins))
     one = time.perf_counter() - t0
-    per_eval = one / (batch.lengths[0] * len(batch.freqs))
-    mean_curve = per_eval * batch.lengths.mean() * len(batch.freqs)
+    per_eval = one / (batch.lengths[0] * max(1, min(len(freqs), 2000)))
+    mean_curve = per_eval * batch.lengths.mean() * len(freqs)
     n_sample = int(min(batch.n_curves, max(cores, round(target_s * cores / max(mean_curve, 1e-9)))))
     n_sample = max(cores, (n_sample // cores) * cores) if n_sample >= cores else n_sample
-    tasks = [(*batch.curve(c), batch.freqs, batch.n_bins) for c in range(n_sample)]
+    n_sample = min(n_sample, batch.n_curves)
+    tasks = [(*batch.curve(c), freqs, batch.n_bins) for c in range(n_sample)]
     ctx = mp.get_context("spawn")
     with ctx.Pool(cores) as pool:
         pool.map(_oracle_curve, tasks[:cores])  # start-up outside the timed region
@@ -86,13 +90,17 @@ def cpu_baseline(batch, target_s: float = 15.0):
                 break
     except OSError:
         pass
+    grid = f"all {len(batch.freqs)} frequencies" if freq_stride == 1 else \
+        f"every {freq_stride}th of {len(batch.freqs)} frequencies"
+    value = evals / wall / 1e9
     return {
-        "value": evals / wall / 1e9,
+        "value": value,
         "unit": "G evals/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"first {n_sample} of {batch.n_curves} curves x all {len(batch.freqs)} frequencies "
+        "sample": f"first {n_sample} of {batch.n_curves} curves x {grid} "
         f"({evals:.3g} evals, {wall:.1f} s wall, one single-threaded NumPy process per core, {cpu})",
+        "extrapolated_full_s": batch.evals() / (value * 1e9),
     }
 
 
@@ -446,11 +454,19 @@ def bench_uneven(args):
         log(f"multi-M (40 -> 20, 10; {nv} variants): {wall * 1e3:.1f} ms/pass")
         plan.close()
         del idx, val
+    cpu = None
+    if not args.no_cpu_baseline:
+        b20 = batch.subset(range(min(batch.n_curves, 4096)))
+        b20.n_bins = 20
+        cpu = cpu_baseline(b20, args.cpu_seconds)
+        cpu["extrapolated_full_s"] = evals / (cpu["value"] * 1e9)  # one M over the whole batch
+        cpu["sample"] = "M=20: " + cpu["sample"]
+        log(f"cpu baseline: {cpu['value']:.4f} G evals/s on {cpu['cores']} cores")
     print(json.dumps({"workload": f"uneven: {batch.n_curves} curves (N lognormal 50-2000, sum {batch.n_points}), "
                                   f"{len(batch.freqs)} freqs 0.05-50 /d, M in {{10,20,40}}, top-5, periodogram not stored",
                       "evals_per_M": evals, "total_ms_three_M": total_ms,
                       "value": 3 * evals / (total_ms * 1e-3) / 1e9, "unit": "G evals/s", "per_M": res,
-                      "multi_M_one_pass": multi}), flush=True)
+                      "multi_M_one_pass": multi, "cpu_baseline": cpu}), flush=True)
 
 
 def bench_stress(args):
@@ -475,6 +491,11 @@ def bench_stress(args):
     wall_s, kms_s = _time_passes(ps, 2, 1, store_s=True, topk=False)
     fp = _fp64_rate(ps, sub.evals())
     ps.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(batch.subset(range(min(batch.n_curves, 256))), args.cpu_seconds, freq_stride=10)
+        cpu["extrapolated_full_s"] = evals / (cpu["value"] * 1e9)
+        log(f"cpu baseline: {cpu['value']:.4f} G evals/s on {cpu['cores']} cores")
     print(json.dumps({"workload": f"stress: {batch.n_curves} curves x 3000 points over 2000 d, "
                                   f"{len(batch.freqs)} freqs 0.01-200 /d, M=50, top-5, periodogram not stored",
                       "evals": evals, "s_per_pass": wall, "value": evals / wall / 1e9, "unit": "G evals/s",
@@ -482,7 +503,8 @@ def bench_stress(args):
                       "roofline": _roofline(evals, batch.n_curves, len(batch.freqs), 50, batch.n_points,
                                             float(kms[:, 1].mean())),
                       "subset200": {"batched_G_evals_per_s": sub.evals() / wall_s / 1e9,
-                                    "fp64_plain": fp, "speedup": (sub.evals() / wall_s / 1e9) / fp["value"]}}),
+                                    "fp64_plain": fp, "speedup": (sub.evals() / wall_s / 1e9) / fp["value"]},
+                      "cpu_baseline": cpu}),
           flush=True)
 
 
