@@ -402,12 +402,23 @@ def bench_baseline(args):
             nbytes = {1: 8, 2: 12, 3: 16}[K]  # LDS bytes added per evaluation: (w, w x), then w T_1 (and w T_2)
             r["lds"] = {"bytes_per_eval": nbytes, "achieved_TBps": evals * nbytes / (kernel_ms * 1e-3) / 1e12,
                         "peak_TBps": LDS_PEAK / 1e12, "frac": evals * nbytes / (kernel_ms * 1e-3) / LDS_PEAK}
+        r["hist_share"] = plan.info().hist_share
         log(f"baseline K={K}: {wall * 1e3:.3f} ms/pass, kernel {kernel_ms:.3f} ms, {evals / wall / 1e9:.0f} G evals/s")
         res[f"K{K}"] = r
         plan.close()
+    # kernel time of the baseline kernel by histogram sharing (waves per histogram)
+    shares = {}
+    for K in (1, 2, 3):
+        for share in (1, 2, 4):
+            plan = fpw.Plan.from_batch(batch, topk=5, baseline_terms=K, hist_share=share, profile=True)
+            _, kms = _time_passes(plan, 3, 1, S_out=S, idx_out=idx, val_out=val)
+            shares[f"K{K}_share{share}"] = {"kernel_ms": float(np.median(kms[:, 1])),
+                                            "grid_groups": plan.info().grid_groups, "lds_bytes": plan.info().lds_bytes}
+            plan.close()
     print(json.dumps({"workload": "baseline: 1000 ZTF-like curves, 1e5 freqs 0.05-50 /d, M=20, periodogram + top-5, "
                                   "marginalised Chebyshev baseline of K terms (K=0: Eq. 1)",
-                      "evals": evals, "value": res["K3"]["G_evals_per_s"], "unit": "G evals/s", "per_K": res}),
+                      "evals": evals, "value": res["K3"]["G_evals_per_s"], "unit": "G evals/s", "per_K": res,
+                      "kernel_ms_by_share": shares}),
           flush=True)
 
 
@@ -564,7 +575,7 @@ def bench_precision(args):
 
 
 def bench_sweep(args):
-    """Kernel time of each point source and bin count on the ztf1000 data (one JSON line per shape)."""
+    """Kernel time of each point source, histogram sharing and bin count on the ztf1000 data (one JSON line per shape)."""
     import numpy as np
     import torch
 
@@ -576,17 +587,19 @@ def bench_sweep(args):
     S = torch.empty((batch.n_curves, len(batch.freqs)), dtype=torch.float32, device="cuda")
     idx = torch.empty((batch.n_curves, 5), dtype=torch.int32, device="cuda")
     val = torch.empty((batch.n_curves, 5), dtype=torch.float32, device="cuda")
-    for M in (10, 20, 40, 50, 100):
+    for M in (10, 20, 32, 40, 50, 64, 80, 100, 160):
         for src in ("scalar", "dpp"):
-            plan = fpw.Plan.from_batch(batch, n_bins=M, topk=5, point_source=src, profile=True)
-            info = plan.info()
-            _, kms = _time_passes(plan, 4, 1, S_out=S, idx_out=idx, val_out=val)
-            k = float(np.median(kms[:, 1]))
-            print(json.dumps({"M": M, "point_source": src, "chunk_freqs": info.chunk_freqs, "grid_groups": info.grid_groups,
-                              "kernel_ms": k, "G_evals_per_s": evals / (k * 1e-3) / 1e9,
-                              "roofline_frac": _roofline(evals, batch.n_curves, len(batch.freqs), M, batch.n_points, k)["frac"]}),
-                  flush=True)
-            plan.close()
+            for share in (1, 2, 4):
+                plan = fpw.Plan.from_batch(batch, n_bins=M, topk=5, point_source=src, hist_share=share, profile=True)
+                info = plan.info()
+                _, kms = _time_passes(plan, 4, 1, S_out=S, idx_out=idx, val_out=val)
+                k = float(np.median(kms[:, 1]))
+                print(json.dumps({"M": M, "point_source": src, "hist_share": share, "chunk_freqs": info.chunk_freqs,
+                                  "grid_groups": info.grid_groups, "lds_bytes": info.lds_bytes,
+                                  "kernel_ms": k, "G_evals_per_s": evals / (k * 1e-3) / 1e9,
+                                  "roofline_frac": _roofline(evals, batch.n_curves, len(batch.freqs), M, batch.n_points, k)["frac"]}),
+                      flush=True)
+                plan.close()
     # launch shapes of the headline configuration (M = 20, scalar source)
     for fl in (1, 2):
         for wpg in (1, 2, 4):

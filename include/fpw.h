@@ -129,6 +129,17 @@ typedef struct {
                              FPW_MAX_BASELINE_BINS and no derived bin counts. */
   double baseline_scale;  /* prior standard deviation of each baseline coefficient, in flux
                              units (> 0, finite; default 1) */
+  int32_t hist_share;     /* launch shape override: waves that share one LDS histogram.
+                             0 = default: by M (1 below 16 bins, 2 up to 31, 4 from 32) for
+                             the FP64 phase modes when freqs_per_lane and waves_per_group are
+                             0, else 1.  1 = one private histogram per wave.  2 or 4 = a
+                             workgroup of that many waves folds disjoint slices of each
+                             curve's observations into one histogram (waves_per_group must be
+                             0 or equal; FP64 phase modes, one frequency per lane).  S is
+                             summed in one fixed order for every launch shape, so results are
+                             bit-identical to private histograms.  With baseline_terms > 0 it
+                             sets the baseline kernel's sharing instead; 0 = by histogram size
+                             (1 up to 13 KiB per wave, 4 above). */
 } fpw_options;
 
 /* Kernel of a shared-timestamp plan (fpw_plan_shared). */
@@ -281,6 +292,8 @@ typedef struct {
   int32_t n_variants;     /* periodograms per curve and pass */
   int32_t kernel;         /* 0 general batched kernel, 1 shared-timestamp matrix-core kernel,
                              2 baseline-marginalised kernel */
+  int32_t hist_share;     /* waves per LDS histogram (1, 2, 4) of the general batched kernel
+                             or of the baseline kernel; 0 for the matrix-core kernel */
 } fpw_plan_info;
 
 fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);

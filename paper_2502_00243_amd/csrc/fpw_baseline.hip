@@ -56,20 +56,91 @@ __device__ __forceinline__ void bm_point(const RecB& cur, const Folder<PH>& fo, 
   if (NZ == NZ_ONE) lds_add32(hz32 + b * kWave, row_bcast32<Q>(lo32(cur.pz)));
 }
 
-// Slots per lane: M (weight, residual) words, then M extra words ([m][lane]).
-template <int PH, int NZ>
-__global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restrict__ rec,
-                                                   const int64_t* __restrict__ offsets,
-                                                   const BaseConst* __restrict__ bcs,
-                                                   const double* __restrict__ freqs,
-                                                   const Item* __restrict__ items) {
+// Per-lane sums of the FP64 epilogue over a range of bins: v^T L^-1 v, r = Z^T L^-1 v
+// and P = Z^T L^-1 Z (upper triangle).
+struct BmSums {
+  double s1, r0, r1, r2, p00, p01, p02, p11, p12, p22;
+};
+constexpr int kBmSums = 10;
+
+// Reads and clears bins [mb, me) of one lane's histograms and returns their sums.
+template <int NZ>
+__device__ __forceinline__ BmSums bm_bins(uint64_t* hw, uint64_t* hz, uint32_t* hz32, int mb, int me,
+                                          const BaseConst& bc) {
+  BmSums a{};
+  for (int m = mb; m < me; ++m) {
+    const uint64_t vw = lds_take(hw + m * kWave);
+    const uint64_t vz = NZ == NZ_PAIR ? lds_take(hz + m * kWave)
+                        : (NZ == NZ_ONE ? (uint64_t)(int64_t)(int32_t)lds_take32(hz32 + m * kWave) : (uint64_t)0);
+    const uint32_t lw = lo32(vw), lz = lo32(vz);
+    const uint32_t wq = hi32(vw) + (lw >> 31);
+    const int32_t yq = (int32_t)lw;
+    const int32_t z1q = (int32_t)lz;
+    const int32_t z2q = (int32_t)(hi32(vz) + (lz >> 31));
+    const double W = (double)wq * bc.inv_sw;
+    const double Y = (double)yq * bc.inv_sy;
+    const double Z0 = bc.beta * W;
+    const double Z1 = bc.beta * ((double)z1q * bc.inv_sz);
+    const double Z2 = bc.beta * ((double)z2q * bc.inv_sz);
+    const double d = W + bc.ia2;
+    const double inv = d > 0.0 ? 1.0 / d : 0.0;  // an empty bin adds nothing
+    const double v = Y - (Z0 * bc.g[0] + Z1 * bc.g[1] + Z2 * bc.g[2]);
+    const double vi = v * inv;
+    a.s1 += v * vi;
+    a.r0 += Z0 * vi;
+    a.r1 += Z1 * vi;
+    a.r2 += Z2 * vi;
+    const double z0i = Z0 * inv, z1i = Z1 * inv, z2i = Z2 * inv;
+    a.p00 += Z0 * z0i;
+    a.p01 += Z0 * z1i;
+    a.p02 += Z0 * z2i;
+    a.p11 += Z1 * z1i;
+    a.p12 += Z1 * z2i;
+    a.p22 += Z2 * z2i;
+  }
+  return a;
+}
+
+// S = v^T L^-1 v + r^T Q^-1 r with Q = H - P (symmetric positive definite,
+// Q >= I), by an LDL^T factorisation of the 3x3 Q.
+__device__ __forceinline__ double bm_statistic(const BmSums& a, const BaseConst& bc) {
+  const double q00 = bc.H[0] - a.p00, q01 = bc.H[1] - a.p01, q02 = bc.H[2] - a.p02;
+  const double q11 = bc.H[3] - a.p11, q12 = bc.H[4] - a.p12, q22 = bc.H[5] - a.p22;
+  const double l1 = q01 / q00, l2 = q02 / q00;
+  const double a11 = q11 - l1 * q01, a12 = q12 - l1 * q02, a22 = q22 - l2 * q02;
+  const double m2 = a12 / a11;
+  const double c22 = a22 - m2 * a12;
+  const double y1 = a.r1 - l1 * a.r0;
+  const double y2 = a.r2 - l2 * a.r0 - m2 * y1;
+  const double s2 = a.r0 * a.r0 / q00 + y1 * y1 / a11 + y2 * y2 / c22;
+  return a.s1 + s2;
+}
+
+// Slots per histogram lane: M (weight, residual) words, then M extra words
+// ([m][lane]).  SH == 1: one wave per workgroup with its own histograms.
+// SH > 1: the SH waves of a workgroup share them; each folds a contiguous
+// slice of the curve's observations, then each takes the epilogue sums of a
+// contiguous range of bins, and wave 0 adds them (in wave order) and forms
+// S.  After the histograms: the partial sums [SH-1][10][lane] (FP64) and
+// the group's item index.
+template <int PH, int NZ, int SH>
+__global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const RecB* __restrict__ rec,
+                                                        const int64_t* __restrict__ offsets,
+                                                        const BaseConst* __restrict__ bcs,
+                                                        const double* __restrict__ freqs,
+                                                        const Item* __restrict__ items) {
   extern __shared__ __align__(16) uint64_t lds[];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // uniform: keeps slice loads scalar
   const int M = a.n_bins;
   uint64_t* hw = lds + lane;                      // [m][lane]: weight and residual
   uint64_t* hz = lds + (size_t)M * kWave + lane;  // [m][lane]: w T_1 and w T_2 (64-bit pair)
   uint32_t* hz32 = reinterpret_cast<uint32_t*>(lds + (size_t)M * kWave) + lane;  // [m][lane]: w T_1 alone
-  for (int m = 0; m < M; ++m) {
+  // histogram size in 64-bit words: 8, 12 or 16 bytes per (bin, lane)
+  const int hist_words = (NZ == NZ_NONE ? 2 : (NZ == NZ_ONE ? 3 : 4)) * M * kWave / 2;
+  double* part = reinterpret_cast<double*>(lds + hist_words);
+  int* group_item = reinterpret_cast<int*>(part + (SH - 1) * kBmSums * kWave);
+  for (int m = wave; m < M; m += SH) {
     hw[m * kWave] = 0;
     if (NZ == NZ_PAIR) hz[m * kWave] = 0;
     if (NZ == NZ_ONE) hz32[m * kWave] = 0;
@@ -77,82 +148,75 @@ __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restr
   const int sub = lane & (kGroup - 1);
   for (;;) {
     int it = 0;
-    if (lane == 0) it = (int)atomicAdd(a.queue, 1u);
-    it = __builtin_amdgcn_readfirstlane(it);
+    if (SH > 1) {
+      // one pop per workgroup; the previous item's barriers order this write
+      // after every wave's read of the previous index
+      if (threadIdx.x == 0) *group_item = (int)atomicAdd(a.queue, 1u);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(*group_item);
+    } else {
+      if (lane == 0) it = (int)atomicAdd(a.queue, 1u);
+      it = __builtin_amdgcn_readfirstlane(it);
+    }
     if (it >= a.n_items) break;
     const Item item = items[it];
     const int c = item.curve, k0 = item.k0, k1 = item.k1;
     const int64_t p0 = offsets[c];
-    const int n = (int)(offsets[c + 1] - p0);
-    const RecB* __restrict__ rc = rec + p0;
+    const int n_all = (int)(offsets[c + 1] - p0);
+    const int lo = SH > 1 ? (int)((int64_t)wave * n_all / SH) : 0;
+    const int n = SH > 1 ? (int)((int64_t)(wave + 1) * n_all / SH) - lo : n_all;
+    const RecB* __restrict__ rc = rec + p0 + lo;
     const BaseConst bc = bcs[c];
     for (int kt = k0; kt < k1; kt += kWave) {
       const int k = kt + lane;
-      Folder<PH> fo;
-      fo.init(freqs[k < k1 ? k : k1 - 1], M);
-      RecB cur = rc[sub < n ? sub : n - 1];
-      for (int g = 0; g < n; g += kGroup) {
-        const int nxt = g + kGroup + sub;
-        const RecB next = rc[nxt < n ? nxt : n - 1];  // prefetch (clamped, in bounds)
-        const int cnt = n - g;                         // wave-uniform
-        if (cnt >= kGroup) {
-          static_for<0, kGroup>([&](auto qc) { bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz, hz32); });
-        } else {
-          static_for<0, kGroup>([&](auto qc) {
-            if (decltype(qc)::value < cnt) bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz, hz32);
-          });
+      if (n > 0) {
+        Folder<PH> fo;
+        fo.init(freqs[k < k1 ? k : k1 - 1], M);
+        RecB cur = rc[sub < n ? sub : n - 1];
+        for (int g = 0; g < n; g += kGroup) {
+          const int nxt = g + kGroup + sub;
+          const RecB next = rc[nxt < n ? nxt : n - 1];  // prefetch (clamped, in bounds)
+          const int cnt = n - g;                         // wave-uniform
+          if (cnt >= kGroup) {
+            static_for<0, kGroup>([&](auto qc) { bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz, hz32); });
+          } else {
+            static_for<0, kGroup>([&](auto qc) {
+              if (decltype(qc)::value < cnt) bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz, hz32);
+            });
+          }
+          cur = next;
         }
-        cur = next;
       }
-      // FP64 epilogue: v^T L^-1 v and the 3x3 correction
-      double s1 = 0.0, r0 = 0.0, r1 = 0.0, r2 = 0.0;
-      double p00 = 0.0, p01 = 0.0, p02 = 0.0, p11 = 0.0, p12 = 0.0, p22 = 0.0;
-      for (int m = 0; m < M; ++m) {
-        const uint64_t vw = lds_take(hw + m * kWave);
-        const uint64_t vz = NZ == NZ_PAIR ? lds_take(hz + m * kWave)
-                            : (NZ == NZ_ONE ? (uint64_t)(int64_t)(int32_t)lds_take32(hz32 + m * kWave) : (uint64_t)0);
-        const uint32_t lw = lo32(vw), lz = lo32(vz);
-        const uint32_t wq = hi32(vw) + (lw >> 31);
-        const int32_t yq = (int32_t)lw;
-        const int32_t z1q = (int32_t)lz;
-        const int32_t z2q = (int32_t)(hi32(vz) + (lz >> 31));
-        const double W = (double)wq * bc.inv_sw;
-        const double Y = (double)yq * bc.inv_sy;
-        const double Z0 = bc.beta * W;
-        const double Z1 = bc.beta * ((double)z1q * bc.inv_sz);
-        const double Z2 = bc.beta * ((double)z2q * bc.inv_sz);
-        const double d = W + bc.ia2;
-        const double inv = d > 0.0 ? 1.0 / d : 0.0;  // an empty bin adds nothing
-        const double v = Y - (Z0 * bc.g[0] + Z1 * bc.g[1] + Z2 * bc.g[2]);
-        const double vi = v * inv;
-        s1 += v * vi;
-        r0 += Z0 * vi;
-        r1 += Z1 * vi;
-        r2 += Z2 * vi;
-        const double z0i = Z0 * inv, z1i = Z1 * inv, z2i = Z2 * inv;
-        p00 += Z0 * z0i;
-        p01 += Z0 * z1i;
-        p02 += Z0 * z2i;
-        p11 += Z1 * z1i;
-        p12 += Z1 * z2i;
-        p22 += Z2 * z2i;
+      if constexpr (SH == 1) {
+        const BmSums sums = bm_bins<NZ>(hw, hz, hz32, 0, M, bc);
+        if (k < k1) a.S[(int64_t)c * a.n_freq + k] = (float)(bm_statistic(sums, bc) * bc.scale);
+      } else {
+        __syncthreads();  // every slice is in the histograms
+        BmSums sums = bm_bins<NZ>(hw, hz, hz32, wave * M / SH, (wave + 1) * M / SH, bc);
+        if (wave > 0) {
+          double* pp = part + (size_t)(wave - 1) * kBmSums * kWave + lane;
+          const double* sv = &sums.s1;
+#pragma unroll
+          for (int q = 0; q < kBmSums; ++q) pp[q * kWave] = sv[q];
+        }
+        __syncthreads();  // partial sums visible, histograms clear for the next sub-tile
+        if (wave == 0) {
+          double* sv = &sums.s1;
+#pragma unroll
+          for (int w = 1; w < SH; ++w) {
+            const double* pp = part + (size_t)(w - 1) * kBmSums * kWave + lane;
+#pragma unroll
+            for (int q = 0; q < kBmSums; ++q) sv[q] += pp[q * kWave];
+          }
+          if (k < k1) a.S[(int64_t)c * a.n_freq + k] = (float)(bm_statistic(sums, bc) * bc.scale);
+        }
       }
-      // r^T Q^-1 r with Q = H - P (symmetric positive definite, Q >= I)
-      const double q00 = bc.H[0] - p00, q01 = bc.H[1] - p01, q02 = bc.H[2] - p02;
-      const double q11 = bc.H[3] - p11, q12 = bc.H[4] - p12, q22 = bc.H[5] - p22;
-      const double l1 = q01 / q00, l2 = q02 / q00;
-      const double a11 = q11 - l1 * q01, a12 = q12 - l1 * q02, a22 = q22 - l2 * q02;
-      const double m2 = a12 / a11;
-      const double c22 = a22 - m2 * a12;
-      const double y1 = r1 - l1 * r0;
-      const double y2 = r2 - l2 * r0 - m2 * y1;
-      const double s2 = r0 * r0 / q00 + y1 * y1 / a11 + y2 * y2 / c22;
-      if (k < k1) a.S[(int64_t)c * a.n_freq + k] = (float)((s1 + s2) * bc.scale);
     }
   }
   if (lane == 0) {
     __threadfence();
-    if (atomicAdd(a.queue + 1, 1u) == gridDim.x - 1) {
+    const uint32_t total = gridDim.x * SH;
+    if (atomicAdd(a.queue + 1, 1u) == total - 1) {
       atomicExch(a.queue, 0u);
       atomicExch(a.queue + 1, 0u);
     }
@@ -161,31 +225,41 @@ __global__ __launch_bounds__(kWave) void bm_kernel(BmArgs a, const RecB* __restr
 
 }  // namespace
 
-size_t bm_lds_bytes(int n_bins, int n_terms) {
+size_t bm_lds_bytes(int n_bins, int n_terms, int share) {
   const size_t per_slot = n_terms >= 3 ? 16 : (n_terms == 2 ? 12 : 8);
-  return per_slot * n_bins * kWave;
+  const size_t hist = per_slot * n_bins * kWave;
+  if (share <= 1) return hist;
+  return hist + (size_t)(share - 1) * kBmSums * kWave * sizeof(double) + 16;
 }
 
 namespace {
-const void* bm_fn(int phase, int n_terms) {
-  const bool lst = phase == PH_LISTING;
-  if (n_terms >= 3) return lst ? (const void*)bm_kernel<PH_LISTING, NZ_PAIR> : (const void*)bm_kernel<PH_FP64, NZ_PAIR>;
-  if (n_terms == 2) return lst ? (const void*)bm_kernel<PH_LISTING, NZ_ONE> : (const void*)bm_kernel<PH_FP64, NZ_ONE>;
-  return lst ? (const void*)bm_kernel<PH_LISTING, NZ_NONE> : (const void*)bm_kernel<PH_FP64, NZ_NONE>;
+template <int PH, int SH>
+const void* bm_fn_sh(int n_terms) {
+  if (n_terms >= 3) return (const void*)bm_kernel<PH, NZ_PAIR, SH>;
+  if (n_terms == 2) return (const void*)bm_kernel<PH, NZ_ONE, SH>;
+  return (const void*)bm_kernel<PH, NZ_NONE, SH>;
+}
+template <int PH>
+const void* bm_fn_ph(int n_terms, int share) {
+  return share == 4 ? bm_fn_sh<PH, 4>(n_terms) : (share == 2 ? bm_fn_sh<PH, 2>(n_terms) : bm_fn_sh<PH, 1>(n_terms));
+}
+const void* bm_fn(int phase, int n_terms, int share) {
+  return phase == PH_LISTING ? bm_fn_ph<PH_LISTING>(n_terms, share) : bm_fn_ph<PH_FP64>(n_terms, share);
 }
 }  // namespace
 
-hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int* out) {
-  const void* fn = bm_fn(phase, n_terms);
-  const size_t lds = bm_lds_bytes(n_bins, n_terms);
+hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int share, int* out) {
+  const void* fn = bm_fn(phase, n_terms, share);
+  const size_t lds = bm_lds_bytes(n_bins, n_terms, share);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, kWave, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, kWave * share, lds);
 }
 
 hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s) {
-  const void* fn = bm_fn(phase, a.n_terms);
-  const size_t lds = bm_lds_bytes(a.n_bins, a.n_terms);
+  const int share = a.share > 1 ? a.share : 1;
+  const void* fn = bm_fn(phase, a.n_terms, share);
+  const size_t lds = bm_lds_bytes(a.n_bins, a.n_terms, share);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   BmArgs args = a;
@@ -195,7 +269,7 @@ hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s) {
   const double* freqs = a.freqs;
   const Item* items = a.items;
   void* params[] = {&args, &rec, &offsets, &bcs, &freqs, &items};
-  return hipLaunchKernel(fn, dim3(grid), dim3(kWave), params, lds, s);
+  return hipLaunchKernel(fn, dim3(grid), dim3(kWave * share), params, lds, s);
 }
 
 }  // namespace fpw

@@ -22,7 +22,12 @@
 //    FP64 instructions plus the LDS address;
 //  * work is a queue of (curve, frequency chunk) items, longest curves first,
 //    popped by persistent waves with one atomic each; the peak selection is
-//    fused so that large periodograms never reach HBM.
+//    fused so that large periodograms never reach HBM;
+//  * for large M a private histogram per wave leaves room for few waves per
+//    CU, so SH > 1 waves of a workgroup share one: each folds a contiguous
+//    slice of the curve's observations into it (LDS atomics from different
+//    waves add up exactly), then each reduces a contiguous range of bins and
+//    wave 0 adds the partial sums.
 #include "fpw_common.h"
 
 namespace fpw {
@@ -129,9 +134,16 @@ __device__ __forceinline__ void accumulate(const Rec* __restrict__ rc, int n, co
 template <int PH, int NV>
 __device__ __forceinline__ void reduce_variants(uint64_t* h, int M, float ia2q, const Variants& vs, float (&out)[NV]) {
   const uint64_t wrap = take_wrap_slot<PH>(h, M);
+  const int nb = (M + kReduceBlock - 1) / kReduceBlock;
   uint64_t run = 0;
-  float fine = 0.f;
-  for (int m0 = 0; m0 < M; m0 += kReduceBlock) {
+  float fine = 0.f, fine_parts = 0.f;  // variant 0 in the order of reduce_hist
+  int part = 0;
+  for (int m0 = 0, b = 0; m0 < M; m0 += kReduceBlock, ++b) {
+    while (part < kSumParts && b == part_block(part + 1, nb)) {  // the parts ending here (empty ones add 0)
+      fine_parts += fine;
+      fine = 0.f;
+      ++part;
+    }
     uint64_t f[kReduceBlock];
     take_block<PH>(h, M, m0, f);
     if (m0 == 0) f[0] += wrap;
@@ -146,7 +158,7 @@ __device__ __forceinline__ void reduce_variants(uint64_t* h, int M, float ia2q, 
     }
   }
   const uint64_t total = run;  // P(M)
-  out[0] = fine;
+  out[0] = fine_parts + fine;
 #pragma unroll
   for (int v = 1; v < NV; ++v) {
     out[v] = 0.f;
@@ -181,6 +193,33 @@ __device__ __forceinline__ void reduce_variants(uint64_t* h, int M, float ia2q, 
       bits &= bits - 1;
       h[(w * 32 + b) * kWave] = 0;
     }
+  }
+}
+
+// The part sums of reduce_hist that one wave of a histogram shared by SH
+// waves owns (parts [w K/SH, (w+1) K/SH), K = kSumParts), read and cleared,
+// each written to part_sums[p][lane].  The wave whose first block is block 0
+// also takes the wrap slot.  Slots of other waves' parts are neither read
+// nor cleared.
+template <int PH, int SH>
+__device__ __forceinline__ void reduce_parts(uint64_t* h, int M, int wave, float ia2q, float* part_sums, int lane) {
+  const int nb = (M + kReduceBlock - 1) / kReduceBlock;
+  const int p0 = wave * kSumParts / SH, p1 = (wave + 1) * kSumParts / SH;
+  const bool first = part_block(p0, nb) == 0 && part_block(p1, nb) > 0;
+  const uint64_t wrap = first ? take_wrap_slot<PH>(h, M) : (uint64_t)0;
+  for (int p = p0; p < p1; ++p) {
+    float acc = 0.f;
+    for (int b = part_block(p, nb); b < part_block(p + 1, nb); ++b) {
+      const int m0 = b * kReduceBlock;
+      uint64_t f[kReduceBlock];
+#pragma unroll
+      for (int q = 0; q < kReduceBlock; ++q) f[q] = m0 + q < M ? lds_take(h + (m0 + q) * kWave) : (uint64_t)0;
+      if (m0 == 0) f[0] += wrap;
+#pragma unroll
+      for (int q = 0; q < kReduceBlock; ++q)
+        if (m0 + q < M) acc = add_bin_term(acc, f[q], ia2q);
+    }
+    part_sums[p * kWave + lane] = acc;
   }
 }
 
@@ -242,15 +281,25 @@ struct PeakState {
   }
 };
 
-template <int PH, int FL, int PK, int SRC, int NV>
+// SH > 1: the SH waves of the workgroup work on the same item with one shared
+// histogram; `part` holds the kSumParts part sums of S.  Only wave 0 (the
+// lead) stores S and keeps the peaks; with several variants it also does the
+// whole reduction.
+template <int PH, int FL, int PK, int SRC, int NV, int SH>
 __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, const Item& item, uint64_t* hist,
-                                             int lane) {
+                                             int lane, int wave, float* part) {
+  static_assert(SH == 1 || FL == 1, "a shared histogram serves one frequency per lane");
+  static_assert(kSumParts % SH == 0, "each wave owns whole parts of the sum");
   const int M = a.n_bins;
   const int slots = M + 1;
   const int c = item.curve, k0 = item.k0, k1 = item.k1;
   const int64_t p0 = ro.offsets[c];
-  const int n = (int)(ro.offsets[c + 1] - p0);
-  const Rec* __restrict__ rc = ro.rec + p0;
+  const int n_all = (int)(ro.offsets[c + 1] - p0);
+  // this wave's slice of the observations (all of them when SH == 1)
+  const int lo = SH > 1 ? (int)((int64_t)wave * n_all / SH) : 0;
+  const int n = SH > 1 ? (int)((int64_t)(wave + 1) * n_all / SH) - lo : n_all;
+  const Rec* __restrict__ rc = ro.rec + p0 + lo;
+  const bool lead = SH == 1 || wave == 0;
   const CurveConst cc = ro.cc[c];
   const float outscale = cc.kc * cc.scale;
   const int nvar = NV == 1 ? 1 : a.var.n;
@@ -272,15 +321,29 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
       fo[j].init(ro.freqs[k < k1 ? k : k1 - 1], M);
       h[j] = hist + (j * slots) * kWave + lane;
     }
-    // fold, bin and accumulate every observation of the curve
-    accumulate<PH, FL, SRC>(rc, n, fo, h, lane);
+    // fold, bin and accumulate every observation of the curve (of this wave's slice)
+    if (SH == 1 || n > 0) accumulate<PH, FL, SRC>(rc, n, fo, h, lane);
     // reduce each sub-tile of 64 frequencies, store, and pick peaks
 #pragma unroll
     for (int j = 0; j < FL; ++j) {
       const int kb = kt + j * kWave;
       if (kb >= k1) break;
       float sv[NV];
-      if constexpr (NV == 1) {
+      if constexpr (SH > 1 && NV == 1) {
+        __syncthreads();  // every slice is in the histogram
+        reduce_parts<PH, SH>(h[j], M, wave, cc.ia2q, part, lane);
+        __syncthreads();  // part sums visible, histogram clear for the next sub-tile
+        if (!lead) continue;
+        float s = 0.f;
+#pragma unroll
+        for (int p = 0; p < kSumParts; ++p) s += part[p * kWave + lane];
+        sv[0] = s;
+      } else if constexpr (SH > 1) {
+        __syncthreads();  // every slice is in the histogram
+        if (lead) reduce_variants<PH, NV>(h[j], M, cc.ia2q, a.var, sv);
+        __syncthreads();  // histogram clear for the next sub-tile
+        if (!lead) continue;
+      } else if constexpr (NV == 1) {
         sv[0] = reduce_hist<PH>(h[j], M, cc.ia2q);
       } else {
         reduce_variants<PH, NV>(h[j], M, cc.ia2q, a.var, sv);
@@ -297,7 +360,7 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
       pend = kb + kWave - 1 < k1 - 1;
     }
   }
-  if (PK) {
+  if (PK && lead) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       if (v < nvar) {
@@ -308,11 +371,15 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
   }
 }
 
-// The DPP-source shapes serve large M, where LDS admits at most ~2 waves per
-// SIMD; telling the compiler so lets it spend registers on overlapping the
-// FP64 fold chains instead of minimising them.
-template <int PH, int FL, int PK, int SRC, int NV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == SRC_DPP ? 2 : 10))) void batched_kernel(BatchArgs a, const Rec* __restrict__ rec,
+// The DPP-source shapes with private histograms serve large M, where LDS
+// admits at most ~2 waves per SIMD; telling the compiler so lets it spend
+// registers on overlapping the FP64 fold chains instead of minimising them.
+//
+// LDS: SH == 1: one histogram set per wave, [wave][j][bin][lane].  SH > 1
+// (the workgroup is the SH waves of one histogram): [bin][lane], then the
+// part sums [kSumParts][lane] (float) and the item index of the group.
+template <int PH, int FL, int PK, int SRC, int NV, int SH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == SRC_DPP && SH == 1 ? 2 : 10))) void batched_kernel(BatchArgs a, const Rec* __restrict__ rec,
                                                       const int64_t* __restrict__ offsets,
                                                       const CurveConst* __restrict__ ccs,
                                                       const double* __restrict__ freqs,
@@ -320,17 +387,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
   const RO ro{rec, offsets, ccs, freqs};
   extern __shared__ __align__(16) uint64_t lds[];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // uniform: keeps slice loads scalar
   const int slots = a.n_bins + 1;
-  uint64_t* hist = lds + (size_t)wave * FL * slots * kWave;  // this wave's histograms: [j][bin][lane]
-  for (int s = 0; s < FL * slots; ++s) hist[s * kWave + lane] = 0;
+  uint64_t* hist = lds + (SH > 1 ? (size_t)0 : (size_t)wave * FL * slots * kWave);
+  float* part = reinterpret_cast<float*>(lds + (size_t)slots * kWave);
+  int* group_item = reinterpret_cast<int*>(part + kSumParts * kWave);
+  if (SH > 1) {
+    for (int s = wave; s < slots; s += SH) hist[s * kWave + lane] = 0;
+  } else {
+    for (int s = 0; s < FL * slots; ++s) hist[s * kWave + lane] = 0;
+  }
   for (;;) {
     int it = 0;
-    if (lane == 0) it = (int)atomicAdd(a.queue, 1u);
-    it = __builtin_amdgcn_readfirstlane(it);
+    if (SH > 1) {
+      // one pop per workgroup; the previous item's barriers order this write
+      // after every wave's read of the previous index
+      if (threadIdx.x == 0) *group_item = (int)atomicAdd(a.queue, 1u);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(*group_item);
+    } else {
+      if (lane == 0) it = (int)atomicAdd(a.queue, 1u);
+      it = __builtin_amdgcn_readfirstlane(it);
+    }
     if (it >= a.n_items) break;
     const Item item = items[it];
-    process_item<PH, FL, PK, SRC, NV>(a, ro, item, hist, lane);
+    process_item<PH, FL, PK, SRC, NV, SH>(a, ro, item, hist, lane, wave, part);
   }
   // The last wave out resets the queue, so the next launch (or graph replay)
   // starts from zero without a memset.
@@ -344,18 +425,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
   }
 }
 
-template <int PH, int FL, int PK, int SRC, int NV>
+template <int PH, int FL, int PK, int SRC, int NV, int SH>
 void* batched_ptr() {
-  return (void*)&batched_kernel<PH, FL, PK, SRC, NV>;
+  return (void*)&batched_kernel<PH, FL, PK, SRC, NV, SH>;
 }
 
-template <int PH, int FL, int SRC, int NV>
+template <int PH, int FL, int SRC, int NV, int SH = 1>
 void* batched_ptr_k(int pk) {
-  return pk ? batched_ptr<PH, FL, 1, SRC, NV>() : batched_ptr<PH, FL, 0, SRC, NV>();
+  return pk ? batched_ptr<PH, FL, 1, SRC, NV, SH>() : batched_ptr<PH, FL, 0, SRC, NV, SH>();
+}
+
+template <int PH, int SRC, int NV>
+void* batched_ptr_sh(int pk, int share) {
+  return share == 4 ? batched_ptr_k<PH, 1, SRC, NV, 4>(pk) : batched_ptr_k<PH, 1, SRC, NV, 2>(pk);
 }
 
 template <int PH>
-void* batched_ptr_src(int fl, int pk, int src, int nv) {
+void* batched_ptr_src(int fl, int pk, int src, int nv, int share) {
+  if (share > 1) {
+    if constexpr (PH == PH_DF32 || PH == PH_FP32) {
+      return nullptr;
+    } else {
+      if (fl != 1) return nullptr;
+      if (nv > 1) return src == SRC_DPP ? batched_ptr_sh<PH, SRC_DPP, kMaxVariants>(pk, share)
+                                        : batched_ptr_sh<PH, SRC_SCALAR, kMaxVariants>(pk, share);
+      return src == SRC_DPP ? batched_ptr_sh<PH, SRC_DPP, 1>(pk, share) : batched_ptr_sh<PH, SRC_SCALAR, 1>(pk, share);
+    }
+  }
   if (nv > 1) return src == SRC_DPP ? batched_ptr_k<PH, 1, SRC_DPP, kMaxVariants>(pk)
                                     : batched_ptr_k<PH, 1, SRC_SCALAR, kMaxVariants>(pk);
   if (src == SRC_DPP) return batched_ptr_k<PH, 1, SRC_DPP, 1>(pk);
@@ -365,13 +461,14 @@ void* batched_ptr_src(int fl, int pk, int src, int nv) {
 
 // Instantiated shapes: two frequencies per lane exist for the FP64 folds with
 // scalar point loads and one variant only; several variants take one
-// frequency per lane.
-void* batched_fn(int phase, int fl, int pk, int src, int nv) {
+// frequency per lane; shared histograms (2 or 4 waves) exist for the FP64
+// folds with one frequency per lane.  Null for a shape that is not built.
+void* batched_fn(int phase, int fl, int pk, int src, int nv, int share) {
   switch (phase) {
-    case PH_FP64: return batched_ptr_src<PH_FP64>(fl, pk, src, nv);
-    case PH_LISTING: return batched_ptr_src<PH_LISTING>(fl, pk, src, nv);
-    case PH_DF32: return batched_ptr_src<PH_DF32>(1, pk, src, nv);
-    default: return batched_ptr_src<PH_FP32>(1, pk, src, nv);
+    case PH_FP64: return batched_ptr_src<PH_FP64>(fl, pk, src, nv, share);
+    case PH_LISTING: return batched_ptr_src<PH_LISTING>(fl, pk, src, nv, share);
+    case PH_DF32: return batched_ptr_src<PH_DF32>(1, pk, src, nv, share);
+    default: return batched_ptr_src<PH_FP32>(1, pk, src, nv, share);
   }
 }
 
@@ -379,18 +476,26 @@ void* batched_fn(int phase, int fl, int pk, int src, int nv) {
 
 int topk_capacity(int k) { return k <= 0 ? 0 : (k <= 8 ? 8 : 16); }
 
+bool batched_shape_built(const Shape& shape, int phase, int n_var) {
+  return batched_fn(phase, shape.freqs_per_lane, 0, shape.point_source, n_var, shape.share) != nullptr;
+}
+
 size_t batched_lds_bytes(const Shape& shape, int n_bins) {
-  return (size_t)shape.waves_per_group * shape.freqs_per_lane * (size_t)(n_bins + 1) * kWave * sizeof(uint64_t);
+  const size_t hist = (size_t)(n_bins + 1) * kWave * sizeof(uint64_t);
+  if (shape.share > 1) return hist + (size_t)kSumParts * kWave * sizeof(float) + 16;
+  return (size_t)shape.waves_per_group * shape.freqs_per_lane * hist;
 }
 
 hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, int n_var, size_t lds_bytes, int* out) {
-  void* fn = batched_fn(phase, shape.freqs_per_lane, topk > 0, shape.point_source, n_var);
+  void* fn = batched_fn(phase, shape.freqs_per_lane, topk > 0, shape.point_source, n_var, shape.share);
+  if (fn == nullptr) return hipErrorInvalidDeviceFunction;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, shape.waves_per_group * kWave, lds_bytes);
 }
 
 hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int grid_groups, size_t lds_bytes,
                           hipStream_t s) {
-  void* fn = batched_fn(phase, shape.freqs_per_lane, a.topk > 0, shape.point_source, a.var.n);
+  void* fn = batched_fn(phase, shape.freqs_per_lane, a.topk > 0, shape.point_source, a.var.n, shape.share);
+  if (fn == nullptr) return hipErrorInvalidDeviceFunction;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (e != hipSuccess) return e;
   BatchArgs args = a;

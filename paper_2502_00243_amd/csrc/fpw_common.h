@@ -186,21 +186,36 @@ __device__ __forceinline__ void take_block(uint64_t* h, int M, int m0, uint64_t 
   for (int q = 0; q < kReduceBlock; ++q) f[q] = lds_take(h + min(m0 + q, M) * kWave);
 }
 
+// S is summed in one fixed order whatever the launch shape: the read blocks
+// of 8 bins are split into kSumParts consecutive parts (part p = blocks
+// [p nb / 4, (p+1) nb / 4) of nb), each part's terms are added in bin order
+// from zero, and the part sums are added in part order.  A histogram shared
+// by 2 or 4 waves gives each wave whole parts, so private and shared
+// histograms (and the multi-M reduction) produce bit-identical S.
+constexpr int kSumParts = 4;
+__device__ __forceinline__ int part_block(int p, int n_blocks) { return p * n_blocks / kSumParts; }
+
 // Reads and clears one lane's histogram (slot m at h + 64 m) and returns
-// sum_m Y_m^2 / (W_m + 1/alpha^2) in fixed-point units, bins in order.
+// sum_m Y_m^2 / (W_m + 1/alpha^2) in fixed-point units, in the order above.
 template <int PH>
 __device__ __forceinline__ float reduce_hist(uint64_t* h, int M, float ia2q) {
   const uint64_t wrap = take_wrap_slot<PH>(h, M);
-  float acc = 0.f;
-  for (int m0 = 0; m0 < M; m0 += kReduceBlock) {
-    uint64_t f[kReduceBlock];
-    take_block<PH>(h, M, m0, f);
-    if (m0 == 0) f[0] += wrap;
+  const int nb = (M + kReduceBlock - 1) / kReduceBlock;
+  float s = 0.f;
+  for (int p = 0; p < kSumParts; ++p) {
+    float acc = 0.f;
+    for (int b = part_block(p, nb); b < part_block(p + 1, nb); ++b) {
+      const int m0 = b * kReduceBlock;
+      uint64_t f[kReduceBlock];
+      take_block<PH>(h, M, m0, f);
+      if (m0 == 0) f[0] += wrap;
 #pragma unroll
-    for (int q = 0; q < kReduceBlock; ++q)
-      if (m0 + q < M) acc = add_bin_term(acc, f[q], ia2q);
+      for (int q = 0; q < kReduceBlock; ++q)
+        if (m0 + q < M) acc = add_bin_term(acc, f[q], ia2q);
+    }
+    s += acc;
   }
-  return acc;
+  return s;
 }
 
 // Whole-wave neighbour exchange through DPP (no LDS traffic): the value of

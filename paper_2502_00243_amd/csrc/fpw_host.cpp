@@ -77,7 +77,7 @@ struct fpw_plan_s {
   DevBuf t, y, dy, offsets, freqs, rec, cc, tau64, w64, wx64;
   // work queue and peak-selection scratch
   DevBuf items, queue, cand_val, cand_idx, edge, slot_k0, curve_slot;
-  fpw::Shape shape{1, 1, 4096, 0};
+  fpw::Shape shape{1, 1, 4096, 0, 1};
   fpw::Variants var{};        // periodogram variants (multi-M reuse); var.n >= 1
   std::vector<int32_t> var_bins;  // bin count of each variant
   int grid_groups = 0;
@@ -117,6 +117,7 @@ struct fpw_plan_s {
   // marginalised baseline (App. A general case)
   bool bm = false;
   int bm_grid = 0;
+  int bm_share = 1;  // waves per histogram of the baseline kernel
   DevBuf bm_rec, bm_const, bm_S;
   // profiling events: before prepare, after prepare, after batched, after merge
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -133,8 +134,17 @@ struct fpw_plan_s {
 namespace {
 
 const int kWave = 64;
-// Smallest M for which the default point source is the DPP broadcast.
+// Smallest M for which, by default, two waves share one histogram (and four
+// from kShare4MinBins): a private histogram of M+1 slots per wave would
+// leave room for too few waves per CU (measured on 1000 ZTF-like curves:
+// M = 20 +10 % with two waves, M = 50 +73 % with four, M = 10 even).
+const int kShare2MinBins = 16;
+const int kShare4MinBins = 32;
+// Smallest M for which the default point source is the DPP broadcast, with
+// private histograms and with shared ones (their extra waves hide the scalar
+// loads' waits up to M ~ 100).
 const int kDppMinBins = 32;
+const int kDppMinBinsShared = 128;
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -158,6 +168,15 @@ fpw_status check_options(const fpw_options& o) {
   if (o.point_source < 0 || o.point_source > 2) return fail(FPW_EINVAL, "point_source must be 0, 1 or 2");
   if (o.point_source == 2 && o.freqs_per_lane == 2)
     return fail(FPW_EUNSUPPORTED, "DPP point broadcast is built for one frequency per lane");
+  if (!(o.hist_share == 0 || o.hist_share == 1 || o.hist_share == 2 || o.hist_share == 4))
+    return fail(FPW_EINVAL, "hist_share must be 0, 1, 2 or 4");
+  if (o.hist_share > 1) {
+    if (o.freqs_per_lane == 2) return fail(FPW_EUNSUPPORTED, "a shared histogram is built for one frequency per lane");
+    if (o.waves_per_group != 0 && o.waves_per_group != o.hist_share)
+      return fail(FPW_EINVAL, "with hist_share %d the workgroup has %d waves (waves_per_group 0 or %d)", o.hist_share,
+                  o.hist_share, o.hist_share);
+    if (o.phase >= FPW_PHASE_DF32) return fail(FPW_EUNSUPPORTED, "a shared histogram is built for the FP64 phase modes");
+  }
   int nvar = 1;
   for (int d = 0; d < FPW_MAX_DERIVED && o.derived_bins[d] != 0; ++d) {
     const int m = o.derived_bins[d];
@@ -293,6 +312,8 @@ int default_chunk(const fpw_plan_s* p, const fpw::Shape& s, int total_waves) {
 }
 
 fpw_status configure_shape(fpw_plan_s* p, fpw::Shape s) {
+  if (!fpw::batched_shape_built(s, p->opt.phase, p->var.n))
+    return fail(FPW_EUNSUPPORTED, "no batched kernel is built for this launch shape");
   const size_t lds = fpw::batched_lds_bytes(s, p->opt.n_bins);
   if (lds > 160 * 1024) return fail(FPW_EUNSUPPORTED, "LDS %zu bytes per workgroup exceeds 160 KiB", lds);
   int per_cu = 0;
@@ -301,7 +322,9 @@ fpw_status configure_shape(fpw_plan_s* p, fpw::Shape s) {
   p->shape = s;
   p->lds_bytes = lds;
   p->grid_groups = per_cu * p->n_cu;
-  if (s.chunk_freqs <= 0) p->shape.chunk_freqs = default_chunk(p, s, p->grid_groups * s.waves_per_group);
+  // a group of waves sharing a histogram takes one item at a time
+  const int consumers = p->grid_groups * (s.share > 1 ? 1 : s.waves_per_group);
+  if (s.chunk_freqs <= 0) p->shape.chunk_freqs = default_chunk(p, s, consumers);
   p->shape.chunk_freqs = round_up(p->shape.chunk_freqs, s.freqs_per_lane * kWave);
   return FPW_OK;
 }
@@ -337,7 +360,7 @@ fpw_status upload_items(fpw_plan_s* p) {
 
 // Persistent workgroups actually launched: never more than the items can keep busy.
 int launch_groups(const fpw_plan_s* p, int n_items) {
-  const int wpg = p->shape.waves_per_group;
+  const int wpg = p->shape.share > 1 ? 1 : p->shape.waves_per_group;
   const int need = (n_items + wpg - 1) / wpg;
   return std::max(1, std::min(p->grid_groups, need));
 }
@@ -492,6 +515,7 @@ fpw_status enqueue_bm_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hi
   a.n_freq = (int32_t)p->n_freq;
   a.n_bins = p->opt.n_bins;
   a.n_terms = p->opt.baseline_terms;
+  a.share = p->bm_share;
   a.S = Sd;
   a.queue = p->queue.as<uint32_t>();
   FPW_HIP(fpw::launch_bm(a, p->opt.phase, p->bm_grid, s), "baseline kernel");
@@ -543,20 +567,24 @@ std::string tune_key(const fpw_plan_s* p) {
   return k.str();
 }
 
-// Cache file: one line per key, "key fl waves chunk source".
+// Cache file: one line per key, "key fl waves chunk source share" (a line
+// without the share field means private histograms).
 bool cache_lookup(const char* path, const std::string& key, fpw::Shape* s) {
   if (!path) return false;
   std::ifstream f(path);
-  std::string k;
-  int fl, w, ch, src;
-  while (f >> k >> fl >> w >> ch >> src) {
-    if (k == key) {
-      s->freqs_per_lane = fl;
-      s->waves_per_group = w;
-      s->chunk_freqs = ch;
-      s->point_source = src;
-      return true;
-    }
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream in(line);
+    std::string k;
+    int fl, w, ch, src, sh = 1;
+    if (!(in >> k >> fl >> w >> ch >> src) || k != key) continue;
+    if (!(in >> sh)) sh = 1;
+    s->freqs_per_lane = fl;
+    s->waves_per_group = w;
+    s->chunk_freqs = ch;
+    s->point_source = src;
+    s->share = sh;
+    return true;
   }
   return false;
 }
@@ -570,7 +598,8 @@ void cache_store(const char* path, const std::string& key, const fpw::Shape& s) 
     while (f >> k && std::getline(f, rest)) lines[k] = rest;
   }
   std::ostringstream v;
-  v << " " << s.freqs_per_lane << " " << s.waves_per_group << " " << s.chunk_freqs << " " << s.point_source;
+  v << " " << s.freqs_per_lane << " " << s.waves_per_group << " " << s.chunk_freqs << " " << s.point_source << " "
+    << s.share;
   lines[key] = v.str();
   std::ofstream f(path, std::ios::trunc);
   for (auto& kv : lines) f << kv.first << kv.second << "\n";
@@ -593,7 +622,11 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
   for (int src = 0; src <= 1; ++src)
     for (int fl = 1; fl <= (src == 1 ? 1 : fls); ++fl)
       for (int w : {1, 2})
-        for (int cm : {1, 4}) cands.push_back(fpw::Shape{fl, w, -cm, src});
+        for (int cm : {1, 4}) cands.push_back(fpw::Shape{fl, w, -cm, src, 1});
+  // histograms shared by 2 or 4 waves (FP64 folds)
+  if (p->opt.phase <= FPW_PHASE_FP64_LISTING)
+    for (int src = 0; src <= 1; ++src)
+      for (int sh : {2, 4}) cands.push_back(fpw::Shape{1, sh, -1, src, sh});
   // calibration slice: about 2e9 evaluations
   const double target = 2e9;
   const double per_curve = (double)p->n_points / p->n_curves * (double)p->n_freq;
@@ -760,10 +793,17 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
     // Large M leaves room for few waves per CU; their scalar-load waits then
     // stall the LDS atomics, so the DPP broadcast source is the default there.
-    const int src = o.point_source ? o.point_source - 1 : (o.n_bins >= kDppMinBins ? 1 : 0);
-    const int fl = (src == 1 || p->var.n > 1) ? 1 : (o.freqs_per_lane ? o.freqs_per_lane : 1);
-    fpw::Shape sh{fl, o.waves_per_group ? o.waves_per_group : 1, o.chunk_freqs, src};
-    if (o.autotune && !o.freqs_per_lane && !o.waves_per_group && !o.chunk_freqs && !o.point_source) {
+    int share = o.hist_share;
+    if (share == 0) {  // by M, where a shared histogram is built and no other group shape was asked for
+      const bool can = o.phase <= FPW_PHASE_FP64_LISTING && o.freqs_per_lane != 2 && o.waves_per_group == 0;
+      share = !can ? 1 : (o.n_bins >= kShare4MinBins ? 4 : (o.n_bins >= kShare2MinBins ? 2 : 1));
+    }
+    const int src = o.point_source ? o.point_source - 1
+                                   : (o.n_bins >= (share > 1 ? kDppMinBinsShared : kDppMinBins) ? 1 : 0);
+    const int fl = (src == 1 || p->var.n > 1 || share > 1) ? 1 : (o.freqs_per_lane ? o.freqs_per_lane : 1);
+    const int wpg = share > 1 ? share : (o.waves_per_group ? o.waves_per_group : 1);
+    fpw::Shape sh{fl, wpg, o.chunk_freqs, src, share};
+    if (o.autotune && !o.freqs_per_lane && !o.waves_per_group && !o.chunk_freqs && !o.point_source && !o.hist_share) {
       st = autotune(p, s);
     } else {
       st = configure_shape(p, sh);
@@ -777,7 +817,12 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
       FPW_HIP(p->bm_const.alloc((size_t)n_curves * sizeof(fpw::BaseConst)), "alloc baseline constants");
       FPW_HIP(p->bm_S.alloc((size_t)n_curves * (size_t)n_freq * sizeof(float)), "alloc baseline periodogram");
       int per_cu = 0;
-      FPW_HIP(fpw::bm_groups_per_cu(o.phase, o.n_bins, o.baseline_terms, &per_cu), "baseline kernel occupancy");
+      // histograms of more than ~1/12 of the LDS are shared by four waves (measured: K = 3, M = 20
+      // 12 % faster than private, two waves 3 %; K = 1, M = 20, 10 KiB, slower shared)
+      const size_t hb = fpw::bm_lds_bytes(o.n_bins, o.baseline_terms, 1);
+      p->bm_share = o.hist_share ? o.hist_share : (hb > 13 * 1024 ? 4 : 1);
+      FPW_HIP(fpw::bm_groups_per_cu(o.phase, o.n_bins, o.baseline_terms, p->bm_share, &per_cu),
+              "baseline kernel occupancy");
       p->bm_grid = std::max(1, std::min(std::max(1, per_cu) * p->n_cu, p->n_items));
     }
     FPW_HIP(hipStreamSynchronize(s), "plan sync");
@@ -1055,12 +1100,14 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   info->point_source = p->shape.point_source + 1;
   info->n_variants = p->var.n;
   info->kernel = p->mfma ? 1 : (p->bm ? 2 : 0);
+  info->hist_share = p->shape.share;
   if (p->bm) {
     info->grid_groups = p->bm_grid;
-    info->waves_per_group = 1;
+    info->waves_per_group = p->bm_share;
     info->freqs_per_lane = 1;
-    info->point_source = 1;
-    info->lds_bytes = (int32_t)fpw::bm_lds_bytes(p->opt.n_bins, p->opt.baseline_terms);
+    info->point_source = 2;  // vector loads + DPP broadcast
+    info->hist_share = p->bm_share;
+    info->lds_bytes = (int32_t)fpw::bm_lds_bytes(p->opt.n_bins, p->opt.baseline_terms, p->bm_share);
   }
   if (p->mfma) {
     info->grid_groups = p->sh_grid_x * p->sh_grid_y;
@@ -1070,6 +1117,7 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
     info->waves_per_group = fpw::kSharedWaves;
     info->freqs_per_lane = 0;
     info->point_source = 0;
+    info->hist_share = 0;
   }
   return FPW_OK;
 }

@@ -226,14 +226,15 @@ struct BmArgs {
   const Item* items;
   int32_t n_items, n_freq, n_bins;
   int32_t n_terms;   // baseline terms K (1..3); K = 1 needs no second sum
+  int32_t share;     // waves per histogram (1, 2, 4): the workgroup size in waves
   float* S;          // [n_curves * n_freq]
   uint32_t* queue;   // [2], self-resetting as for the batched kernel
 };
 
 hipError_t launch_bm_prepare(const BmPrepArgs& a, hipStream_t s);
 hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s);
-hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int* out);
-size_t bm_lds_bytes(int n_bins, int n_terms);
+hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int share, int* out);
+size_t bm_lds_bytes(int n_bins, int n_terms, int share);
 
 // Launch shapes of the batched kernel.
 struct Shape {
@@ -241,6 +242,7 @@ struct Shape {
   int waves_per_group;  // 1, 2 or 4
   int chunk_freqs;      // frequencies per work item
   int point_source;     // 0: scalar loads, 1: vector loads + DPP broadcast (one frequency per lane)
+  int share;            // waves per histogram: 1 (private), or 2 / 4 = waves_per_group (one item per group)
 };
 
 // Launchers; each returns the hipError_t of its launch.
@@ -262,6 +264,8 @@ void shared_shape(int n_bins, int* nb, int* fw);
 
 // LDS bytes the batched kernel needs per workgroup.
 size_t batched_lds_bytes(const Shape& shape, int n_bins);
+// Whether the batched kernel is built for this shape, phase mode and variant count.
+bool batched_shape_built(const Shape& shape, int phase, int n_var);
 // Persistent workgroups per CU the batched kernel reaches for this shape.
 hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, int n_var, size_t lds_bytes, int* out);
 // Top-k list length the kernels are instantiated for (8 or 16; 0 without peaks).

@@ -59,6 +59,7 @@ class Options(ctypes.Structure):
         ("shared_kernel", ctypes.c_int32),
         ("baseline_terms", ctypes.c_int32),
         ("baseline_scale", ctypes.c_double),
+        ("hist_share", ctypes.c_int32),
     ]
 
 
@@ -81,6 +82,7 @@ class PlanInfo(ctypes.Structure):
         ("point_source", ctypes.c_int32),
         ("n_variants", ctypes.c_int32),
         ("kernel", ctypes.c_int32),
+        ("hist_share", ctypes.c_int32),
     ]
 
 
@@ -158,7 +160,7 @@ def default_options() -> Options:
 def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="fp64", stat_scale="eq1", topk=0,
                  inv_alpha2=0.0, autotune=False, use_graph=True, freqs_per_lane=0, waves_per_group=0, chunk_freqs=0,
                  tune_cache=None, profile=False, point_source=0, derived_bins=(), all_offsets=False,
-                 shared_kernel=0, baseline_terms=0, baseline_scale=1.0) -> Options:
+                 shared_kernel=0, baseline_terms=0, baseline_scale=1.0, hist_share=0) -> Options:
     o = default_options()
     o.n_bins = int(n_bins)
     o.center = CENTER[center] if isinstance(center, str) else int(center)
@@ -184,6 +186,7 @@ def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="
     o.shared_kernel = SHARED_KERNEL[shared_kernel] if isinstance(shared_kernel, str) else int(shared_kernel)
     o.baseline_terms = int(baseline_terms)
     o.baseline_scale = float(baseline_scale)
+    o.hist_share = int(hist_share)
     return o
 
 

@@ -36,6 +36,7 @@ def test_options_defaults():
     o = fpw.default_options()
     assert (o.n_bins, o.center, o.tref_mode, o.phase, o.stat_scale, o.topk) == (10, 0, 0, 0, 0, 0)
     assert o.inv_alpha2 == 0.0 and o.use_graph == 1 and o.autotune == 0
+    assert o.hist_share == 0 and o.baseline_terms == 0 and o.baseline_scale == 1.0
     assert fpw.load().fpw_version().decode().startswith("fpw ")
 
 
@@ -77,6 +78,11 @@ CASES = [
     ("derived M twice", dict(n_bins=12, opts=dict(derived_bins=(6, 6))), fpw.EINVAL),
     ("too many variants", dict(n_bins=40, opts=dict(derived_bins=(5, 10), all_offsets=True)), fpw.EUNSUPPORTED),
     ("two freqs per lane with variants", dict(n_bins=12, opts=dict(derived_bins=(6,), freqs_per_lane=2)), fpw.EUNSUPPORTED),
+    ("bad hist share", dict(opts=dict(hist_share=3)), fpw.EINVAL),
+    ("negative hist share", dict(opts=dict(hist_share=-2)), fpw.EINVAL),
+    ("hist share with other waves per group", dict(opts=dict(hist_share=2, waves_per_group=4)), fpw.EINVAL),
+    ("hist share with two freqs per lane", dict(opts=dict(hist_share=2, freqs_per_lane=2)), fpw.EUNSUPPORTED),
+    ("hist share in df32", dict(opts=dict(hist_share=4, phase="df32")), fpw.EUNSUPPORTED),
 ]
 
 
@@ -216,3 +222,28 @@ def test_c_client_compiles_links_and_checks_arguments(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "C ABI checks ok" in r.stdout
+
+
+@pytest.mark.parametrize("struct", ["fpw_options", "fpw_plan_info"])
+def test_binding_structs_match_header_layout(tmp_path, struct):
+    """The ctypes mirrors of the header's structs have the C compiler's field offsets and size."""
+    import shutil
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirror = {"fpw_options": fpw.Options, "fpw_plan_info": fpw.PlanInfo}[struct]
+    names = [f[0] for f in mirror._fields_]
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("{n} %zu\\n", offsetof({struct}, {n}));\n' for n in names)
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"fpw.h\"\nint main(void) {\n"
+                   f'  printf("sizeof %zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    exe = str(tmp_path / "layout")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", str(src), "-I", os.path.join(root, "include"), "-o", exe],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = dict(line.split() for line in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n") if line)
+    assert int(out["sizeof"]) == ctypes.sizeof(mirror)
+    for n in names:
+        assert int(out[n]) == getattr(mirror, n).offset, n

@@ -166,3 +166,39 @@ def test_ztf1000_with_baseline_sampled():
         parity.assert_s_close(S[c, fi], ref, S_abs, what=f"curve {c}")
     parity.assert_topk_matches_rule(S[:50], idx.cpu().numpy()[:50], val.cpu().numpy()[:50], 5)
     plan.close()
+
+
+@pytest.mark.parametrize("M,K,share,n_max", [(20, 3, 2, 260), (64, 3, 4, 260), (1, 2, 2, 3), (7, 1, 4, 3),
+                                             (40, 2, 2, 260), (13, 3, 4, 5)],
+                         ids=lambda v: str(v))
+def test_baseline_kernel_shared_histograms(M, K, share, n_max):
+    """Histograms shared by 2 or 4 waves (each folds a slice of the observations, the epilogue
+    sums are split by bins): same parity bar, also for curves with fewer observations than waves."""
+    _say(f"baseline shared histograms M={M} K={K} share={share} n_max={n_max}")
+    b = synth.random_batch(66 + M + n_max, 10, 1, n_max, FREQS, M)
+    y = _with_drift(b, 0.3)
+    plan = fpw.Plan(b.offsets, b.t, y, b.dy, b.freqs, M, baseline_terms=K, hist_share=share, topk=3)
+    info = plan.info()
+    assert (info.kernel, info.hist_share, info.waves_per_group) == (2, share, share)
+    S, idx, val = plan.eval()
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    for c in range(b.n_curves):
+        ref, S_abs = _reference(plan, b, y, K, 1.0, {}, c)
+        parity.assert_s_close(S[c], ref, S_abs, what=f"curve {c}")
+    parity.assert_topk_matches_rule(S, idx.cpu().numpy(), val.cpu().numpy(), 3)
+    # private histograms on the same data: the FP64 epilogue sums differ only in order
+    priv = fpw.Plan(b.offsets, b.t, y, b.dy, b.freqs, M, baseline_terms=K, hist_share=1)
+    Sp = priv.eval(topk=False)[0].cpu().numpy()
+    np.testing.assert_allclose(S, Sp, rtol=1e-6, atol=1e-9 * float(np.abs(Sp).max()))
+    for p in (plan, priv):
+        p.close()
+
+
+def test_baseline_default_share_by_histogram_size():
+    _say("baseline default share")
+    b = synth.random_batch(67, 4, 20, 80, FREQS, 10)
+    for M, K, sh in [(20, 1, 1), (20, 2, 4), (20, 3, 4), (26, 1, 1), (27, 1, 4), (40, 3, 4), (64, 2, 4)]:
+        p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, M, baseline_terms=K)
+        assert p.info().hist_share == sh, (M, K)
+        p.close()
