@@ -406,19 +406,22 @@ def bench_baseline(args):
         log(f"baseline K={K}: {wall * 1e3:.3f} ms/pass, kernel {kernel_ms:.3f} ms, {evals / wall / 1e9:.0f} G evals/s")
         res[f"K{K}"] = r
         plan.close()
-    # kernel time of the baseline kernel by histogram sharing (waves per histogram)
+    # kernel time of the baseline kernel by point source and histogram sharing (waves per histogram)
     shares = {}
     for K in (1, 2, 3):
-        for share in (1, 2, 4):
-            plan = fpw.Plan.from_batch(batch, topk=5, baseline_terms=K, hist_share=share, profile=True)
-            _, kms = _time_passes(plan, 3, 1, S_out=S, idx_out=idx, val_out=val)
-            shares[f"K{K}_share{share}"] = {"kernel_ms": float(np.median(kms[:, 1])),
-                                            "grid_groups": plan.info().grid_groups, "lds_bytes": plan.info().lds_bytes}
-            plan.close()
+        for src in ("scalar", "dpp"):
+            for share in (1, 2, 4):
+                plan = fpw.Plan.from_batch(batch, topk=5, baseline_terms=K, hist_share=share, point_source=src,
+                                           profile=True)
+                _, kms = _time_passes(plan, 3, 1, S_out=S, idx_out=idx, val_out=val)
+                shares[f"K{K}_{src}_share{share}"] = {"kernel_ms": float(np.median(kms[:, 1])),
+                                                      "grid_groups": plan.info().grid_groups,
+                                                      "lds_bytes": plan.info().lds_bytes}
+                plan.close()
     print(json.dumps({"workload": "baseline: 1000 ZTF-like curves, 1e5 freqs 0.05-50 /d, M=20, periodogram + top-5, "
                                   "marginalised Chebyshev baseline of K terms (K=0: Eq. 1)",
                       "evals": evals, "value": res["K3"]["G_evals_per_s"], "unit": "G evals/s", "per_K": res,
-                      "kernel_ms_by_share": shares}),
+                      "kernel_ms_by_shape": shares}),
           flush=True)
 
 

@@ -106,8 +106,9 @@ typedef struct {
   int32_t chunk_freqs;    /* launch shape override, 0 = default: frequencies per work item */
   const char* tune_cache; /* path of a text cache of autotune results; NULL = none */
   int32_t point_source;   /* launch shape override: how a wave fetches observations.
-                             0 = default (by M), 1 = scalar loads, 2 = vector loads + DPP
-                             broadcast (one frequency per lane) */
+                             0 = default (by M; scalar loads for the baseline kernel),
+                             1 = scalar loads, 2 = vector loads + DPP broadcast (one
+                             frequency per lane) */
   int32_t derived_bins[FPW_MAX_DERIVED];
                           /* multi-M reuse (Sec. 3.4): further bin counts M' < n_bins that
                              divide n_bins, 0-terminated.  Their sums are combined from the
@@ -139,7 +140,7 @@ typedef struct {
                              summed in one fixed order for every launch shape, so results are
                              bit-identical to private histograms.  With baseline_terms > 0 it
                              sets the baseline kernel's sharing instead; 0 = by histogram size
-                             (1 up to 13 KiB per wave, 4 above). */
+                             per wave (1 below 8704 bytes, 2 below 16896, else 4). */
 } fpw_options;
 
 /* Kernel of a shared-timestamp plan (fpw_plan_shared). */

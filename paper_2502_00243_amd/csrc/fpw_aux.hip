@@ -313,12 +313,12 @@ __global__ __launch_bounds__(kPrepThreads) void bm_prepare_kernel(BmPrepArgs a) 
       const int64_t yq = (int64_t)rint(wx * s_y);
       const int64_t z1 = (int64_t)rint(w * T1 * s_z);
       const int64_t z2 = (int64_t)rint(w * T2 * s_z);
-      RecB r;
+      Rec r;
       r.tau_bits = (uint64_t)__double_as_longlong(a.t[p] - tref);
       r.pk = ((uint64_t)wqd << 32) + (uint64_t)yq;
-      r.pz = (uint64_t)(z2 * 4294967296LL + z1);
-      r.pad = 0;
       a.rec[p] = r;
+      if (a.n_terms >= 3) a.z64[p] = (uint64_t)(z2 * 4294967296LL + z1);
+      if (a.n_terms == 2) a.z32[p] = (uint32_t)z1;
       const double wt = wqd / s_w, yt = (double)yq / s_y, a1 = (double)z1 / s_z, a2 = (double)z2 / s_z;
       h[0] += wt;
       h[1] += a1;

@@ -22,17 +22,19 @@ namespace {
 
 using namespace dev;
 
-// Observations reach the lanes as in the general kernel's vector source: the
-// lanes of each row of 16 load 16 consecutive records (one coalesced load),
-// and each record is then broadcast to its row with 64-bit DPP row_newbcast
-// moves.  Only vector-memory counters are waited on, so the LDS atomics of
-// earlier points stay in flight.
+// Where a wave's observations come from, as in the general kernel.
+//  BSRC_SCALAR: wave-uniform scalar loads of 8 records at a time into SGPRs;
+//    tau is a scalar operand of the fold, the packed words take one move each.
+//  BSRC_DPP: the lanes of each row of 16 load 16 consecutive records (one
+//    coalesced load) and each record is broadcast to its row with 64-bit DPP
+//    row_newbcast moves; only vector-memory counters are waited on.
+enum BmSource { BSRC_SCALAR = 0, BSRC_DPP = 1 };
 constexpr int kGroup = 16;
 
 // Extra sums per bin: none with one baseline term (Z_0 = beta W needs no sum
 // of its own), one 32-bit word (w T_1) with two, one 64-bit word (w T_1,
 // w T_2) with three.
-enum { NZ_NONE = 0, NZ_PAIR = 1, NZ_ONE = 2 };
+enum BmExtra { NZ_NONE = 0, NZ_PAIR = 1, NZ_ONE = 2 };
 
 template <int Q>
 __device__ __forceinline__ uint32_t row_bcast32(uint32_t v) {
@@ -45,15 +47,77 @@ __device__ __forceinline__ uint32_t lds_take32(uint32_t* p) {
   return __hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// One point q of the current group: fold, bin, and the sums.
-template <int PH, int NZ, int Q>
-__device__ __forceinline__ void bm_point(const RecB& cur, const Folder<PH>& fo, uint32_t M, uint64_t* hw, uint64_t* hz,
-                                         uint32_t* hz32) {
-  const uint32_t b0 = (uint32_t)fo.bin(row_bcast<Q>(cur.tau_bits));
-  const uint32_t b = min(b0, b0 - M);  // the fused fold reports bin 0 as M
-  lds_add(hw + b * kWave, row_bcast<Q>(cur.pk));
-  if (NZ == NZ_PAIR) lds_add(hz + b * kWave, row_bcast<Q>(cur.pz));
-  if (NZ == NZ_ONE) lds_add32(hz32 + b * kWave, row_bcast32<Q>(lo32(cur.pz)));
+// Histogram slot stride in 64-bit words: with the 64-bit pair the two sums
+// of a bin are interleaved, [m][2][lane], so the second atomic reuses the
+// first one's address with a constant offset; otherwise [m][lane].
+template <int NZ>
+constexpr int kSlotWords = (NZ == NZ_PAIR ? 2 : 1) * kWave;
+
+// The sums of one observation at the lane's bin b (0 <= b <= M; slot M is
+// the fused fold's name for bin 0 and is added to bin 0 when read).
+template <int NZ>
+__device__ __forceinline__ void bm_add(int b, uint64_t pk, uint64_t pz, uint64_t* hw, uint64_t* hz, uint32_t* hz32) {
+  lds_add(hw + b * kSlotWords<NZ>, pk);
+  if (NZ == NZ_PAIR) lds_add(hz + b * kSlotWords<NZ>, pz);
+  if (NZ == NZ_ONE) lds_add32(hz32 + b * kWave, lo32(pz));
+}
+
+// Baseline sums per observation as stored for NZ: 64-bit pair, 32-bit word, or none.
+template <int NZ>
+using ZWord = typename std::conditional<NZ == NZ_PAIR, uint64_t, uint32_t>::type;
+
+// Folds and adds observations [0, n) of rc / zc (n >= 1).
+template <int PH, int NZ, int SRC>
+__device__ __forceinline__ void bm_accumulate(const Rec* __restrict__ rc, const ZWord<NZ>* __restrict__ zc, int n,
+                                              const Folder<PH>& fo, uint64_t* hw, uint64_t* hz, uint32_t* hz32,
+                                              int lane) {
+  if (SRC == BSRC_SCALAR) {
+    int i = 0;
+    for (; i + kBatch <= n; i += kBatch) {
+      Rec r[kBatch];
+      ZWord<NZ> z[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) r[q] = rc[i + q];
+      if (NZ != NZ_NONE) {
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) z[q] = zc[i + q];
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+        bm_add<NZ>(fo.bin(r[q].tau_bits), uniform_to_vgpr(r[q].pk),
+                   NZ == NZ_PAIR ? uniform_to_vgpr((uint64_t)z[q]) : (NZ == NZ_ONE ? (uint64_t)z[q] : 0), hw, hz, hz32);
+    }
+    for (; i < n; ++i) {
+      const Rec r = rc[i];
+      const uint64_t z = NZ == NZ_NONE ? 0 : (uint64_t)zc[i];
+      bm_add<NZ>(fo.bin(r.tau_bits), uniform_to_vgpr(r.pk), NZ == NZ_PAIR ? uniform_to_vgpr(z) : z, hw, hz, hz32);
+    }
+  } else {
+    const int sub = lane & (kGroup - 1);
+    Rec cur = rc[sub < n ? sub : n - 1];
+    ZWord<NZ> curz = NZ == NZ_NONE ? 0 : zc[sub < n ? sub : n - 1];
+    for (int g = 0; g < n; g += kGroup) {
+      const int nxt = g + kGroup + sub;
+      const int ld = nxt < n ? nxt : n - 1;  // prefetch (clamped, in bounds)
+      const Rec next = rc[ld];
+      const ZWord<NZ> nextz = NZ == NZ_NONE ? 0 : zc[ld];
+      const int cnt = n - g;  // wave-uniform
+      auto point = [&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        bm_add<NZ>(fo.bin(row_bcast<q>(cur.tau_bits)), row_bcast<q>(cur.pk),
+                   NZ == NZ_PAIR ? row_bcast<q>((uint64_t)curz) : (uint64_t)row_bcast32<q>((uint32_t)curz), hw, hz, hz32);
+      };
+      if (cnt >= kGroup) {
+        static_for<0, kGroup>(point);  // a full group, straight-line
+      } else {
+        static_for<0, kGroup>([&](auto qc) {
+          if (decltype(qc)::value < cnt) point(qc);
+        });
+      }
+      cur = next;
+      curz = nextz;
+    }
+  }
 }
 
 // Per-lane sums of the FP64 epilogue over a range of bins: v^T L^-1 v, r = Z^T L^-1 v
@@ -63,15 +127,27 @@ struct BmSums {
 };
 constexpr int kBmSums = 10;
 
-// Reads and clears bins [mb, me) of one lane's histograms and returns their sums.
-template <int NZ>
-__device__ __forceinline__ BmSums bm_bins(uint64_t* hw, uint64_t* hz, uint32_t* hz32, int mb, int me,
+// Reads and clears bins [mb, me) of one lane's histograms and returns their
+// sums; the range that starts at bin 0 also takes the wrap slot M.
+template <int PH, int NZ>
+__device__ __forceinline__ BmSums bm_bins(uint64_t* hw, uint64_t* hz, uint32_t* hz32, int M, int mb, int me,
                                           const BaseConst& bc) {
   BmSums a{};
+  uint64_t wrap_w = 0, wrap_z = 0;
+  constexpr int SW = kSlotWords<NZ>;
+  if (PH == PH_FP64 && mb == 0 && me > 0) {
+    wrap_w = lds_take(hw + M * SW);
+    if (NZ == NZ_PAIR) wrap_z = lds_take(hz + M * SW);
+    if (NZ == NZ_ONE) wrap_z = lds_take32(hz32 + M * kWave);
+  }
   for (int m = mb; m < me; ++m) {
-    const uint64_t vw = lds_take(hw + m * kWave);
-    const uint64_t vz = NZ == NZ_PAIR ? lds_take(hz + m * kWave)
-                        : (NZ == NZ_ONE ? (uint64_t)(int64_t)(int32_t)lds_take32(hz32 + m * kWave) : (uint64_t)0);
+    uint64_t vw = lds_take(hw + m * SW);
+    uint64_t vz = NZ == NZ_PAIR ? lds_take(hz + m * SW) : (NZ == NZ_ONE ? (uint64_t)lds_take32(hz32 + m * kWave) : 0);
+    if (m == 0) {  // integer sums: adding the wrap slot is exact (modulo the word, like every addition)
+      vw += wrap_w;
+      vz += wrap_z;
+    }
+    if (NZ == NZ_ONE) vz = (uint64_t)(int64_t)(int32_t)lo32(vz);
     const uint32_t lw = lo32(vw), lz = lo32(vz);
     const uint32_t wq = hi32(vw) + (lw >> 31);
     const int32_t yq = (int32_t)lw;
@@ -116,15 +192,21 @@ __device__ __forceinline__ double bm_statistic(const BmSums& a, const BaseConst&
   return a.s1 + s2;
 }
 
-// Slots per histogram lane: M (weight, residual) words, then M extra words
-// ([m][lane]).  SH == 1: one wave per workgroup with its own histograms.
-// SH > 1: the SH waves of a workgroup share them; each folds a contiguous
-// slice of the curve's observations, then each takes the epilogue sums of a
-// contiguous range of bins, and wave 0 adds them (in wave order) and forms
-// S.  After the histograms: the partial sums [SH-1][10][lane] (FP64) and
-// the group's item index.
-template <int PH, int NZ, int SH>
-__global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const RecB* __restrict__ rec,
+// Slots per histogram lane: M+1 (weight, residual) words and M+1 extra
+// words (slot M is bin 0 seen through the fused fold): interleaved per bin
+// for the 64-bit pair, else the extra words after the (weight, residual)
+// words.  SH == 1:
+// one wave per workgroup with its own histograms.  SH > 1: the SH waves of a
+// workgroup share them; each folds a contiguous slice of the curve's
+// observations, then each takes the epilogue sums of a contiguous range of
+// bins, and wave 0 adds them (in wave order) and forms S.  After the
+// histograms: the partial sums [SH-1][10][lane] (FP64) and the group's item
+// index.
+template <int PH, int NZ, int SH, int SRC>
+// (The sums' pointer is untyped in the signature: a type that depends on an
+// unnamed enum would mangle differently in the host and device compilations.)
+__global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const Rec* __restrict__ rec,
+                                                        const void* __restrict__ zs,
                                                         const int64_t* __restrict__ offsets,
                                                         const BaseConst* __restrict__ bcs,
                                                         const double* __restrict__ freqs,
@@ -133,19 +215,20 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const RecB* __
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // uniform: keeps slice loads scalar
   const int M = a.n_bins;
-  uint64_t* hw = lds + lane;                      // [m][lane]: weight and residual
-  uint64_t* hz = lds + (size_t)M * kWave + lane;  // [m][lane]: w T_1 and w T_2 (64-bit pair)
-  uint32_t* hz32 = reinterpret_cast<uint32_t*>(lds + (size_t)M * kWave) + lane;  // [m][lane]: w T_1 alone
-  // histogram size in 64-bit words: 8, 12 or 16 bytes per (bin, lane)
-  const int hist_words = (NZ == NZ_NONE ? 2 : (NZ == NZ_ONE ? 3 : 4)) * M * kWave / 2;
+  const int slots = M + 1;
+  constexpr int SW = kSlotWords<NZ>;
+  uint64_t* hw = lds + lane;          // slot m at hw + m SW: weight and residual
+  uint64_t* hz = lds + kWave + lane;  // NZ_PAIR, slot m at hz + m SW: w T_1 and w T_2
+  uint32_t* hz32 = reinterpret_cast<uint32_t*>(lds + (size_t)slots * kWave) + lane;  // NZ_ONE, [m][lane]: w T_1
+  // histogram size in 64-bit words: 8, 12 or 16 bytes per (slot, lane)
+  const int hist_words = (NZ == NZ_NONE ? 2 : (NZ == NZ_ONE ? 3 : 4)) * slots * kWave / 2;
   double* part = reinterpret_cast<double*>(lds + hist_words);
   int* group_item = reinterpret_cast<int*>(part + (SH - 1) * kBmSums * kWave);
-  for (int m = wave; m < M; m += SH) {
-    hw[m * kWave] = 0;
-    if (NZ == NZ_PAIR) hz[m * kWave] = 0;
+  for (int m = wave; m < slots; m += SH) {
+    hw[m * SW] = 0;
+    if (NZ == NZ_PAIR) hz[m * SW] = 0;
     if (NZ == NZ_ONE) hz32[m * kWave] = 0;
   }
-  const int sub = lane & (kGroup - 1);
   for (;;) {
     int it = 0;
     if (SH > 1) {
@@ -165,34 +248,22 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const RecB* __
     const int n_all = (int)(offsets[c + 1] - p0);
     const int lo = SH > 1 ? (int)((int64_t)wave * n_all / SH) : 0;
     const int n = SH > 1 ? (int)((int64_t)(wave + 1) * n_all / SH) - lo : n_all;
-    const RecB* __restrict__ rc = rec + p0 + lo;
+    const Rec* __restrict__ rc = rec + p0 + lo;
+    const ZWord<NZ>* __restrict__ zc = static_cast<const ZWord<NZ>*>(zs) + p0 + lo;
     const BaseConst bc = bcs[c];
     for (int kt = k0; kt < k1; kt += kWave) {
       const int k = kt + lane;
       if (n > 0) {
         Folder<PH> fo;
         fo.init(freqs[k < k1 ? k : k1 - 1], M);
-        RecB cur = rc[sub < n ? sub : n - 1];
-        for (int g = 0; g < n; g += kGroup) {
-          const int nxt = g + kGroup + sub;
-          const RecB next = rc[nxt < n ? nxt : n - 1];  // prefetch (clamped, in bounds)
-          const int cnt = n - g;                         // wave-uniform
-          if (cnt >= kGroup) {
-            static_for<0, kGroup>([&](auto qc) { bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz, hz32); });
-          } else {
-            static_for<0, kGroup>([&](auto qc) {
-              if (decltype(qc)::value < cnt) bm_point<PH, NZ, decltype(qc)::value>(cur, fo, (uint32_t)M, hw, hz, hz32);
-            });
-          }
-          cur = next;
-        }
+        bm_accumulate<PH, NZ, SRC>(rc, zc, n, fo, hw, hz, hz32, lane);
       }
       if constexpr (SH == 1) {
-        const BmSums sums = bm_bins<NZ>(hw, hz, hz32, 0, M, bc);
+        const BmSums sums = bm_bins<PH, NZ>(hw, hz, hz32, M, 0, M, bc);
         if (k < k1) a.S[(int64_t)c * a.n_freq + k] = (float)(bm_statistic(sums, bc) * bc.scale);
       } else {
         __syncthreads();  // every slice is in the histograms
-        BmSums sums = bm_bins<NZ>(hw, hz, hz32, wave * M / SH, (wave + 1) * M / SH, bc);
+        BmSums sums = bm_bins<PH, NZ>(hw, hz, hz32, M, wave * M / SH, (wave + 1) * M / SH, bc);
         if (wave > 0) {
           double* pp = part + (size_t)(wave - 1) * kBmSums * kWave + lane;
           const double* sv = &sums.s1;
@@ -227,29 +298,33 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const RecB* __
 
 size_t bm_lds_bytes(int n_bins, int n_terms, int share) {
   const size_t per_slot = n_terms >= 3 ? 16 : (n_terms == 2 ? 12 : 8);
-  const size_t hist = per_slot * n_bins * kWave;
+  const size_t hist = per_slot * (n_bins + 1) * kWave;
   if (share <= 1) return hist;
   return hist + (size_t)(share - 1) * kBmSums * kWave * sizeof(double) + 16;
 }
 
 namespace {
-template <int PH, int SH>
+template <int PH, int SH, int SRC>
 const void* bm_fn_sh(int n_terms) {
-  if (n_terms >= 3) return (const void*)bm_kernel<PH, NZ_PAIR, SH>;
-  if (n_terms == 2) return (const void*)bm_kernel<PH, NZ_ONE, SH>;
-  return (const void*)bm_kernel<PH, NZ_NONE, SH>;
+  if (n_terms >= 3) return (const void*)bm_kernel<PH, NZ_PAIR, SH, SRC>;
+  if (n_terms == 2) return (const void*)bm_kernel<PH, NZ_ONE, SH, SRC>;
+  return (const void*)bm_kernel<PH, NZ_NONE, SH, SRC>;
 }
-template <int PH>
+template <int PH, int SRC>
 const void* bm_fn_ph(int n_terms, int share) {
-  return share == 4 ? bm_fn_sh<PH, 4>(n_terms) : (share == 2 ? bm_fn_sh<PH, 2>(n_terms) : bm_fn_sh<PH, 1>(n_terms));
+  return share == 4 ? bm_fn_sh<PH, 4, SRC>(n_terms) : (share == 2 ? bm_fn_sh<PH, 2, SRC>(n_terms) : bm_fn_sh<PH, 1, SRC>(n_terms));
 }
-const void* bm_fn(int phase, int n_terms, int share) {
-  return phase == PH_LISTING ? bm_fn_ph<PH_LISTING>(n_terms, share) : bm_fn_ph<PH_FP64>(n_terms, share);
+// source: 0 scalar loads, 1 vector loads + DPP broadcast
+const void* bm_fn(int phase, int n_terms, int share, int source) {
+  if (source == BSRC_DPP)
+    return phase == PH_LISTING ? bm_fn_ph<PH_LISTING, BSRC_DPP>(n_terms, share) : bm_fn_ph<PH_FP64, BSRC_DPP>(n_terms, share);
+  return phase == PH_LISTING ? bm_fn_ph<PH_LISTING, BSRC_SCALAR>(n_terms, share)
+                             : bm_fn_ph<PH_FP64, BSRC_SCALAR>(n_terms, share);
 }
 }  // namespace
 
-hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int share, int* out) {
-  const void* fn = bm_fn(phase, n_terms, share);
+hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int share, int source, int* out) {
+  const void* fn = bm_fn(phase, n_terms, share, source);
   const size_t lds = bm_lds_bytes(n_bins, n_terms, share);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -258,17 +333,18 @@ hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int share, int* 
 
 hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s) {
   const int share = a.share > 1 ? a.share : 1;
-  const void* fn = bm_fn(phase, a.n_terms, share);
+  const void* fn = bm_fn(phase, a.n_terms, share, a.source);
   const size_t lds = bm_lds_bytes(a.n_bins, a.n_terms, share);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   BmArgs args = a;
-  const RecB* rec = a.rec;
+  const Rec* rec = a.rec;
+  const void* zs = a.z;
   const int64_t* offsets = a.offsets;
   const BaseConst* bcs = a.bc;
   const double* freqs = a.freqs;
   const Item* items = a.items;
-  void* params[] = {&args, &rec, &offsets, &bcs, &freqs, &items};
+  void* params[] = {&args, &rec, &zs, &offsets, &bcs, &freqs, &items};
   return hipLaunchKernel(fn, dim3(grid), dim3(kWave * share), params, lds, s);
 }
 

@@ -223,6 +223,118 @@ __device__ __forceinline__ void reduce_parts(uint64_t* h, int M, int wave, float
   }
 }
 
+// Several variants from a histogram shared by SH waves (the reduction of
+// reduce_variants split over the waves).
+//  Phase 1 (every wave, its own parts as in reduce_parts): takes the fine
+//    slots, writes the part sums of variant 0 to part_sums, writes the prefix
+//    of its own range (from the range start) back to the slots a derived
+//    variant reads, and its range total to totals[wave].
+//  Phase 2 (after a barrier): the wave computes the derived variants it owns
+//    (v = 1, 2, ... go to waves SH-1, SH-2, ..., cyclically, so the lead gets
+//    the fewest); P(x) is the prefix at slot x-1 plus the totals of the waves
+//    before that slot's owner.  Reads are plain: a slot may serve variants of
+//    several waves.  Results go to var_sums[v].
+//  Then (after a barrier) each wave clears the prefix slots of its range.
+template <int PH, int SH>
+__device__ __forceinline__ void variants_phase1(uint64_t* h, int M, int wave, float ia2q, const Variants& vs,
+                                                float* part_sums, uint64_t* totals, int lane) {
+  const int nb = (M + kReduceBlock - 1) / kReduceBlock;
+  const int p0 = wave * kSumParts / SH, p1 = (wave + 1) * kSumParts / SH;
+  const bool first = part_block(p0, nb) == 0 && part_block(p1, nb) > 0;
+  const uint64_t wrap = first ? take_wrap_slot<PH>(h, M) : (uint64_t)0;
+  uint64_t run = 0;
+  for (int p = p0; p < p1; ++p) {
+    float acc = 0.f;
+    for (int b = part_block(p, nb); b < part_block(p + 1, nb); ++b) {
+      const int m0 = b * kReduceBlock;
+      uint64_t f[kReduceBlock];
+#pragma unroll
+      for (int q = 0; q < kReduceBlock; ++q) f[q] = m0 + q < M ? lds_take(h + (m0 + q) * kWave) : (uint64_t)0;
+      if (m0 == 0) f[0] += wrap;
+#pragma unroll
+      for (int q = 0; q < kReduceBlock; ++q) {
+        const int m = m0 + q;
+        if (m < M) {
+          run += f[q];
+          acc = add_bin_term(acc, f[q], ia2q);
+          if ((vs.need[m >> 5] >> (m & 31)) & 1u) h[m * kWave] = run;
+        }
+      }
+    }
+    part_sums[p * kWave + lane] = acc;
+  }
+  totals[wave * kWave + lane] = run;
+}
+
+template <int SH>
+__device__ __forceinline__ int wave_of_variant(int v) {
+  return (SH - 1) - (v - 1) % SH;
+}
+
+template <int NV, int SH>
+__device__ __forceinline__ void variants_phase2(const uint64_t* h, int M, int wave, float ia2q, const Variants& vs,
+                                                const uint64_t* totals, float* var_sums, int lane) {
+  const int nb = (M + kReduceBlock - 1) / kReduceBlock;
+  // first block of the ranges of waves 1..3, and the prefix offset of waves 1..3
+  // (waves beyond SH-1 start past the last block and are never chosen)
+  const int wb1 = part_block(1 * kSumParts / SH, nb);
+  const int wb2 = SH > 2 ? part_block(2 * kSumParts / SH, nb) : nb;
+  const int wb3 = SH > 3 ? part_block(3 * kSumParts / SH, nb) : nb;
+  const uint64_t off1 = totals[lane];
+  const uint64_t off2 = SH > 2 ? off1 + totals[kWave + lane] : (uint64_t)0;
+  const uint64_t off3 = SH > 3 ? off2 + totals[2 * kWave + lane] : (uint64_t)0;
+  const uint64_t total = SH == 2 ? off1 + totals[kWave + lane] : (SH == 3 ? off2 + totals[2 * kWave + lane]
+                                                                          : off3 + totals[3 * kWave + lane]);
+  // P(x), 1 <= x <= M: prefix through slot x-1 (the owner's choice is wave-uniform)
+  auto prefix = [&](int x) -> uint64_t {
+    const int b = (x - 1) / kReduceBlock;
+    const uint64_t o = b >= wb3 ? off3 : (b >= wb2 ? off2 : (b >= wb1 ? off1 : (uint64_t)0));
+    return h[(x - 1) * kWave] + o;
+  };
+#pragma unroll
+  for (int v = 1; v < NV; ++v) {
+    if (v >= vs.n || wave_of_variant<SH>(v) != wave) continue;
+    const int k = vs.k[v], o = vs.o[v], mv = M / k;
+    uint64_t prev = o == 0 ? (uint64_t)0 : prefix(o);  // P(o)
+    float out = 0.f;
+    for (int c0 = 0; c0 < mv; c0 += kReduceBlock) {
+      uint64_t pe[kReduceBlock];
+#pragma unroll
+      for (int q = 0; q < kReduceBlock; ++q) {
+        // end of window c0+q: e = o + (c0+q+1) k, clamped past the last window
+        const int e = min(o + (c0 + q + 1) * k, M + o);
+        const int x = e > M ? e - M : e;  // 1 <= x <= M
+        pe[q] = prefix(x);
+        if (e > M) pe[q] += total;
+      }
+#pragma unroll
+      for (int q = 0; q < kReduceBlock; ++q) {
+        if (c0 + q < mv) {
+          out = add_bin_term(out, pe[q] - prev, ia2q);
+          prev = pe[q];
+        }
+      }
+    }
+    var_sums[v * kWave + lane] = out;
+  }
+}
+
+// Clears the prefix slots (need bits) of this wave's range.
+template <int SH>
+__device__ __forceinline__ void clear_need_slots(uint64_t* h, int M, int wave, const Variants& vs) {
+  const int nb = (M + kReduceBlock - 1) / kReduceBlock;
+  const int lo = part_block(wave * kSumParts / SH, nb) * kReduceBlock;
+  const int hi = min(M, part_block((wave + 1) * kSumParts / SH, nb) * kReduceBlock);
+  for (int w = lo >> 5; w * 32 < hi; ++w) {
+    uint32_t bits = vs.need[w];
+    while (bits) {
+      const int m = w * 32 + __builtin_ctz(bits);
+      bits &= bits - 1;
+      if (m >= lo && m < hi) h[m * kWave] = 0;
+    }
+  }
+}
+
 // Peak bookkeeping of one periodogram variant along a work item.
 struct PeakState {
   WaveTop top;
@@ -282,12 +394,12 @@ struct PeakState {
 };
 
 // SH > 1: the SH waves of the workgroup work on the same item with one shared
-// histogram; `part` holds the kSumParts part sums of S.  Only wave 0 (the
-// lead) stores S and keeps the peaks; with several variants it also does the
-// whole reduction.
+// histogram; `part` holds the kSumParts part sums of S, and with several
+// variants `totals` the range totals and `var_sums` the derived variants'
+// sums.  Only wave 0 (the lead) stores S and keeps the peaks.
 template <int PH, int FL, int PK, int SRC, int NV, int SH>
 __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, const Item& item, uint64_t* hist,
-                                             int lane, int wave, float* part) {
+                                             int lane, int wave, float* part, uint64_t* totals, float* var_sums) {
   static_assert(SH == 1 || FL == 1, "a shared histogram serves one frequency per lane");
   static_assert(kSumParts % SH == 0, "each wave owns whole parts of the sum");
   const int M = a.n_bins;
@@ -340,8 +452,20 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
         sv[0] = s;
       } else if constexpr (SH > 1) {
         __syncthreads();  // every slice is in the histogram
-        if (lead) reduce_variants<PH, NV>(h[j], M, cc.ia2q, a.var, sv);
-        __syncthreads();  // histogram clear for the next sub-tile
+        variants_phase1<PH, SH>(h[j], M, wave, cc.ia2q, a.var, part, totals, lane);
+        __syncthreads();  // prefixes, range totals and part sums visible
+        variants_phase2<NV, SH>(h[j], M, wave, cc.ia2q, a.var, totals, var_sums, lane);
+        __syncthreads();  // every derived variant has read its prefixes
+        clear_need_slots<SH>(h[j], M, wave, a.var);
+        if (lead) {
+          float s0 = 0.f;
+#pragma unroll
+          for (int p = 0; p < kSumParts; ++p) s0 += part[p * kWave + lane];
+          sv[0] = s0;
+#pragma unroll
+          for (int v = 1; v < NV; ++v) sv[v] = v < nvar ? var_sums[v * kWave + lane] : 0.f;
+        }
+        __syncthreads();  // histogram clear for the next sub-tile; sums read
         if (!lead) continue;
       } else if constexpr (NV == 1) {
         sv[0] = reduce_hist<PH>(h[j], M, cc.ia2q);
@@ -377,7 +501,9 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
 //
 // LDS: SH == 1: one histogram set per wave, [wave][j][bin][lane].  SH > 1
 // (the workgroup is the SH waves of one histogram): [bin][lane], then the
-// part sums [kSumParts][lane] (float) and the item index of the group.
+// part sums [kSumParts][lane] (float), with several variants the range
+// totals [SH][lane] (64-bit) and the variant sums [NV][lane] (float), and
+// the item index of the group.
 template <int PH, int FL, int PK, int SRC, int NV, int SH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == SRC_DPP && SH == 1 ? 2 : 10))) void batched_kernel(BatchArgs a, const Rec* __restrict__ rec,
                                                       const int64_t* __restrict__ offsets,
@@ -391,7 +517,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
   const int slots = a.n_bins + 1;
   uint64_t* hist = lds + (SH > 1 ? (size_t)0 : (size_t)wave * FL * slots * kWave);
   float* part = reinterpret_cast<float*>(lds + (size_t)slots * kWave);
-  int* group_item = reinterpret_cast<int*>(part + kSumParts * kWave);
+  uint64_t* totals = reinterpret_cast<uint64_t*>(part + kSumParts * kWave);        // used when NV > 1
+  float* var_sums = reinterpret_cast<float*>(totals + (NV > 1 ? SH * kWave : 0));  // used when NV > 1
+  int* group_item = reinterpret_cast<int*>(var_sums + (NV > 1 ? NV * kWave : 0));
   if (SH > 1) {
     for (int s = wave; s < slots; s += SH) hist[s * kWave + lane] = 0;
   } else {
@@ -411,7 +539,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
     }
     if (it >= a.n_items) break;
     const Item item = items[it];
-    process_item<PH, FL, PK, SRC, NV, SH>(a, ro, item, hist, lane, wave, part);
+    process_item<PH, FL, PK, SRC, NV, SH>(a, ro, item, hist, lane, wave, part, totals, var_sums);
   }
   // The last wave out resets the queue, so the next launch (or graph replay)
   // starts from zero without a memset.
@@ -480,9 +608,13 @@ bool batched_shape_built(const Shape& shape, int phase, int n_var) {
   return batched_fn(phase, shape.freqs_per_lane, 0, shape.point_source, n_var, shape.share) != nullptr;
 }
 
-size_t batched_lds_bytes(const Shape& shape, int n_bins) {
+size_t batched_lds_bytes(const Shape& shape, int n_bins, int n_var) {
   const size_t hist = (size_t)(n_bins + 1) * kWave * sizeof(uint64_t);
-  if (shape.share > 1) return hist + (size_t)kSumParts * kWave * sizeof(float) + 16;
+  if (shape.share > 1) {
+    size_t extra = (size_t)kSumParts * kWave * sizeof(float) + 16;
+    if (n_var > 1) extra += (size_t)shape.share * kWave * sizeof(uint64_t) + (size_t)kMaxVariants * kWave * sizeof(float);
+    return hist + extra;
+  }
   return (size_t)shape.waves_per_group * shape.freqs_per_lane * hist;
 }
 

@@ -117,8 +117,9 @@ struct fpw_plan_s {
   // marginalised baseline (App. A general case)
   bool bm = false;
   int bm_grid = 0;
-  int bm_share = 1;  // waves per histogram of the baseline kernel
-  DevBuf bm_rec, bm_const, bm_S;
+  int bm_share = 1;   // waves per histogram of the baseline kernel
+  int bm_source = 0;  // its point source: 0 scalar loads, 1 vector loads + DPP broadcast
+  DevBuf bm_rec, bm_z, bm_const, bm_S;
   // profiling events: before prepare, after prepare, after batched, after merge
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool ev_recorded = false;
@@ -314,7 +315,7 @@ int default_chunk(const fpw_plan_s* p, const fpw::Shape& s, int total_waves) {
 fpw_status configure_shape(fpw_plan_s* p, fpw::Shape s) {
   if (!fpw::batched_shape_built(s, p->opt.phase, p->var.n))
     return fail(FPW_EUNSUPPORTED, "no batched kernel is built for this launch shape");
-  const size_t lds = fpw::batched_lds_bytes(s, p->opt.n_bins);
+  const size_t lds = fpw::batched_lds_bytes(s, p->opt.n_bins, p->var.n);
   if (lds > 160 * 1024) return fail(FPW_EUNSUPPORTED, "LDS %zu bytes per workgroup exceeds 160 KiB", lds);
   int per_cu = 0;
   FPW_HIP(fpw::batched_groups_per_cu(s, p->opt.phase, p->opt.topk, p->var.n, lds, &per_cu), "occupancy query");
@@ -501,12 +502,15 @@ fpw_status enqueue_bm_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hi
   pa.inv_alpha2 = p->opt.inv_alpha2;
   pa.beta = p->opt.baseline_scale;
   pa.stat_scale = p->opt.stat_scale == FPW_STAT_LISTING_HALF ? 0.5 : 1.0;
-  pa.rec = p->bm_rec.as<fpw::RecB>();
+  pa.rec = p->bm_rec.as<fpw::Rec>();
+  pa.z64 = p->bm_z.as<uint64_t>();
+  pa.z32 = p->bm_z.as<uint32_t>();
   pa.bc = p->bm_const.as<fpw::BaseConst>();
   FPW_HIP(fpw::launch_bm_prepare(pa, s), "baseline prepare kernel");
   if (prof) FPW_HIP(hipEventRecord(p->ev[1], s), "event record");
   fpw::BmArgs a{};
-  a.rec = p->bm_rec.as<fpw::RecB>();
+  a.rec = p->bm_rec.as<fpw::Rec>();
+  a.z = p->bm_z.p;
   a.offsets = p->offsets.as<int64_t>();
   a.bc = p->bm_const.as<fpw::BaseConst>();
   a.freqs = p->freqs.as<double>();
@@ -516,6 +520,7 @@ fpw_status enqueue_bm_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hi
   a.n_bins = p->opt.n_bins;
   a.n_terms = p->opt.baseline_terms;
   a.share = p->bm_share;
+  a.source = p->bm_source;
   a.S = Sd;
   a.queue = p->queue.as<uint32_t>();
   FPW_HIP(fpw::launch_bm(a, p->opt.phase, p->bm_grid, s), "baseline kernel");
@@ -813,15 +818,18 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     if (st != FPW_OK) return st;
     if (o.baseline_terms > 0) {
       p->bm = true;
-      FPW_HIP(p->bm_rec.alloc(np * sizeof(fpw::RecB)), "alloc baseline records");
+      FPW_HIP(p->bm_rec.alloc(np * sizeof(fpw::Rec)), "alloc baseline records");
+      const size_t zb = o.baseline_terms >= 3 ? sizeof(uint64_t) : (o.baseline_terms == 2 ? sizeof(uint32_t) : 0);
+      FPW_HIP(p->bm_z.alloc(std::max<size_t>(np * zb, 8)), "alloc baseline sums");
       FPW_HIP(p->bm_const.alloc((size_t)n_curves * sizeof(fpw::BaseConst)), "alloc baseline constants");
       FPW_HIP(p->bm_S.alloc((size_t)n_curves * (size_t)n_freq * sizeof(float)), "alloc baseline periodogram");
       int per_cu = 0;
-      // histograms of more than ~1/12 of the LDS are shared by four waves (measured: K = 3, M = 20
-      // 12 % faster than private, two waves 3 %; K = 1, M = 20, 10 KiB, slower shared)
+      // as for the batched kernel: histograms of ~8.5 KiB or more per wave are shared by two waves,
+      // of ~16.5 KiB or more by four; scalar point loads unless asked otherwise
       const size_t hb = fpw::bm_lds_bytes(o.n_bins, o.baseline_terms, 1);
-      p->bm_share = o.hist_share ? o.hist_share : (hb > 13 * 1024 ? 4 : 1);
-      FPW_HIP(fpw::bm_groups_per_cu(o.phase, o.n_bins, o.baseline_terms, p->bm_share, &per_cu),
+      p->bm_share = o.hist_share ? o.hist_share : (hb >= 16896 ? 4 : (hb >= 8704 ? 2 : 1));
+      p->bm_source = o.point_source == 2 ? 1 : 0;
+      FPW_HIP(fpw::bm_groups_per_cu(o.phase, o.n_bins, o.baseline_terms, p->bm_share, p->bm_source, &per_cu),
               "baseline kernel occupancy");
       p->bm_grid = std::max(1, std::min(std::max(1, per_cu) * p->n_cu, p->n_items));
     }
@@ -1105,7 +1113,7 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
     info->grid_groups = p->bm_grid;
     info->waves_per_group = p->bm_share;
     info->freqs_per_lane = 1;
-    info->point_source = 2;  // vector loads + DPP broadcast
+    info->point_source = p->bm_source + 1;
     info->hist_share = p->bm_share;
     info->lds_bytes = (int32_t)fpw::bm_lds_bytes(p->opt.n_bins, p->opt.baseline_terms, p->bm_share);
   }

@@ -190,12 +190,9 @@ struct SharedArgs {
 // sums are exact; the per-curve constants are formed from the same rounded
 // per-point values, which keeps S = v^T L^-1 v + r^T Q^-1 r consistent with
 // one exactly solved (rounded) problem.
-struct alignas(16) RecB {
-  uint64_t tau_bits;  // FP64 time offset
-  uint64_t pk;        // (weight, weighted residual), packed as in Rec
-  uint64_t pz;        // (w T_1(s), w T_2(s)) in fixed point: T_2 * 2^32 + T_1, two's complement
-  uint64_t pad;
-};
+// Baseline sums of an observation (the records themselves are Rec): with
+// K = 3 terms the pair (w T_1, w T_2) in fixed point, T_2 * 2^32 + T_1 (two's
+// complement), one 64-bit word; with K = 2 the word w T_1 alone (32 bits).
 
 struct BaseConst {
   double g[3];      // H^-1 z: the best-fitting baseline coefficients
@@ -214,12 +211,15 @@ struct BmPrepArgs {
   int64_t n_curves;
   int center, tref_mode, n_terms;
   double t_ref, inv_alpha2, beta, stat_scale;
-  RecB* rec;        // [n_points]
+  Rec* rec;         // [n_points]: tau and (weight, weighted residual), as for the batched kernel
+  uint64_t* z64;    // [n_points] when n_terms == 3
+  uint32_t* z32;    // [n_points] when n_terms == 2
   BaseConst* bc;    // [n_curves]
 };
 
 struct BmArgs {
-  const RecB* rec;
+  const Rec* rec;
+  const void* z;     // baseline sums per observation: uint64_t (K = 3), uint32_t (K = 2), unused (K = 1)
   const int64_t* offsets;
   const BaseConst* bc;
   const double* freqs;
@@ -227,13 +227,14 @@ struct BmArgs {
   int32_t n_items, n_freq, n_bins;
   int32_t n_terms;   // baseline terms K (1..3); K = 1 needs no second sum
   int32_t share;     // waves per histogram (1, 2, 4): the workgroup size in waves
+  int32_t source;    // observations: 0 scalar loads, 1 vector loads + DPP broadcast
   float* S;          // [n_curves * n_freq]
   uint32_t* queue;   // [2], self-resetting as for the batched kernel
 };
 
 hipError_t launch_bm_prepare(const BmPrepArgs& a, hipStream_t s);
 hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s);
-hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int share, int* out);
+hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int share, int source, int* out);
 size_t bm_lds_bytes(int n_bins, int n_terms, int share);
 
 // Launch shapes of the batched kernel.
@@ -262,8 +263,8 @@ hipError_t launch_shared(const SharedArgs& a, int phase, int curve_groups, int n
 // B tiles and frequencies per wave for M bins: the choice with the best column use
 void shared_shape(int n_bins, int* nb, int* fw);
 
-// LDS bytes the batched kernel needs per workgroup.
-size_t batched_lds_bytes(const Shape& shape, int n_bins);
+// LDS bytes the batched kernel needs per workgroup (n_var periodogram variants).
+size_t batched_lds_bytes(const Shape& shape, int n_bins, int n_var);
 // Whether the batched kernel is built for this shape, phase mode and variant count.
 bool batched_shape_built(const Shape& shape, int phase, int n_var);
 // Persistent workgroups per CU the batched kernel reaches for this shape.

@@ -247,3 +247,40 @@ def test_binding_structs_match_header_layout(tmp_path, struct):
     assert int(out["sizeof"]) == ctypes.sizeof(mirror)
     for n in names:
         assert int(out[n]) == getattr(mirror, n).offset, n
+
+
+def _llvm_tool(name):
+    path = os.path.join("/opt/rocm/llvm/bin", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not found")
+    return path
+
+
+def test_every_registered_kernel_exists_in_the_device_code(tmp_path):
+    """The host side registers each kernel under its mangled device name; the gfx950 code objects
+    must define every one of them, or the runtime cannot load the library's kernels.  (Host and
+    device compilations number unnamed types independently, so a kernel signature that mentions
+    one can mangle differently on the two sides.)"""
+    objcopy, readelf, bundler = _llvm_tool("llvm-objcopy"), _llvm_tool("llvm-readelf"), _llvm_tool("clang-offload-bundler")
+    rodata, fatbin = tmp_path / "rodata.bin", tmp_path / "fatbin.bin"
+    subprocess.run([objcopy, "-O", "binary", "--only-section=.rodata", LIB, str(rodata)], check=True)
+    subprocess.run([objcopy, "-O", "binary", "--only-section=.hip_fatbin", LIB, str(fatbin)], check=True)
+    # names handed to the runtime at registration: mangled fpw symbols among the host's constant strings
+    registered = {s.decode() for s in rodata.read_bytes().split(b"\0") if s.startswith(b"_ZN3fpw")}
+    assert registered, "no registered kernel names found"
+    # device symbols: every offload bundle in the fat binary section, gfx950 part
+    blob = fatbin.read_bytes()
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    starts = [i for i in range(len(blob)) if blob.startswith(magic, i)]
+    assert starts, "no offload bundles"
+    defined = set()
+    for n, a in enumerate(starts):
+        b = starts[n + 1] if n + 1 < len(starts) else len(blob)
+        part, code = tmp_path / f"bundle{n}.bin", tmp_path / f"bundle{n}.co"
+        part.write_bytes(blob[a:b])
+        subprocess.run([bundler, "--unbundle", "--type=o", f"--input={part}", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
+                        f"--output={code}"], check=True)
+        syms = subprocess.run([readelf, "--dyn-syms", "-W", str(code)], check=True, capture_output=True, text=True).stdout
+        defined |= {line.split()[-1] for line in syms.splitlines() if " FUNC " in line}
+    missing = sorted(registered - defined)
+    assert not missing, f"{len(missing)} registered kernels have no device code, e.g. {missing[0]}"

@@ -168,18 +168,22 @@ def test_ztf1000_with_baseline_sampled():
     plan.close()
 
 
-@pytest.mark.parametrize("M,K,share,n_max", [(20, 3, 2, 260), (64, 3, 4, 260), (1, 2, 2, 3), (7, 1, 4, 3),
-                                             (40, 2, 2, 260), (13, 3, 4, 5)],
+@pytest.mark.parametrize("M,K,share,n_max,src", [(20, 3, 2, 260, "scalar"), (64, 3, 4, 260, "dpp"),
+                                                 (1, 2, 2, 3, "scalar"), (7, 1, 4, 3, "dpp"), (40, 2, 2, 260, "dpp"),
+                                                 (13, 3, 4, 5, "scalar"), (33, 1, 1, 200, "scalar"),
+                                                 (5, 2, 1, 40, "scalar"), (64, 3, 1, 300, "dpp")],
                          ids=lambda v: str(v))
-def test_baseline_kernel_shared_histograms(M, K, share, n_max):
+def test_baseline_kernel_shared_histograms(M, K, share, n_max, src):
     """Histograms shared by 2 or 4 waves (each folds a slice of the observations, the epilogue
-    sums are split by bins): same parity bar, also for curves with fewer observations than waves."""
-    _say(f"baseline shared histograms M={M} K={K} share={share} n_max={n_max}")
+    sums are split by bins) and either point source: same parity bar, also for curves with fewer
+    observations than waves."""
+    _say(f"baseline histograms M={M} K={K} share={share} n_max={n_max} source={src}")
     b = synth.random_batch(66 + M + n_max, 10, 1, n_max, FREQS, M)
     y = _with_drift(b, 0.3)
-    plan = fpw.Plan(b.offsets, b.t, y, b.dy, b.freqs, M, baseline_terms=K, hist_share=share, topk=3)
+    plan = fpw.Plan(b.offsets, b.t, y, b.dy, b.freqs, M, baseline_terms=K, hist_share=share, topk=3, point_source=src)
     info = plan.info()
     assert (info.kernel, info.hist_share, info.waves_per_group) == (2, share, share)
+    assert info.point_source == (1 if src == "scalar" else 2)
     S, idx, val = plan.eval()
     torch.cuda.synchronize()
     S = S.cpu().numpy()
@@ -188,7 +192,8 @@ def test_baseline_kernel_shared_histograms(M, K, share, n_max):
         parity.assert_s_close(S[c], ref, S_abs, what=f"curve {c}")
     parity.assert_topk_matches_rule(S, idx.cpu().numpy(), val.cpu().numpy(), 3)
     # private histograms on the same data: the FP64 epilogue sums differ only in order
-    priv = fpw.Plan(b.offsets, b.t, y, b.dy, b.freqs, M, baseline_terms=K, hist_share=1)
+    priv = fpw.Plan(b.offsets, b.t, y, b.dy, b.freqs, M, baseline_terms=K, hist_share=1,
+                    point_source="dpp" if src == "scalar" else "scalar")
     Sp = priv.eval(topk=False)[0].cpu().numpy()
     np.testing.assert_allclose(S, Sp, rtol=1e-6, atol=1e-9 * float(np.abs(Sp).max()))
     for p in (plan, priv):
@@ -198,7 +203,9 @@ def test_baseline_kernel_shared_histograms(M, K, share, n_max):
 def test_baseline_default_share_by_histogram_size():
     _say("baseline default share")
     b = synth.random_batch(67, 4, 20, 80, FREQS, 10)
-    for M, K, sh in [(20, 1, 1), (20, 2, 4), (20, 3, 4), (26, 1, 1), (27, 1, 4), (40, 3, 4), (64, 2, 4)]:
+    # histogram bytes per wave: (8, 12, 16 for K = 1, 2, 3) x (M + 1) x 64; two waves from 8704, four from 16896
+    for M, K, sh in [(15, 1, 1), (16, 1, 2), (20, 1, 2), (20, 2, 2), (20, 3, 4), (10, 2, 1), (11, 2, 2),
+                     (32, 1, 4), (31, 1, 2), (40, 3, 4), (64, 2, 4)]:
         p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, M, baseline_terms=K)
-        assert p.info().hist_share == sh, (M, K)
+        assert (p.info().hist_share, p.info().point_source) == (sh, 1), (M, K)
         p.close()
