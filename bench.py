@@ -603,6 +603,22 @@ def bench_sweep(args):
                                   "roofline_frac": _roofline(evals, batch.n_curves, len(batch.freqs), M, batch.n_points, k)["frac"]}),
                       flush=True)
                 plan.close()
+    # several bin counts from one pass (M = 40 giving 20 and 10): offset 0 only and every offset
+    Sv = torch.empty((8, batch.n_curves, len(batch.freqs)), dtype=torch.float32, device="cuda")
+    idv = torch.empty((8, batch.n_curves, 5), dtype=torch.int32, device="cuda")
+    vav = torch.empty((8, batch.n_curves, 5), dtype=torch.float32, device="cuda")
+    for all_offsets in (False, True):
+        for src in ("scalar", "dpp"):
+            for share in (1, 2, 4):
+                plan = fpw.Plan.from_batch(batch, n_bins=40, derived_bins=(20, 10), all_offsets=all_offsets, topk=5,
+                                           point_source=src, hist_share=share, profile=True)
+                nv = plan.n_variants
+                _, kms = _time_passes(plan, 4, 1, S_out=Sv[:nv], idx_out=idv[:nv], val_out=vav[:nv])
+                k = float(np.median(kms[:, 1]))
+                print(json.dumps({"M": 40, "derived": [20, 10], "all_offsets": all_offsets, "variants": nv,
+                                  "point_source": src, "hist_share": share, "kernel_ms": k}), flush=True)
+                plan.close()
+    del Sv, idv, vav
     # launch shapes of the headline configuration (M = 20, scalar source)
     for fl in (1, 2):
         for wpg in (1, 2, 4):

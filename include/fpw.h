@@ -106,7 +106,8 @@ typedef struct {
   int32_t chunk_freqs;    /* launch shape override, 0 = default: frequencies per work item */
   const char* tune_cache; /* path of a text cache of autotune results; NULL = none */
   int32_t point_source;   /* launch shape override: how a wave fetches observations.
-                             0 = default (by M; scalar loads for the baseline kernel),
+                             0 = default (by M and the kind of plan; scalar loads for
+                             the baseline kernel),
                              1 = scalar loads, 2 = vector loads + DPP broadcast (one
                              frequency per lane) */
   int32_t derived_bins[FPW_MAX_DERIVED];

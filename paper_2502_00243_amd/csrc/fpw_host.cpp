@@ -142,8 +142,8 @@ const int kWave = 64;
 const int kShare2MinBins = 16;
 const int kShare4MinBins = 32;
 // Smallest M for which the default point source is the DPP broadcast, with
-// private histograms and with shared ones (their extra waves hide the scalar
-// loads' waits up to M ~ 100).
+// private histograms (or several variants) and with shared histograms and
+// one variant (their extra waves hide the scalar loads' waits up to M ~ 100).
 const int kDppMinBins = 32;
 const int kDppMinBinsShared = 128;
 
@@ -803,8 +803,10 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
       const bool can = o.phase <= FPW_PHASE_FP64_LISTING && o.freqs_per_lane != 2 && o.waves_per_group == 0;
       share = !can ? 1 : (o.n_bins >= kShare4MinBins ? 4 : (o.n_bins >= kShare2MinBins ? 2 : 1));
     }
-    const int src = o.point_source ? o.point_source - 1
-                                   : (o.n_bins >= (share > 1 ? kDppMinBinsShared : kDppMinBins) ? 1 : 0);
+    // with several variants the scalar source loses to the DPP broadcast even with shared
+    // histograms (measured: M = 40 -> 20, 10 on 1000 ZTF-like curves, 20.1 vs 17.8 ms)
+    const int dpp_from = share > 1 && p->var.n == 1 ? kDppMinBinsShared : kDppMinBins;
+    const int src = o.point_source ? o.point_source - 1 : (o.n_bins >= dpp_from ? 1 : 0);
     const int fl = (src == 1 || p->var.n > 1 || share > 1) ? 1 : (o.freqs_per_lane ? o.freqs_per_lane : 1);
     const int wpg = share > 1 ? share : (o.waves_per_group ? o.waves_per_group : 1);
     fpw::Shape sh{fl, wpg, o.chunk_freqs, src, share};

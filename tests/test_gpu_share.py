@@ -158,7 +158,7 @@ def test_default_share_by_bin_count():
         assert p.info().hist_share == 1, opts
         p.close()
     p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, derived_bins=(20,))
-    assert p.info().hist_share == 4  # derived bin counts share too
+    assert (p.info().hist_share, p.info().point_source) == (4, 2)  # derived bin counts share too, DPP source
     p.close()
 
 
