@@ -141,7 +141,7 @@ typedef struct {
                              summed in one fixed order for every launch shape, so results are
                              bit-identical to private histograms.  With baseline_terms > 0 it
                              sets the baseline kernel's sharing instead; 0 = by histogram size
-                             per wave (1 below 8704 bytes, 2 below 16896, else 4). */
+                             per wave (1 below 8704 bytes, else 4). */
 } fpw_options;
 
 /* Kernel of a shared-timestamp plan (fpw_plan_shared). */
