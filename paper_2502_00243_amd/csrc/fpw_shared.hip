@@ -152,32 +152,81 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
         }
       }
       wave_lds_fence();
-      // Products, four K-blocks per step: the chunk's tiles sit in LDS as
-      // [K-block][curve group], so within a step every read is an immediate
-      // offset from one base pointer per operand.
-      for (int kb4 = 0; kb4 < kbn; kb4 += 4) {
-        const unsigned char* abase = vals + (size_t)kb4 * CG * kSharedTileBytes + lane * 16;
-        const unsigned char* bbase[kNB];
+      // Products.  The chunk's tiles sit in LDS as [K-block][curve group], so
+      // every A read is an immediate offset from one base pointer.
+      const unsigned char* bbase[kNB];
 #pragma unroll
-        for (int b = 0; b < kNB; ++b) bbase[b] = priv + colf[b] * KC + kb4 * 32 + h * 16;
+      for (int b = 0; b < kNB; ++b) bbase[b] = priv + colf[b] * KC + h * 16;
+      const unsigned char* abase = vals + lane * 16;
+      auto read_a = [&](int kb, v4i (&av)[CG]) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (kb4 + j < kbn) {
-            v4i av[CG], bv[kNB];
+        for (int ai = 0; ai < CG; ++ai) av[ai] = *reinterpret_cast<const v4i*>(abase + (kb * CG + ai) * kSharedTileBytes);
+      };
+      auto read_bins = [&](int kb, v4i (&nb)[kNB]) {
+#pragma unroll
+        for (int b = 0; b < kNB; ++b) nb[b] = *reinterpret_cast<const v4i*>(bbase[b] + kb * 32);
+      };
+      if constexpr (kNB == 2) {
+        // Software-pipelined: the products of K-block kb run while the bins
+        // of kb + 1 (read one step earlier) become one-hot operands and the
+        // reads for kb + 1 (A tiles) and kb + 2 (bins) are in flight; the
+        // issue order alternates one product and two VALU instructions, so
+        // the VALU work sits in the matrix cores' shadow.  Reads past the
+        // last K-block are clamped to it (harmless rereads).
+        v4i bv[kNB], nb0[kNB], nb1[kNB], av0[CG], av1[CG];
+        read_bins(0, nb0);
+#pragma unroll
+        for (int b = 0; b < kNB; ++b)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)nb0[b][i], colm[b]);
+        read_bins(min(1, kbn - 1), nb0);
+        read_a(0, av0);
+        // one K-block: products with (av, bv); bv <- one-hot of nb (the next
+        // K-block's bins); reads of the next A tiles into an and of the bins
+        // two K-blocks ahead into nn
+        auto step = [&](int kb, v4i (&av)[CG], v4i (&an)[CG], v4i (&nb)[kNB], v4i (&nn)[kNB]) {
+          read_a(min(kb + 1, kbn - 1), an);
+          read_bins(min(kb + 2, kbn - 1), nn);
+#pragma unroll
+          for (int b = 0; b < kNB; ++b) {
 #pragma unroll
             for (int ai = 0; ai < CG; ++ai)
-              av[ai] = *reinterpret_cast<const v4i*>(abase + (j * CG + ai) * kSharedTileBytes);
+              acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
 #pragma unroll
-            for (int b = 0; b < kNB; ++b) {
-              const v4i bins = *reinterpret_cast<const v4i*>(bbase[b] + j * 32);
+            for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)nb[b][i], colm[b]);
+          }
 #pragma unroll
-              for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)bins[i], colm[b]);
-            }
+          for (int q = 0; q < CG * kNB; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix product
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two VALU instructions
+          }
+        };
+        // two K-blocks per iteration, so the operand sets swap roles without copies
+        int kb = 0;
+        for (; kb + 1 < kbn; kb += 2) {
+          step(kb, av0, av1, nb0, nb1);
+          step(kb + 1, av1, av0, nb1, nb0);
+        }
+        if (kb < kbn) step(kb, av0, av1, nb0, nb1);
+      } else {
+        // four K-blocks per step, each: its bins become one-hot operands, then its products
+        for (int kb4 = 0; kb4 < kbn; kb4 += 4) {
 #pragma unroll
-            for (int ai = 0; ai < CG; ++ai)
+          for (int j = 0; j < 4; ++j) {
+            if (kb4 + j < kbn) {
+              v4i av[CG], bv[kNB];
+              read_a(kb4 + j, av);
+              read_bins(kb4 + j, bv);
 #pragma unroll
               for (int b = 0; b < kNB; ++b)
-                acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)bv[b][i], colm[b]);
+#pragma unroll
+              for (int ai = 0; ai < CG; ++ai)
+#pragma unroll
+                for (int b = 0; b < kNB; ++b)
+                  acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
+            }
           }
         }
       }
