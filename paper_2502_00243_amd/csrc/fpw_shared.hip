@@ -102,11 +102,16 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
 
   for (int r = 0; r < a.rounds; ++r) {
     const int f0 = ((blockIdx.x * a.rounds + r) * kSharedWaves + wave) * a.fw;
+    // accumulators: the pipelined two-tile loop starts each round with
+    // products whose addend is zero (an inline constant); the three-tile
+    // path clears them here (peeling its first K-block measured slower)
     v16i acc[CG][kNB];
+    if constexpr (kNB != 2) {
 #pragma unroll
-    for (int ai = 0; ai < CG; ++ai)
+      for (int ai = 0; ai < CG; ++ai)
 #pragma unroll
-      for (int b = 0; b < kNB; ++b) acc[ai][b] = (v16i){};
+        for (int b = 0; b < kNB; ++b) acc[ai][b] = (v16i){};
+    }
 
     for (int ch = 0; ch < n_chunks; ++ch) {
       const int kb0 = ch * KCB;
@@ -184,14 +189,15 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
         // one K-block: products with (av, bv); bv <- one-hot of nb (the next
         // K-block's bins); reads of the next A tiles into an and of the bins
         // two K-blocks ahead into nn
-        auto step = [&](int kb, v4i (&av)[CG], v4i (&an)[CG], v4i (&nb)[kNB], v4i (&nn)[kNB]) {
+        auto step = [&](int kb, v4i (&av)[CG], v4i (&an)[CG], v4i (&nb)[kNB], v4i (&nn)[kNB], auto first) {
           read_a(min(kb + 1, kbn - 1), an);
           read_bins(min(kb + 2, kbn - 1), nn);
 #pragma unroll
           for (int b = 0; b < kNB; ++b) {
 #pragma unroll
             for (int ai = 0; ai < CG; ++ai)
-              acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
+              acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], decltype(first)::value ? (v16i){} : acc[ai][b],
+                                                               0, 0, 0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)nb[b][i], colm[b]);
           }
@@ -201,33 +207,42 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
             __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two VALU instructions
           }
         };
-        // two K-blocks per iteration, so the operand sets swap roles without copies
+        // two K-blocks per iteration, so the operand sets swap roles without
+        // copies; the round's first two are peeled (the very first product
+        // of each accumulator adds to zero)
+        const std::false_type later{};
         int kb = 0;
-        for (; kb + 1 < kbn; kb += 2) {
-          step(kb, av0, av1, nb0, nb1);
-          step(kb + 1, av1, av0, nb1, nb0);
+        if (ch == 0) {
+          step(0, av0, av1, nb0, nb1, std::true_type{});
+          if (kbn > 1) step(1, av1, av0, nb1, nb0, later);
+          kb = 2;
         }
-        if (kb < kbn) step(kb, av0, av1, nb0, nb1);
+        for (; kb + 1 < kbn; kb += 2) {
+          step(kb, av0, av1, nb0, nb1, later);
+          step(kb + 1, av1, av0, nb1, nb0, later);
+        }
+        if (kb < kbn) step(kb, av0, av1, nb0, nb1, later);
       } else {
-        // four K-blocks per step, each: its bins become one-hot operands, then its products
+        // one K-block: its bins become one-hot operands, then its products
+        auto block = [&](int kb) {
+          v4i av[CG], bv[kNB];
+          read_a(kb, av);
+          read_bins(kb, bv);
+#pragma unroll
+          for (int b = 0; b < kNB; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)bv[b][i], colm[b]);
+#pragma unroll
+          for (int ai = 0; ai < CG; ++ai)
+#pragma unroll
+            for (int b = 0; b < kNB; ++b)
+              acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
+        };
+        // four K-blocks per step
         for (int kb4 = 0; kb4 < kbn; kb4 += 4) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (kb4 + j < kbn) {
-              v4i av[CG], bv[kNB];
-              read_a(kb4 + j, av);
-              read_bins(kb4 + j, bv);
-#pragma unroll
-              for (int b = 0; b < kNB; ++b)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) bv[b][i] = one_hot4((uint32_t)bv[b][i], colm[b]);
-#pragma unroll
-              for (int ai = 0; ai < CG; ++ai)
-#pragma unroll
-                for (int b = 0; b < kNB; ++b)
-                  acc[ai][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[ai], bv[b], acc[ai][b], 0, 0, 0);
-            }
-          }
+          for (int j = 0; j < 4; ++j)
+            if (kb4 + j < kbn) block(kb4 + j);
         }
       }
     }
