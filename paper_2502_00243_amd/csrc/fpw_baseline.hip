@@ -10,11 +10,14 @@
 //     S = v^T L^-1 v + r^T Q^-1 r,
 // where H = I + B^T C_sigma^-1 B and g = H^-1 B^T C_sigma^-1 X are per-curve
 // constants (both terms are non-negative; Q >= I).  Z_m0 = beta W_m, so with
-// K <= 3 the kernel needs one more packed 64-bit sum per bin, (Z_1, Z_2),
-// accumulated with a second ds_add_u64 per (point, frequency).  The epilogue
-// runs in FP64: the bin sums are exact integers and the constants were formed
-// from the same rounded values (the constant direction of Q is then exactly
-// the prior's 1, not a difference of two large sums).
+// K <= 3 the kernel needs at most one more sum per bin: none for K = 1, the
+// 32-bit word Z_1 for K = 2 (a ds_add_u32), the packed pair (Z_1, Z_2) for
+// K = 3 (a second ds_add_u64).  The epilogue runs in FP64: the bin sums are
+// exact integers and the constants were formed from the same rounded values
+// (the constant direction of Q is then exactly the prior's 1, not a
+// difference of two large sums).  Observations come through the general
+// kernel's point sources, and for large histograms several waves share one,
+// as in the general kernel.
 #include "fpw_common.h"
 
 namespace fpw {

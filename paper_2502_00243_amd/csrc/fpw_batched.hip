@@ -11,9 +11,9 @@
 //  * one lane = one trial frequency; a wave sweeps 64 (or 128) consecutive
 //    frequencies of one curve, so every observation is wave-uniform and is
 //    fetched once per wave through the scalar cache into SGPRs;
-//  * each lane owns a private histogram of M+1 packed 64-bit fixed-point
-//    words in LDS, laid out [bin][lane] so the 64 lanes of a wave always hit
-//    distinct banks whatever their bins are;
+//  * each lane owns a histogram of M+1 packed 64-bit fixed-point words in
+//    LDS, laid out [bin][lane] so the 64 lanes of a wave always hit distinct
+//    banks whatever their bins are;
 //  * one `ds_add_u64` per (observation, frequency) accumulates both sums
 //    exactly: the weight sits in the high word, the weighted residual in the
 //    low word, and integer addition carries them without rounding;
@@ -21,13 +21,15 @@
 //    comes out of the low word of one more FP64 fma, so a fold costs three
 //    FP64 instructions plus the LDS address;
 //  * work is a queue of (curve, frequency chunk) items, longest curves first,
-//    popped by persistent waves with one atomic each; the peak selection is
-//    fused so that large periodograms never reach HBM;
-//  * for large M a private histogram per wave leaves room for few waves per
-//    CU, so SH > 1 waves of a workgroup share one: each folds a contiguous
-//    slice of the curve's observations into it (LDS atomics from different
-//    waves add up exactly), then each reduces a contiguous range of bins and
-//    wave 0 adds the partial sums.
+//    popped by persistent waves (or groups of waves) with one atomic each;
+//    the peak selection is fused so that large periodograms never reach HBM;
+//  * for large M a histogram per wave leaves room for few waves per CU, so
+//    SH > 1 waves of a workgroup share one: each folds a contiguous slice of
+//    the curve's observations into it (LDS atomics from different waves add
+//    up exactly), then each reduces whole parts of the bin sum and wave 0
+//    adds the part sums in order;
+//  * S is summed in one fixed order for every launch shape (see kSumParts),
+//    so the result does not depend on the shape.
 #include "fpw_common.h"
 
 namespace fpw {

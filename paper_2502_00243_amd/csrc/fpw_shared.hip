@@ -22,7 +22,8 @@
 // wave owns fw frequencies per round (fw * M <= 32 NB columns, NB = 2 or 3
 // B tiles), folds the chunk's points at those frequencies into bytes in its
 // private LDS, builds the one-hot operand from them and issues CG * NB
-// products per 32 points.
+// products per 32 points (with two B tiles the K loop is software-pipelined
+// so the one-hot work overlaps the products' issue).
 #include <algorithm>
 
 #include "fpw_common.h"
