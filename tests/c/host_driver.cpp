@@ -1,0 +1,199 @@
+// Drives the host runtime through plan creation, passes and destruction for
+// every kind of plan and launch shape (general, baseline K = 1..3, derived
+// bin counts, shared histograms, both point sources, shared timestamps), and
+// through the other entry points (stored-S peaks, FP64 comparator, bins hook,
+// phase entropy, profiled passes, autotune with its cache file, the captured
+// pass cache cycling through more output buffers than it keeps), for use
+// with the HIP stand-ins in hip_stub.cpp under the sanitizers.  argv[1]: a
+// scratch path for the autotune cache.  Prints "failures: 0" when every call
+// returned what it should.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "fpw.h"
+
+namespace {
+
+int failures = 0;
+int plans = 0;
+
+void expect(fpw_status got, fpw_status want, const char* what) {
+  if (got != want) {
+    std::printf("FAIL %s: status %d (want %d) %s\n", what, got, want, fpw_last_error());
+    ++failures;
+  }
+}
+
+struct Batch {
+  std::vector<int64_t> off;
+  std::vector<double> t, y, dy, f;
+};
+
+Batch make_batch(int C, int n_freq) {
+  Batch b;
+  b.off.assign(C + 1, 0);
+  for (int c = 0; c < C; ++c) {
+    const int n = 1 + (c * 37) % 260;
+    for (int i = 0; i < n; ++i) {
+      b.t.push_back(i * 3.7 + c);
+      b.y.push_back(std::sin(i * 0.3));
+      b.dy.push_back(0.02 + 0.001 * i);
+    }
+    b.off[c + 1] = (int64_t)b.t.size();
+  }
+  b.f.resize(n_freq);
+  for (int i = 0; i < n_freq; ++i) b.f[i] = 0.05 + i * 0.025;
+  return b;
+}
+
+// device buffers are host memory under the stand-ins
+template <class T>
+std::vector<T> buf(size_t n) {
+  return std::vector<T>(n ? n : 1);
+}
+
+void passes(fpw_plan_t p, const fpw_options& o, int64_t C, int64_t F, int nvar) {
+  auto S = buf<float>((size_t)nvar * C * F);
+  auto idx = buf<int32_t>((size_t)nvar * C * 16);
+  auto val = buf<float>((size_t)nvar * C * 16);
+  for (int r = 0; r < 3; ++r)
+    expect(fpw_eval_batch(p, S.data(), o.topk ? idx.data() : nullptr, o.topk ? val.data() : nullptr, nullptr), FPW_OK,
+           "eval");
+  if (o.topk) expect(fpw_eval_batch(p, nullptr, idx.data(), val.data(), nullptr), FPW_OK, "eval without S");
+  if (o.profile) {
+    float ms[3];
+    expect(fpw_pass_timings(p, ms), FPW_OK, "timings");
+  }
+}
+
+void run(const Batch& b, const fpw_options& o, const char* what) {
+  const int64_t C = (int64_t)b.off.size() - 1, F = (int64_t)b.f.size();
+  fpw_plan_t p = nullptr;
+  fpw_status st = fpw_plan(&p, C, b.off.data(), b.t.data(), b.y.data(), b.dy.data(), F, b.f.data(), &o, nullptr);
+  expect(st, FPW_OK, what);
+  if (st != FPW_OK) return;
+  ++plans;
+  fpw_plan_info info;
+  expect(fpw_get_plan_info(p, &info), FPW_OK, "info");
+  passes(p, o, C, F, info.n_variants);
+  for (int v = 0; v < info.n_variants; ++v) {
+    int32_t m, off;
+    expect(fpw_variant(p, v, &m, &off), FPW_OK, "variant");
+  }
+  auto S = buf<float>((size_t)C * F);
+  auto idx = buf<int32_t>((size_t)C * 4);
+  auto val = buf<float>((size_t)C * 4);
+  expect(fpw_topk(p, S.data(), 4, idx.data(), val.data(), nullptr), FPW_OK, "topk");
+  auto S64 = buf<double>((size_t)C * F);
+  expect(fpw_eval_fp64(p, S64.data(), nullptr), o.baseline_terms ? FPW_EUNSUPPORTED : FPW_OK, "fp64");
+  auto bins = buf<int32_t>((size_t)(b.off[C] - b.off[C - 1]) * 7);
+  expect(fpw_debug_bins(p, o.phase, C - 1, 3, 10, bins.data(), nullptr), FPW_OK, "bins");
+  auto H = buf<float>((size_t)C * 2), E = buf<float>((size_t)C * 2), V = buf<float>((size_t)C * 2);
+  auto fi = buf<int32_t>((size_t)C * 2);
+  expect(fpw_phase_entropy(p, fi.data(), 2, H.data(), E.data(), V.data(), nullptr), FPW_OK, "entropy");
+  fpw_plan_destroy(p);
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  const Batch b = make_batch(10, 477);
+  fpw_options o;
+  // general and baseline plans over bin counts, waves per histogram and point sources
+  for (int K : {0, 1, 2, 3})
+    for (int M : {1, 7, 20, 40, 64})
+      for (int share : {0, 1, 2, 4})
+        for (int src : {0, 1, 2}) {
+          fpw_options_default(&o);
+          o.n_bins = M;
+          o.baseline_terms = K;
+          o.hist_share = share;
+          o.point_source = src;
+          o.topk = K ? 3 : 5;
+          run(b, o, "plan");
+        }
+  // derived bin counts, every offset, shared and private
+  for (int M : {20, 40, 64})
+    for (int share : {0, 1, 2, 4}) {
+      fpw_options_default(&o);
+      o.n_bins = M;
+      o.derived_bins[0] = M / 2;
+      o.derived_bins[1] = M / 4;
+      o.all_offsets = M == 40;
+      o.hist_share = share;
+      o.topk = 4;
+      run(b, o, "multi-M plan");
+    }
+  // other phase modes, launch overrides, profiling
+  for (int phase : {1, 2, 3}) {
+    fpw_options_default(&o);
+    o.n_bins = 20;
+    o.phase = phase;
+    o.topk = 2;
+    o.profile = 1;
+    run(b, o, "phase plan");
+  }
+  fpw_options_default(&o);
+  o.n_bins = 20;
+  o.freqs_per_lane = 2;
+  o.waves_per_group = 4;
+  o.chunk_freqs = 100;
+  o.topk = 16;
+  run(b, o, "override plan");
+  // autotune, then a second plan that finds the shape in the cache
+  if (argc > 1) {
+    for (int r = 0; r < 2; ++r) {
+      fpw_options_default(&o);
+      o.n_bins = 40;
+      o.topk = 5;
+      o.autotune = 1;
+      o.tune_cache = argv[1];
+      run(b, o, "autotune plan");
+    }
+  }
+  // the captured-pass cache: more output buffer sets than it keeps, in turn
+  {
+    fpw_options_default(&o);
+    o.n_bins = 20;
+    o.topk = 3;
+    const int64_t C = 10, F = 477;
+    fpw_plan_t p = nullptr;
+    expect(fpw_plan(&p, C, b.off.data(), b.t.data(), b.y.data(), b.dy.data(), F, b.f.data(), &o, nullptr), FPW_OK,
+           "graph plan");
+    std::vector<std::vector<float>> Ss(6, buf<float>(C * F));
+    std::vector<std::vector<int32_t>> is(6, buf<int32_t>(C * 3));
+    std::vector<std::vector<float>> vs(6, buf<float>(C * 3));
+    for (int r = 0; r < 20; ++r) {
+      const int k = (r * 5) % 6;
+      expect(fpw_eval_batch(p, Ss[k].data(), is[k].data(), vs[k].data(), nullptr), FPW_OK, "graph eval");
+    }
+    fpw_plan_destroy(p);
+  }
+  // shared timestamps: matrix-core and general kernels, and a baseline on a shared plan
+  // (kernel: 0 auto, 1 general, 2 matrix; the auto plan with a baseline takes the general path)
+  for (int mode : {0, 1, 2, 3})
+    for (int M : {1, 20, 64}) {
+      const int kernel = mode == 3 ? 0 : mode;
+      const int C = 21, N = 37, F = 300;
+      std::vector<double> t(N), y((size_t)C * N), dy((size_t)C * N, 0.03), f(F);
+      for (int i = 0; i < N; ++i) t[i] = i * 11.3;
+      for (size_t i = 0; i < y.size(); ++i) y[i] = std::cos(0.7 * (double)i);
+      for (int i = 0; i < F; ++i) f[i] = 0.1 + 0.03 * i;
+      fpw_options_default(&o);
+      o.n_bins = M;
+      o.shared_kernel = kernel;
+      o.topk = 3;
+      o.baseline_terms = mode == 3 ? 2 : 0;
+      fpw_plan_t p = nullptr;
+      fpw_status st = fpw_plan_shared(&p, C, N, t.data(), y.data(), dy.data(), F, f.data(), &o, nullptr);
+      expect(st, FPW_OK, "shared plan");
+      if (st != FPW_OK) continue;
+      ++plans;
+      passes(p, o, C, F, 1);
+      fpw_plan_destroy(p);
+    }
+  std::printf("plans: %d, failures: %d\n", plans, failures);
+  return failures != 0;
+}
