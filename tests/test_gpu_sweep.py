@@ -52,9 +52,15 @@ def _compare_general_like(b, plan, opts, exact):
     return S
 
 
-@pytest.mark.parametrize("seed", range(10))
+def _shape(rng):
+    """A random launch shape: waves per histogram and point source (defaults included)."""
+    return dict(hist_share=int(rng.choice([0, 1, 2, 4])), point_source=str(rng.choice(["auto", "scalar", "dpp"])))
+
+
+@pytest.mark.parametrize("seed", range(16))
 def test_general_random(seed):
     rng, freqs, opts, phase, M = _draw(seed)
+    opts.update(_shape(rng))
     C = int(rng.integers(1, 20))
     _say(f"general sweep seed={seed} C={C} nf={len(freqs)} M={M} phase={phase} opts={opts}")
     b = synth.random_batch(500 + seed, C, 1, int(rng.integers(2, 400)), freqs, M)
@@ -83,9 +89,10 @@ def test_shared_random(seed):
     plan.close()
 
 
-@pytest.mark.parametrize("seed", range(20, 26))
+@pytest.mark.parametrize("seed", range(20, 30))
 def test_baseline_random(seed):
     rng, freqs, opts, phase, M = _draw(seed, max_freq=200)
+    opts.update(_shape(rng))
     K = int(rng.integers(1, 4))
     beta = float(10 ** rng.uniform(-2, 2))
     C = int(rng.integers(1, 8))
