@@ -136,11 +136,22 @@ __device__ __forceinline__ double recip64(double d) {
 }
 
 // Per-lane sums of the FP64 epilogue over a range of bins: v^T L^-1 v, r = Z^T L^-1 v
-// and P = Z^T L^-1 Z (upper triangle).
+// and P = Z^T L^-1 Z (upper triangle), indexed as below.
+enum { SV = 0, SR0, SR1, SR2, SP00, SP01, SP02, SP11, SP12, SP22, kBmSums };
 struct BmSums {
-  double s1, r0, r1, r2, p00, p01, p02, p11, p12, p22;
+  double v[kBmSums];
 };
-constexpr int kBmSums = 10;
+
+// The sums that K terms can make non-zero (Z_1 = 0 for K = 1, Z_2 = 0 for
+// K <= 2): only these pass between the waves of a shared histogram.
+template <int NZ>
+constexpr int kLiveSums = NZ == NZ_NONE ? 3 : (NZ == NZ_ONE ? 6 : kBmSums);
+template <int NZ>
+constexpr int live_sum(int j) {
+  constexpr int none[3] = {SV, SR0, SP00};
+  constexpr int one[6] = {SV, SR0, SR1, SP00, SP01, SP11};
+  return NZ == NZ_NONE ? none[j] : (NZ == NZ_ONE ? one[j] : j);
+}
 
 // Reads and clears bins [mb, me) of one lane's histograms and returns their
 // sums; the range that starts at bin 0 also takes the wrap slot M.
@@ -177,17 +188,17 @@ __device__ __forceinline__ BmSums bm_bins(uint64_t* hw, uint64_t* hz, uint32_t* 
     const double inv = d > 0.0 ? recip64(d) : 0.0;  // an empty bin adds nothing
     const double v = Y - (Z0 * bc.g[0] + Z1 * bc.g[1] + Z2 * bc.g[2]);
     const double vi = v * inv;
-    a.s1 += v * vi;
-    a.r0 += Z0 * vi;
-    a.r1 += Z1 * vi;
-    a.r2 += Z2 * vi;
+    a.v[SV] += v * vi;
+    a.v[SR0] += Z0 * vi;
+    a.v[SR1] += Z1 * vi;
+    a.v[SR2] += Z2 * vi;
     const double z0i = Z0 * inv, z1i = Z1 * inv, z2i = Z2 * inv;
-    a.p00 += Z0 * z0i;
-    a.p01 += Z0 * z1i;
-    a.p02 += Z0 * z2i;
-    a.p11 += Z1 * z1i;
-    a.p12 += Z1 * z2i;
-    a.p22 += Z2 * z2i;
+    a.v[SP00] += Z0 * z0i;
+    a.v[SP01] += Z0 * z1i;
+    a.v[SP02] += Z0 * z2i;
+    a.v[SP11] += Z1 * z1i;
+    a.v[SP12] += Z1 * z2i;
+    a.v[SP22] += Z2 * z2i;
   }
   return a;
 }
@@ -195,16 +206,17 @@ __device__ __forceinline__ BmSums bm_bins(uint64_t* hw, uint64_t* hz, uint32_t* 
 // S = v^T L^-1 v + r^T Q^-1 r with Q = H - P (symmetric positive definite,
 // Q >= I), by an LDL^T factorisation of the 3x3 Q.
 __device__ __forceinline__ double bm_statistic(const BmSums& a, const BaseConst& bc) {
-  const double q00 = bc.H[0] - a.p00, q01 = bc.H[1] - a.p01, q02 = bc.H[2] - a.p02;
-  const double q11 = bc.H[3] - a.p11, q12 = bc.H[4] - a.p12, q22 = bc.H[5] - a.p22;
+  const double q00 = bc.H[0] - a.v[SP00], q01 = bc.H[1] - a.v[SP01], q02 = bc.H[2] - a.v[SP02];
+  const double q11 = bc.H[3] - a.v[SP11], q12 = bc.H[4] - a.v[SP12], q22 = bc.H[5] - a.v[SP22];
+  const double r0 = a.v[SR0], r1 = a.v[SR1], r2 = a.v[SR2];
   const double l1 = q01 / q00, l2 = q02 / q00;
   const double a11 = q11 - l1 * q01, a12 = q12 - l1 * q02, a22 = q22 - l2 * q02;
   const double m2 = a12 / a11;
   const double c22 = a22 - m2 * a12;
-  const double y1 = a.r1 - l1 * a.r0;
-  const double y2 = a.r2 - l2 * a.r0 - m2 * y1;
-  const double s2 = a.r0 * a.r0 / q00 + y1 * y1 / a11 + y2 * y2 / c22;
-  return a.s1 + s2;
+  const double y1 = r1 - l1 * r0;
+  const double y2 = r2 - l2 * r0 - m2 * y1;
+  const double s2 = r0 * r0 / q00 + y1 * y1 / a11 + y2 * y2 / c22;
+  return a.v[SV] + s2;
 }
 
 // Slots per histogram lane: M+1 (weight, residual) words and M+1 extra
@@ -215,7 +227,7 @@ __device__ __forceinline__ double bm_statistic(const BmSums& a, const BaseConst&
 // workgroup share them; each folds a contiguous slice of the curve's
 // observations, then each takes the epilogue sums of a contiguous range of
 // bins, and wave 0 adds them (in wave order) and forms S.  After the
-// histograms: the partial sums [SH-1][10][lane] (FP64) and the group's item
+// histograms: the partial sums [SH-1][live sums][lane] (FP64) and the group's item
 // index.
 template <int PH, int NZ, int SH, int SRC>
 // (The sums' pointer is untyped in the signature: a type that depends on an
@@ -238,7 +250,7 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const Rec* __r
   // histogram size in 64-bit words: 8, 12 or 16 bytes per (slot, lane)
   const int hist_words = (NZ == NZ_NONE ? 2 : (NZ == NZ_ONE ? 3 : 4)) * slots * kWave / 2;
   double* part = reinterpret_cast<double*>(lds + hist_words);
-  int* group_item = reinterpret_cast<int*>(part + (SH - 1) * kBmSums * kWave);
+  int* group_item = reinterpret_cast<int*>(part + (SH - 1) * kLiveSums<NZ> * kWave);
   for (int m = wave; m < slots; m += SH) {
     hw[m * SW] = 0;
     if (NZ == NZ_PAIR) hz[m * SW] = 0;
@@ -279,20 +291,19 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const Rec* __r
       } else {
         __syncthreads();  // every slice is in the histograms
         BmSums sums = bm_bins<PH, NZ>(hw, hz, hz32, M, wave * M / SH, (wave + 1) * M / SH, bc);
+        constexpr int NL = kLiveSums<NZ>;
         if (wave > 0) {
-          double* pp = part + (size_t)(wave - 1) * kBmSums * kWave + lane;
-          const double* sv = &sums.s1;
+          double* pp = part + (size_t)(wave - 1) * NL * kWave + lane;
 #pragma unroll
-          for (int q = 0; q < kBmSums; ++q) pp[q * kWave] = sv[q];
+          for (int j = 0; j < NL; ++j) pp[j * kWave] = sums.v[live_sum<NZ>(j)];
         }
         __syncthreads();  // partial sums visible, histograms clear for the next sub-tile
         if (wave == 0) {
-          double* sv = &sums.s1;
 #pragma unroll
           for (int w = 1; w < SH; ++w) {
-            const double* pp = part + (size_t)(w - 1) * kBmSums * kWave + lane;
+            const double* pp = part + (size_t)(w - 1) * NL * kWave + lane;
 #pragma unroll
-            for (int q = 0; q < kBmSums; ++q) sv[q] += pp[q * kWave];
+            for (int j = 0; j < NL; ++j) sums.v[live_sum<NZ>(j)] += pp[j * kWave];
           }
           if (k < k1) a.S[(int64_t)c * a.n_freq + k] = (float)(bm_statistic(sums, bc) * bc.scale);
         }
@@ -315,7 +326,8 @@ size_t bm_lds_bytes(int n_bins, int n_terms, int share) {
   const size_t per_slot = n_terms >= 3 ? 16 : (n_terms == 2 ? 12 : 8);
   const size_t hist = per_slot * (n_bins + 1) * kWave;
   if (share <= 1) return hist;
-  return hist + (size_t)(share - 1) * kBmSums * kWave * sizeof(double) + 16;
+  const int live = n_terms >= 3 ? kLiveSums<NZ_PAIR> : (n_terms == 2 ? kLiveSums<NZ_ONE> : kLiveSums<NZ_NONE>);
+  return hist + (size_t)(share - 1) * live * kWave * sizeof(double) + 16;
 }
 
 namespace {
