@@ -132,12 +132,13 @@ typedef struct {
   double baseline_scale;  /* prior standard deviation of each baseline coefficient, in flux
                              units (> 0, finite; default 1) */
   int32_t hist_share;     /* launch shape override: waves that share one LDS histogram.
-                             0 = default: by M (1 below 16 bins, 2 up to 31, 4 from 32) for
-                             the FP64 phase modes when freqs_per_lane and waves_per_group are
-                             0, else 1.  1 = one private histogram per wave.  2 or 4 = a
-                             workgroup of that many waves folds disjoint slices of each
-                             curve's observations into one histogram (waves_per_group must be
-                             0 or equal; FP64 phase modes, one frequency per lane).  S is
+                             0 = default: by M (1 below 16 bins, 2 up to 31, 4 from 32)
+                             when freqs_per_lane and waves_per_group are 0 (and, with derived
+                             bin counts, the phase mode is FP64), else 1.  1 = one private
+                             histogram per wave.  2 or 4 = a workgroup of that many waves folds
+                             disjoint slices of each curve's observations into one histogram
+                             (waves_per_group must be 0 or equal; one frequency per lane;
+                             derived bin counts only with the FP64 phase modes).  S is
                              summed in one fixed order for every launch shape, so results are
                              bit-identical to private histograms.  With baseline_terms > 0 it
                              sets the baseline kernel's sharing instead; 0 = by histogram size

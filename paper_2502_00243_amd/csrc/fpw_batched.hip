@@ -573,8 +573,9 @@ void* batched_ptr_sh(int pk, int share) {
 template <int PH>
 void* batched_ptr_src(int fl, int pk, int src, int nv, int share) {
   if (share > 1) {
-    if constexpr (PH == PH_DF32 || PH == PH_FP32) {
-      return nullptr;
+    if constexpr (PH == PH_DF32 || PH == PH_FP32) {  // study modes: one variant only
+      if (fl != 1 || nv > 1) return nullptr;
+      return src == SRC_DPP ? batched_ptr_sh<PH, SRC_DPP, 1>(pk, share) : batched_ptr_sh<PH, SRC_SCALAR, 1>(pk, share);
     } else {
       if (fl != 1) return nullptr;
       if (nv > 1) return src == SRC_DPP ? batched_ptr_sh<PH, SRC_DPP, kMaxVariants>(pk, share)
@@ -591,8 +592,9 @@ void* batched_ptr_src(int fl, int pk, int src, int nv, int share) {
 
 // Instantiated shapes: two frequencies per lane exist for the FP64 folds with
 // scalar point loads and one variant only; several variants take one
-// frequency per lane; shared histograms (2 or 4 waves) exist for the FP64
-// folds with one frequency per lane.  Null for a shape that is not built.
+// frequency per lane; shared histograms (2 or 4 waves) take one frequency
+// per lane, and with the FP32-based folds one variant.  Null for a shape that
+// is not built.
 void* batched_fn(int phase, int fl, int pk, int src, int nv, int share) {
   switch (phase) {
     case PH_FP64: return batched_ptr_src<PH_FP64>(fl, pk, src, nv, share);

@@ -176,7 +176,6 @@ fpw_status check_options(const fpw_options& o) {
     if (o.waves_per_group != 0 && o.waves_per_group != o.hist_share)
       return fail(FPW_EINVAL, "with hist_share %d the workgroup has %d waves (waves_per_group 0 or %d)", o.hist_share,
                   o.hist_share, o.hist_share);
-    if (o.phase >= FPW_PHASE_DF32) return fail(FPW_EUNSUPPORTED, "a shared histogram is built for the FP64 phase modes");
   }
   int nvar = 1;
   for (int d = 0; d < FPW_MAX_DERIVED && o.derived_bins[d] != 0; ++d) {
@@ -191,6 +190,8 @@ fpw_status check_options(const fpw_options& o) {
     return fail(FPW_EUNSUPPORTED, "%d periodogram variants exceed FPW_MAX_VARIANTS=%d", nvar, FPW_MAX_VARIANTS);
   if (nvar > 1 && o.freqs_per_lane == 2)
     return fail(FPW_EUNSUPPORTED, "derived bin counts are built for one frequency per lane");
+  if (nvar > 1 && o.hist_share > 1 && o.phase >= FPW_PHASE_DF32)
+    return fail(FPW_EUNSUPPORTED, "derived bin counts with a shared histogram are built for the FP64 phase modes");
   if (o.shared_kernel < 0 || o.shared_kernel > 2) return fail(FPW_EINVAL, "shared_kernel must be 0, 1 or 2");
   if (o.baseline_terms < 0) return fail(FPW_EINVAL, "baseline_terms must be >= 0");
   if (o.baseline_terms > FPW_MAX_BASELINE_TERMS)
@@ -628,8 +629,8 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
     for (int fl = 1; fl <= (src == 1 ? 1 : fls); ++fl)
       for (int w : {1, 2})
         for (int cm : {1, 4}) cands.push_back(fpw::Shape{fl, w, -cm, src, 1});
-  // histograms shared by 2 or 4 waves (FP64 folds)
-  if (p->opt.phase <= FPW_PHASE_FP64_LISTING)
+  // histograms shared by 2 or 4 waves (with the FP32-based folds: one variant)
+  if (p->opt.phase <= FPW_PHASE_FP64_LISTING || p->var.n == 1)
     for (int src = 0; src <= 1; ++src)
       for (int sh : {2, 4}) cands.push_back(fpw::Shape{1, sh, -1, src, sh});
   // calibration slice: about 2e9 evaluations
@@ -800,7 +801,8 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     // stall the LDS atomics, so the DPP broadcast source is the default there.
     int share = o.hist_share;
     if (share == 0) {  // by M, where a shared histogram is built and no other group shape was asked for
-      const bool can = o.phase <= FPW_PHASE_FP64_LISTING && o.freqs_per_lane != 2 && o.waves_per_group == 0;
+      const bool can = (o.phase <= FPW_PHASE_FP64_LISTING || p->var.n == 1) && o.freqs_per_lane != 2 &&
+                       o.waves_per_group == 0;
       share = !can ? 1 : (o.n_bins >= kShare4MinBins ? 4 : (o.n_bins >= kShare2MinBins ? 2 : 1));
     }
     // with several variants the scalar source loses to the DPP broadcast even with shared

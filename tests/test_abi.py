@@ -82,7 +82,8 @@ CASES = [
     ("negative hist share", dict(opts=dict(hist_share=-2)), fpw.EINVAL),
     ("hist share with other waves per group", dict(opts=dict(hist_share=2, waves_per_group=4)), fpw.EINVAL),
     ("hist share with two freqs per lane", dict(opts=dict(hist_share=2, freqs_per_lane=2)), fpw.EUNSUPPORTED),
-    ("hist share in df32", dict(opts=dict(hist_share=4, phase="df32")), fpw.EUNSUPPORTED),
+    ("hist share in df32 with variants", dict(n_bins=12, opts=dict(hist_share=4, phase="df32", derived_bins=(6,))),
+     fpw.EUNSUPPORTED),
 ]
 
 

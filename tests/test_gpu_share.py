@@ -70,6 +70,8 @@ CASES = [
     (100, 4, "dpp", "fp64", 5),
     (255, 4, "dpp", "fp64", 5),
     (255, 2, "scalar", "fp64_listing", 2),
+    (20, 2, "scalar", "df32", 5),
+    (50, 4, "dpp", "df32", 3),
 ]
 
 
@@ -91,18 +93,22 @@ def test_shared_histogram_against_oracle(case):
     plan.close()
 
 
-@pytest.mark.parametrize("M", [1, 5, 20, 50, 130])
-def test_shared_equals_private_bit_for_bit(M):
+@pytest.mark.parametrize("M,phase", [(1, "fp64"), (5, "fp64"), (20, "fp64"), (50, "fp64"), (130, "fp64"),
+                                     (20, "df32"), (40, "fp32")])
+def test_shared_equals_private_bit_for_bit(M, phase):
     """S is summed in one fixed order for every launch shape: private and shared histograms, either
-    point source, one or two frequencies per lane give identical S and peaks."""
-    _say(f"shared vs private M={M}")
+    point source, one or two frequencies per lane give identical S and peaks (in every phase mode,
+    the naive FP32 one included)."""
+    _say(f"shared vs private M={M} phase={phase}")
     b = synth.random_batch(80 + M, 40, 1, 600, np.linspace(0.05, 20.0, 1500), M)
-    ref = fpw.Plan.from_batch(b, hist_share=1, point_source="scalar", topk=5)
+    ref = fpw.Plan.from_batch(b, hist_share=1, point_source="scalar", topk=5, phase=phase)
     S1, i1, v1 = (x.cpu().numpy() for x in ref.eval())
     shapes = [dict(hist_share=sh, point_source=src) for sh in (1, 2, 4) for src in ("scalar", "dpp")]
-    shapes += [dict(freqs_per_lane=2)] + ([dict(waves_per_group=4)] if 4 * (M + 1) * 512 <= 160 * 1024 else [])
+    if phase == "fp64":
+        shapes += [dict(freqs_per_lane=2)]
+    shapes += [dict(waves_per_group=4)] if 4 * (M + 1) * 512 <= 160 * 1024 else []
     for opts in shapes:
-        p = fpw.Plan.from_batch(b, topk=5, **opts)
+        p = fpw.Plan.from_batch(b, topk=5, phase=phase, **opts)
         S2, i2, v2 = (x.cpu().numpy() for x in p.eval())
         np.testing.assert_array_equal(S2, S1, err_msg=str(opts))
         np.testing.assert_array_equal(i2, i1, err_msg=str(opts))
@@ -153,13 +159,17 @@ def test_default_share_by_bin_count():
     assert p.info().point_source == 2  # private histograms at large M: DPP source
     p.close()
     # private where no shared form is built or another group shape was asked for
-    for opts in (dict(phase="df32"), dict(waves_per_group=2), dict(freqs_per_lane=2)):
+    for opts in (dict(phase="df32", derived_bins=(20,)), dict(waves_per_group=2), dict(freqs_per_lane=2)):
         p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, **opts)
         assert p.info().hist_share == 1, opts
         p.close()
     p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, derived_bins=(20,))
     assert (p.info().hist_share, p.info().point_source) == (4, 2)  # derived bin counts share too, DPP source
     p.close()
+    for phase in ("df32", "fp32"):  # the study modes share with one variant
+        p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, phase=phase)
+        assert p.info().hist_share == 4, phase
+        p.close()
 
 
 def test_shared_histogram_repeated_passes_and_graph_replays():
