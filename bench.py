@@ -234,21 +234,26 @@ def main():
         torch.cuda.synchronize()
 
     # single-curve latency (1 curve, 200 points, 1e4 frequencies, M = 10), outputs preallocated
-    lat_us = None
+    # (the default plan runs the fused pass; the three-kernel pass is timed beside it)
+    lat_us = lat3_us = None
     if not args.no_latency:
         b1 = synth.single_curve()
-        p1 = fpw.Plan.from_batch(b1, topk=1)
         S1 = torch.empty((1, len(b1.freqs)), dtype=torch.float32, device="cuda")
         i1 = torch.empty((1, 1), dtype=torch.int32, device="cuda")
         v1 = torch.empty((1, 1), dtype=torch.float32, device="cuda")
-        for _ in range(3):
-            p1.eval(S_out=S1, idx_out=i1, val_out=v1)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(50):
-            p1.eval(S_out=S1, idx_out=i1, val_out=v1)
-        torch.cuda.synchronize()
-        lat_us = (time.perf_counter() - t1) / 50 * 1e6
+        lats = []
+        for fuse in (0, -1):
+            p1 = fpw.Plan.from_batch(b1, topk=1, fuse_prepare=fuse)
+            for _ in range(3):
+                p1.eval(S_out=S1, idx_out=i1, val_out=v1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(50):
+                p1.eval(S_out=S1, idx_out=i1, val_out=v1)
+            torch.cuda.synchronize()
+            lats.append((time.perf_counter() - t1) / 50 * 1e6)
+            p1.close()
+        lat_us, lat3_us = lats
 
     out = {
         "metric": METRIC,
@@ -282,6 +287,7 @@ def main():
         "fp64_plain": plain,
         "speedup_vs_fp64_plain": (value / plain["value"]) if plain else None,
         "latency_single_curve_us": lat_us,
+        "latency_single_curve_three_kernels_us": lat3_us,
     }
     print(json.dumps(out), flush=True)
 

@@ -100,7 +100,8 @@ typedef struct {
   double inv_alpha2;   /* 1/alpha^2 >= 0, finite (Eq. 1 prior); default 0 (alpha -> inf) */
   double t_ref;        /* used iff tref_mode == FPW_TREF_GIVEN */
   int32_t autotune;    /* 1: time candidate launch shapes at plan time and keep the fastest */
-  int32_t use_graph;   /* 1 (default): replay fpw_eval_batch as one captured hipGraph */
+  int32_t use_graph;   /* 1 (default): replay fpw_eval_batch as one captured hipGraph (not
+                          for the fused pass of small plans, see fuse_prepare) */
   int32_t freqs_per_lane; /* launch shape override, 0 = default: frequencies per lane (1, 2) */
   int32_t waves_per_group;/* launch shape override, 0 = default: waves per workgroup (1, 2, 4) */
   int32_t chunk_freqs;    /* launch shape override, 0 = default: frequencies per work item */
@@ -143,6 +144,19 @@ typedef struct {
                              bit-identical to private histograms.  With baseline_terms > 0 it
                              sets the baseline kernel's sharing instead; 0 = by histogram size
                              per wave (1 below 8704 bytes, else 4). */
+  int32_t fuse_prepare;   /* fused pass for small plans: the fold kernel prepares its curve
+                             itself (each work item's workgroup of four waves reduces the
+                             curve's constants and forms its records in registers), then
+                             one workgroup per curve merges the peaks: two launches instead
+                             of three, launched directly rather than as a graph (a graph
+                             replay costs the host more than they do).  S and peaks are
+                             bit-identical to the three-kernel pass.
+                             0 = default: for plans of one periodogram variant and no
+                             baseline terms with at most 4 items of 64 frequencies per CU
+                             (n_curves * ceil(n_freq / 64) <= 4 * CUs), when no launch shape
+                             override is set.  -1 = never.  1 = always (FPW_EUNSUPPORTED with
+                             derived bin counts, baseline terms, or a shape override other
+                             than chunk_freqs and four waves per group). */
 } fpw_options;
 
 /* Kernel of a shared-timestamp plan (fpw_plan_shared). */
@@ -291,12 +305,14 @@ typedef struct {
   int32_t work_items;     /* (curve, frequency chunk) items in the queue */
   int32_t lds_bytes;      /* LDS per workgroup */
   int32_t tuned;          /* 1 if the launch shape came from the autotuner or its cache */
-  int32_t point_source;   /* 1 scalar loads, 2 vector loads + DPP broadcast */
+  int32_t point_source;   /* 1 scalar loads, 2 vector loads + DPP broadcast, 3 records formed
+                             in the lanes + readlane broadcast (fused pass) */
   int32_t n_variants;     /* periodograms per curve and pass */
   int32_t kernel;         /* 0 general batched kernel, 1 shared-timestamp matrix-core kernel,
                              2 baseline-marginalised kernel */
   int32_t hist_share;     /* waves per LDS histogram (1, 2, 4) of the general batched kernel
                              or of the baseline kernel; 0 for the matrix-core kernel */
+  int32_t fuse_prepare;   /* 1 if the plan runs the fused pass (see fpw_options) */
 } fpw_plan_info;
 
 fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);

@@ -12,37 +12,27 @@ namespace {
 using namespace dev;
 
 // ---------------------------------------------------------------- chunk merge
-// One wave per (curve, variant): lanes take the curve's chunks in turn, keep
-// the best candidates and decide the peaks on the chunk boundaries, then the
-// wave selects the curve's top k.
+// One wave per (curve, variant).
 template <int K>
 __global__ __launch_bounds__(256) void merge_kernel(MergeArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int gw = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (gw >= a.n_curves * a.n_var) return;  // wave-uniform
   const int v = gw / a.n_curves, c = gw - v * a.n_curves;
-  const int nv = a.n_var;
-  TopList<K> l;
-  l.init();
-  const int q0 = a.curve_slot[c], q1 = a.curve_slot[c + 1];
-  for (int q = q0 + lane; q < q1; q += kWave) {
-    const int64_t cq = ((int64_t)q * nv + v) * a.topk;
-    for (int r = 0; r < a.topk; ++r) {
-      const int ci = a.cand_idx[cq + r];
-      l.insert(a.cand_val[cq + r], ci, ci >= 0);
-    }
-    if (q > q0) {
-      // b = first frequency of this chunk, b-1 = last of the previous one
-      const int b = a.slot_k0[q];
-      const float* ep = a.edge + ((int64_t)(q - 1) * nv + v) * 4;
-      const float* eq = a.edge + ((int64_t)q * nv + v) * 4;
-      const float sa_left = ep[2], sa = ep[3], sb = eq[0], sb_right = eq[1];
-      l.insert(sa, b - 1, sa > sa_left && sa >= sb);
-      l.insert(sb, b, sb > sa && sb >= sb_right);
-    }
-  }
-  const int64_t o = ((int64_t)v * a.n_curves + c) * a.topk;
-  wave_select<K>(l, a.topk, a.out_val + o, a.out_idx + o, lane);
+  merge_curve<K>(a, c, v, lane);
+}
+
+// One workgroup of four waves per (curve, variant), for curves cut into many
+// chunks (the fused pass): the chunks' loads are spread over 256 lanes.
+constexpr int kMergeGroupWaves = 4;
+
+template <int K>
+__global__ __launch_bounds__(kMergeGroupWaves * kWave) void merge_group_kernel(MergeArgs a) {
+  __shared__ float lv[kMergeGroupWaves * K];
+  __shared__ int32_t li[kMergeGroupWaves * K];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int v = blockIdx.x / a.n_curves, c = blockIdx.x - v * a.n_curves;
+  merge_curve_group<K, kMergeGroupWaves>(a, c, v, wave, lane, lv, li);
 }
 
 // ---------------------------------------------------------------- top-k over a stored periodogram
@@ -82,10 +72,30 @@ __global__ __launch_bounds__(kTopkWaves * kWave) void topk_kernel(TopkArgs a) {
 
 // ---------------------------------------------------------------- prepare
 // One workgroup per curve: inverse variances, centring, time offsets and the
-// fixed-point scales, then the packed records.  Reductions use a fixed tree,
-// so results are deterministic.
-constexpr int kPrepThreads = 256;
+// fixed-point scales (curve_prep), then the packed records and the FP64
+// arrays of the plain comparator.
+__global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepArgs a) {
+  __shared__ double red[kPrepRed];
+  const int t = threadIdx.x;
+  for (int64_t c = blockIdx.x; c < a.n_curves; c += gridDim.x) {
+    const int64_t p0 = a.offsets[c];
+    const int n = (int)(a.offsets[c + 1] - p0);
+    const PrepConst k = curve_prep(a.t + p0, a.y + p0, a.dy + p0, n, a.center, a.tref_mode, a.t_ref, red);
+    for (int i = t; i < n; i += kPrepThreads) {
+      const int64_t p = p0 + i;
+      a.rec[p] = make_rec(a.t[p], a.y[p], a.dy[p], k, a.phase);
+      const double d = a.dy[p];
+      const double w = 1.0 / (d * d);
+      a.tau64[p] = a.t[p] - k.tref;
+      a.w64[p] = w;
+      a.wx64[p] = w * (a.y[p] - k.mu);
+    }
+    if (t == 0) a.cc[c] = make_curve_const(k, a.inv_alpha2, a.stat_scale);
+  }
+}
 
+// Fixed-tree workgroup reductions of the shared-timestamp and baseline
+// prepare kernels.
 __device__ __forceinline__ double block_sum(double v, double* red) {
   const int t = threadIdx.x;
   __syncthreads();
@@ -107,68 +117,6 @@ __device__ __forceinline__ double block_min(double v, double* red) {
     __syncthreads();
   }
   return red[0];
-}
-
-__global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepArgs a) {
-  __shared__ double red[kPrepThreads];
-  const int t = threadIdx.x;
-  for (int64_t c = blockIdx.x; c < a.n_curves; c += gridDim.x) {
-    const int64_t p0 = a.offsets[c];
-    const int n = (int)(a.offsets[c + 1] - p0);
-    double sw = 0.0, swy = 0.0, sy = 0.0, tmin = INFINITY;
-    for (int i = t; i < n; i += kPrepThreads) {
-      const double d = a.dy[p0 + i];
-      const double w = 1.0 / (d * d);
-      const double yy = a.y[p0 + i];
-      sw += w;
-      swy += w * yy;
-      sy += yy;
-      tmin = fmin(tmin, a.t[p0 + i]);
-    }
-    sw = block_sum(sw, red);
-    swy = block_sum(swy, red);
-    sy = block_sum(sy, red);
-    tmin = block_min(tmin, red);
-    const double mu = a.center == 0 ? swy / sw : (a.center == 1 ? sy / (double)n : 0.0);
-    const double tref = a.tref_mode == 0 ? 0.0 : (a.tref_mode == 1 ? tmin : a.t_ref);
-    double ay = 0.0;
-    for (int i = t; i < n; i += kPrepThreads) {
-      const double d = a.dy[p0 + i];
-      const double w = 1.0 / (d * d);
-      ay += fabs(w * (a.y[p0 + i] - mu));
-    }
-    ay = block_sum(ay, red);
-    // Fixed-point scales: sum of |weights| < 2^32 and sum of |w x| < 2^31 for
-    // any subset of points, so no bin sum can leave its 32-bit field.
-    const double s_w = (4294967296.0 - 2.0 - 2.0 * (double)n) / sw;
-    const double s_y = ay > 0.0 ? (2147483648.0 - 2.0 - (double)n) / ay : 1.0;
-    for (int i = t; i < n; i += kPrepThreads) {
-      const int64_t p = p0 + i;
-      const double d = a.dy[p];
-      const double w = 1.0 / (d * d);
-      const double wx = w * (a.y[p] - mu);
-      const double tau = a.t[p] - tref;
-      const double wqd = fmax(1.0, rint(w * s_w));
-      const uint64_t wq = (uint64_t)wqd;
-      const int64_t yq = (int64_t)rint(wx * s_y);
-      Rec r;
-      r.tau_bits = encode_tau(tau, a.phase);
-      r.pk = (wq << 32) + (uint64_t)yq;
-      a.rec[p] = r;
-      a.tau64[p] = tau;
-      a.w64[p] = w;
-      a.wx64[p] = wx;
-    }
-    if (t == 0) {
-      CurveConst k;
-      k.kc = (float)(s_w / (s_y * s_y));
-      k.ia2q = (float)(a.inv_alpha2 * s_w);
-      k.scale = a.stat_scale;
-      k.pad = 0.f;
-      a.cc[c] = k;
-    }
-    __syncthreads();
-  }
 }
 
 // ---------------------------------------------------------------- prepare, shared timestamps
@@ -479,7 +427,15 @@ hipError_t launch_bm_prepare(const BmPrepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s, bool group) {
+  if (group) {
+    const dim3 grid((unsigned)(a.n_curves * a.n_var)), block(kMergeGroupWaves * kWave);
+    if (a.topk <= 8)
+      hipLaunchKernelGGL(merge_group_kernel<8>, grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL(merge_group_kernel<16>, grid, block, 0, s, a);
+    return hipGetLastError();
+  }
   const int blocks = (a.n_curves * a.n_var + 3) / 4;
   if (a.topk <= 8)
     hipLaunchKernelGGL(merge_kernel<8>, dim3(blocks), dim3(256), 0, s, a);

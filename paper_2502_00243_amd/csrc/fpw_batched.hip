@@ -58,12 +58,66 @@ struct RO {
 //    Only vector-memory counters are waited on, so LDS atomics stay in
 //    flight; this suits large M, where the histograms leave room for few
 //    waves per CU.
-enum { SRC_SCALAR = 0, SRC_DPP = 1 };
+//  SRC_LANES (one-launch pass): each lane forms the record of one
+//    observation of a block of 64 and the wave broadcasts them one by one
+//    with readlane, so the fold waits on no memory at all.
+enum { SRC_SCALAR = 0, SRC_DPP = 1, SRC_LANES = 2 };
 
-template <int PH, int FL, int SRC>
-__device__ __forceinline__ void accumulate(const Rec* __restrict__ rc, int n, const Folder<PH> (&fo)[FL],
+// The observations of a wave: the prepared records (every source), or, in
+// the one-launch pass, records formed on the fly from the raw inputs and the
+// curve's constants (DPP source only: each lane forms the record it loads).
+struct RecSource {
+  const Rec* __restrict__ rc;
+  __device__ __forceinline__ Rec operator()(int i) const { return rc[i]; }
+};
+// SRC_LANES: the wave takes the blocks of 64 observations that start at
+// first, first + stride, ... (below n_all) of a curve.
+template <int PH>
+struct LaneSource {
+  const double* __restrict__ t;
+  const double* __restrict__ y;
+  const double* __restrict__ dy;
+  PrepConst k;
+  int first, stride, n_all;
+  __device__ __forceinline__ Rec operator()(int i) const { return make_rec(t[i], y[i], dy[i], k, PH); }
+};
+
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int q) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, q);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), q);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int PH, int FL, int SRC, class Src>
+__device__ __forceinline__ void accumulate(const Src& src, int n, const Folder<PH> (&fo)[FL],
                                            uint64_t* const (&h)[FL], int lane) {
-  if (SRC == SRC_SCALAR) {
+  if constexpr (SRC == SRC_LANES) {
+    for (int base = src.first; base < src.n_all; base += src.stride) {
+      const int cnt = min(kWave, src.n_all - base);  // wave-uniform
+      const Rec r = src(base + (lane < cnt ? lane : cnt - 1));
+      int q = 0;
+      for (; q + 4 <= cnt; q += 4) {
+        // four bins formed side by side before their atomics, so the FP64 chains overlap
+        const uint64_t t0 = lane_u64(r.tau_bits, q), t1 = lane_u64(r.tau_bits, q + 1);
+        const uint64_t t2 = lane_u64(r.tau_bits, q + 2), t3 = lane_u64(r.tau_bits, q + 3);
+#pragma unroll
+        for (int j = 0; j < FL; ++j) {
+          const int b0 = fo[j].bin(t0), b1 = fo[j].bin(t1), b2 = fo[j].bin(t2), b3 = fo[j].bin(t3);
+          lds_add(h[j] + b0 * kWave, uniform_to_vgpr(lane_u64(r.pk, q)));
+          lds_add(h[j] + b1 * kWave, uniform_to_vgpr(lane_u64(r.pk, q + 1)));
+          lds_add(h[j] + b2 * kWave, uniform_to_vgpr(lane_u64(r.pk, q + 2)));
+          lds_add(h[j] + b3 * kWave, uniform_to_vgpr(lane_u64(r.pk, q + 3)));
+        }
+      }
+      for (; q < cnt; ++q) {
+        const uint64_t tb = lane_u64(r.tau_bits, q);
+        const uint64_t pk = uniform_to_vgpr(lane_u64(r.pk, q));
+#pragma unroll
+        for (int j = 0; j < FL; ++j) lds_add(h[j] + fo[j].bin(tb) * kWave, pk);
+      }
+    }
+  } else if constexpr (SRC == SRC_SCALAR) {
+    const Rec* __restrict__ rc = src.rc;
     int i = 0;
     for (; i + kBatch <= n; i += kBatch) {
       Rec r[kBatch];
@@ -85,10 +139,10 @@ __device__ __forceinline__ void accumulate(const Rec* __restrict__ rc, int n, co
   } else {
     constexpr int kGroup = 16;
     const int sub = lane & (kGroup - 1);
-    Rec cur = rc[sub < n ? sub : n - 1];
+    Rec cur = src(sub < n ? sub : n - 1);
     for (int g = 0; g < n; g += kGroup) {
       const int nxt = g + kGroup + sub;
-      const Rec next = rc[nxt < n ? nxt : n - 1];  // prefetch (clamped, always in bounds)
+      const Rec next = src(nxt < n ? nxt : n - 1);  // prefetch (clamped, always in bounds)
       const int cnt = n - g;  // wave-uniform
       if (cnt >= kGroup) {
         // a full group, straight-line: bins of four points are formed side by
@@ -399,22 +453,29 @@ struct PeakState {
 // histogram; `part` holds the kSumParts part sums of S, and with several
 // variants `totals` the range totals and `var_sums` the derived variants'
 // sums.  Only wave 0 (the lead) stores S and keeps the peaks.
-template <int PH, int FL, int PK, int SRC, int NV, int SH>
-__device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, const Item& item, uint64_t* hist,
-                                             int lane, int wave, float* part, uint64_t* totals, float* var_sums) {
+// The observations [lo, lo + n) of a curve of n_all that wave `wave` of SH
+// folds (all of them when SH == 1).
+template <int SH>
+__device__ __forceinline__ int slice_begin(int wave, int n_all) {
+  return SH > 1 ? (int)((int64_t)wave * n_all / SH) : 0;
+}
+template <int SH>
+__device__ __forceinline__ int slice_size(int wave, int n_all) {
+  return SH > 1 ? (int)((int64_t)(wave + 1) * n_all / SH) - slice_begin<SH>(wave, n_all) : n_all;
+}
+
+// One work item: `src` yields this wave's n observations of the item's
+// curve, `cc` holds the curve's constants.
+template <int PH, int FL, int PK, int SRC, int NV, int SH, class Src>
+__device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, const Item& item, const CurveConst cc,
+                                             const Src& src, int n, uint64_t* hist, int lane, int wave, float* part,
+                                             uint64_t* totals, float* var_sums) {
   static_assert(SH == 1 || FL == 1, "a shared histogram serves one frequency per lane");
   static_assert(kSumParts % SH == 0, "each wave owns whole parts of the sum");
   const int M = a.n_bins;
   const int slots = M + 1;
   const int c = item.curve, k0 = item.k0, k1 = item.k1;
-  const int64_t p0 = ro.offsets[c];
-  const int n_all = (int)(ro.offsets[c + 1] - p0);
-  // this wave's slice of the observations (all of them when SH == 1)
-  const int lo = SH > 1 ? (int)((int64_t)wave * n_all / SH) : 0;
-  const int n = SH > 1 ? (int)((int64_t)(wave + 1) * n_all / SH) - lo : n_all;
-  const Rec* __restrict__ rc = ro.rec + p0 + lo;
   const bool lead = SH == 1 || wave == 0;
-  const CurveConst cc = ro.cc[c];
   const float outscale = cc.kc * cc.scale;
   const int nvar = NV == 1 ? 1 : a.var.n;
   const int64_t var_stride = (int64_t)a.n_curves * a.n_freq;
@@ -436,7 +497,7 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
       h[j] = hist + (j * slots) * kWave + lane;
     }
     // fold, bin and accumulate every observation of the curve (of this wave's slice)
-    if (SH == 1 || n > 0) accumulate<PH, FL, SRC>(rc, n, fo, h, lane);
+    if (SH == 1 || n > 0) accumulate<PH, FL, SRC>(src, n, fo, h, lane);
     // reduce each sub-tile of 64 frequencies, store, and pick peaks
 #pragma unroll
     for (int j = 0; j < FL; ++j) {
@@ -541,7 +602,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
     }
     if (it >= a.n_items) break;
     const Item item = items[it];
-    process_item<PH, FL, PK, SRC, NV, SH>(a, ro, item, hist, lane, wave, part, totals, var_sums);
+    const int64_t p0 = ro.offsets[item.curve];
+    const int n_all = (int)(ro.offsets[item.curve + 1] - p0);
+    const int lo = slice_begin<SH>(wave, n_all);
+    const RecSource src{ro.rec + p0 + lo};
+    process_item<PH, FL, PK, SRC, NV, SH>(a, ro, item, ro.cc[item.curve], src, slice_size<SH>(wave, n_all), hist,
+                                          lane, wave, part, totals, var_sums);
   }
   // The last wave out resets the queue, so the next launch (or graph replay)
   // starts from zero without a memset.
@@ -552,6 +618,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
       atomicExch(a.queue, 0u);
       atomicExch(a.queue + 1, 0u);
     }
+  }
+}
+
+// ---------------------------------------------------------------- fused pass
+// For small plans the dependent launches of a pass cost more than their
+// work.  Here the prepare step is fused into the fold: one workgroup of four
+// waves per work item reduces the curve's constants (the prepare kernel's
+// function, so the same values); wave w folds the blocks of 64 observations
+// starting at 64 w, 64 w + 256, ... into the shared histogram from records
+// its lanes form (the prepare kernel's records, bit for bit) and broadcast
+// with readlane; the item's S and candidate peaks are stored as by the
+// batched kernel.  Items map to workgroups one to one; there is no queue.
+// The per-curve merge follows as its own kernel: merging here would need a
+// device-wide release of every item's candidates, which costs more on this
+// chip (its L2 is per XCD) than the launch boundary.
+constexpr int kFusedShare = 4;
+
+template <int PH, int PK>
+__global__ __launch_bounds__(kFusedShare * kWave) void fused_kernel(BatchArgs a, FusedArgs o) {
+  extern __shared__ __align__(16) uint64_t lds[];
+  __shared__ double red[kPrepRed];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // uniform: keeps slice loads scalar
+  const Item item = a.items[blockIdx.x];
+  const int c = item.curve;
+  const int64_t p0 = a.offsets[c];
+  const int n_all = (int)(a.offsets[c + 1] - p0);
+  const int slots = a.n_bins + 1;
+  uint64_t* hist = lds;
+  float* part = reinterpret_cast<float*>(lds + (size_t)slots * kWave);
+  for (int s = wave; s < slots; s += kFusedShare) hist[s * kWave + lane] = 0;
+  // (the barriers of curve_prep order the clearing before any accumulation)
+  const PrepConst k = curve_prep(o.t + p0, o.y + p0, o.dy + p0, n_all, o.center, o.tref_mode, o.t_ref, red);
+  const LaneSource<PH> src{o.t + p0, o.y + p0, o.dy + p0, k, wave * kWave, kFusedShare * kWave, n_all};
+  const RO ro{nullptr, a.offsets, nullptr, a.freqs};
+  // (the count passed only tells whether this wave has observations)
+  process_item<PH, 1, PK, SRC_LANES, 1, kFusedShare>(a, ro, item, make_curve_const(k, o.inv_alpha2, o.stat_scale), src,
+                                                     n_all - wave * kWave, hist, lane, wave, part, nullptr, nullptr);
+}
+
+void* fused_fn(int phase, int pk) {
+  switch (phase) {
+    case PH_FP64: return pk ? (void*)&fused_kernel<PH_FP64, 1> : (void*)&fused_kernel<PH_FP64, 0>;
+    case PH_LISTING: return pk ? (void*)&fused_kernel<PH_LISTING, 1> : (void*)&fused_kernel<PH_LISTING, 0>;
+    case PH_DF32: return pk ? (void*)&fused_kernel<PH_DF32, 1> : (void*)&fused_kernel<PH_DF32, 0>;
+    default: return pk ? (void*)&fused_kernel<PH_FP32, 1> : (void*)&fused_kernel<PH_FP32, 0>;
   }
 }
 
@@ -626,6 +738,23 @@ hipError_t batched_groups_per_cu(const Shape& shape, int phase, int topk, int n_
   void* fn = batched_fn(phase, shape.freqs_per_lane, topk > 0, shape.point_source, n_var, shape.share);
   if (fn == nullptr) return hipErrorInvalidDeviceFunction;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, shape.waves_per_group * kWave, lds_bytes);
+}
+
+size_t fused_lds_bytes(int n_bins) {
+  return (size_t)(n_bins + 1) * kWave * sizeof(uint64_t) + (size_t)kSumParts * kWave * sizeof(float);
+}
+
+int fused_waves() { return kFusedShare; }
+
+hipError_t launch_fused(const BatchArgs& a, const FusedArgs& o, int phase, hipStream_t s) {
+  void* fn = fused_fn(phase, a.topk > 0);
+  const size_t lds_bytes = fused_lds_bytes(a.n_bins);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  BatchArgs args = a;
+  FusedArgs fused = o;
+  void* params[] = {&args, &fused};
+  return hipLaunchKernel(fn, dim3((unsigned)a.n_items), dim3(kFusedShare * kWave), params, lds_bytes, s);
 }
 
 hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int grid_groups, size_t lds_bytes,

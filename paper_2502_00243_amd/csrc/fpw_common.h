@@ -358,5 +358,182 @@ __device__ __forceinline__ void wave_select(TopList<K>& l, int k, float* out_v, 
   }
 }
 
+// ---------------------------------------------------------------- chunk merge
+// Offers chunk q's candidate list and the two peaks its first frequency and
+// its predecessor's last one may form across the boundary (decided from the
+// four edge values of each chunk); q0 = the curve's first chunk.
+template <int K>
+__device__ __forceinline__ void merge_slot(const MergeArgs& a, int q, int q0, int v, TopList<K>& l) {
+  const int nv = a.n_var;
+  const int64_t cq = ((int64_t)q * nv + v) * a.topk;
+  for (int r = 0; r < a.topk; ++r) {
+    const int ci = a.cand_idx[cq + r];
+    l.insert(a.cand_val[cq + r], ci, ci >= 0);
+  }
+  if (q > q0) {
+    // b = first frequency of this chunk, b-1 = last of the previous one
+    const int b = a.slot_k0[q];
+    const float* ep = a.edge + ((int64_t)(q - 1) * nv + v) * 4;
+    const float* eq = a.edge + ((int64_t)q * nv + v) * 4;
+    const float sa_left = ep[2], sa = ep[3], sb = eq[0], sb_right = eq[1];
+    l.insert(sa, b - 1, sa > sa_left && sa >= sb);
+    l.insert(sb, b, sb > sa && sb >= sb_right);
+  }
+}
+
+// Peaks of curve c, variant v from its chunks' candidate lists: one wave,
+// lanes take the chunks in turn, then the wave selects the curve's top k.
+// Every lane of the wave must call it.
+template <int K>
+__device__ __forceinline__ void merge_curve(const MergeArgs& a, int c, int v, int lane) {
+  TopList<K> l;
+  l.init();
+  const int q0 = a.curve_slot[c], q1 = a.curve_slot[c + 1];
+  for (int q = q0 + lane; q < q1; q += kWave) merge_slot<K>(a, q, q0, v, l);
+  const int64_t o = ((int64_t)v * a.n_curves + c) * a.topk;
+  wave_select<K>(l, a.topk, a.out_val + o, a.out_idx + o, lane);
+}
+
+// The same with the W waves of a workgroup (every thread must call it): each
+// wave selects the best k of its share of the chunks into LDS (lv, li: W * K
+// entries), then wave 0 selects the curve's k from those.  The k best of a
+// set under the strict order of `better` do not depend on how it is split,
+// so the result equals merge_curve's.
+template <int K, int W>
+__device__ __forceinline__ void merge_curve_group(const MergeArgs& a, int c, int v, int wave, int lane, float* lv,
+                                                  int32_t* li) {
+  TopList<K> l;
+  l.init();
+  const int q0 = a.curve_slot[c], q1 = a.curve_slot[c + 1];
+  for (int q = q0 + wave * kWave + lane; q < q1; q += W * kWave) merge_slot<K>(a, q, q0, v, l);
+  wave_select<K>(l, a.topk, lv + wave * K, li + wave * K, lane);
+  __syncthreads();
+  if (wave == 0) {
+    TopList<K> m;
+    m.init();
+    for (int q = lane; q < W * a.topk; q += kWave) {
+      const int w = q / a.topk, r = q - w * a.topk;
+      const int ci = li[w * K + r];
+      m.insert(lv[w * K + r], ci, ci >= 0);
+    }
+    const int64_t o = ((int64_t)v * a.n_curves + c) * a.topk;
+    wave_select<K>(m, a.topk, a.out_val + o, a.out_idx + o, lane);
+  }
+}
+
+// ---------------------------------------------------------------- per-curve preparation
+// Used by the prepare kernel and by the one-launch pass, so that both derive
+// identical constants and records from the same inputs.  A workgroup of
+// kPrepThreads threads handles one curve: thread t visits points t,
+// t + kPrepThreads, ... in order; each wave reduces with an xor butterfly
+// (both lanes of every exchange add the same two operands, so all lanes end
+// with the same value) and the wave totals are combined in wave order.  The
+// results are identical in every thread and reproducible.
+constexpr int kPrepThreads = 256;
+constexpr int kPrepWaves = kPrepThreads / kWave;
+constexpr int kPrepRed = 5 * kPrepWaves;  // doubles of LDS the reduction needs
+
+// Centring, reference time and fixed-point scales of one curve.
+struct PrepConst {
+  double mu, tref, s_w, s_y;
+};
+
+__device__ __forceinline__ double wave_sum_all(double v) {
+#pragma unroll
+  for (int s = kWave / 2; s > 0; s >>= 1) v += __shfl_xor(v, s);
+  return v;
+}
+__device__ __forceinline__ double wave_min_all(double v) {
+#pragma unroll
+  for (int s = kWave / 2; s > 0; s >>= 1) v = fmin(v, __shfl_xor(v, s));
+  return v;
+}
+
+// Every thread of the workgroup must call it (it holds barriers); `red` is
+// kPrepRed doubles of LDS.  Weights w = 1/dy^2; the centre is the weighted
+// mean, the plain mean or 0 (center 0, 1, 2); the reference time 0, min(t)
+// or t_ref (tref_mode 0, 1, 2).  Fixed-point scales: the sum of the weights
+// of any subset of points stays below 2^32 and the sum of |w x| below 2^31,
+// so no bin sum can leave its 32-bit field.
+__device__ __forceinline__ PrepConst curve_prep(const double* __restrict__ t, const double* __restrict__ y,
+                                                const double* __restrict__ dy, int n, int center, int tref_mode,
+                                                double t_ref, double* red) {
+  const int th = threadIdx.x, lane = th & (kWave - 1), wave = th / kWave;
+  double sw = 0.0, swy = 0.0, sy = 0.0, tmin = INFINITY;
+  for (int i = th; i < n; i += kPrepThreads) {
+    const double d = dy[i];
+    const double w = 1.0 / (d * d);
+    const double yy = y[i];
+    sw += w;
+    swy += w * yy;
+    sy += yy;
+    tmin = fmin(tmin, t[i]);
+  }
+  sw = wave_sum_all(sw);
+  swy = wave_sum_all(swy);
+  sy = wave_sum_all(sy);
+  tmin = wave_min_all(tmin);
+  __syncthreads();  // earlier readers of red are done
+  if (lane == 0) {
+    red[wave] = sw;
+    red[kPrepWaves + wave] = swy;
+    red[2 * kPrepWaves + wave] = sy;
+    red[3 * kPrepWaves + wave] = tmin;
+  }
+  __syncthreads();
+  sw = red[0];
+  swy = red[kPrepWaves];
+  sy = red[2 * kPrepWaves];
+  tmin = red[3 * kPrepWaves];
+#pragma unroll
+  for (int w = 1; w < kPrepWaves; ++w) {
+    sw += red[w];
+    swy += red[kPrepWaves + w];
+    sy += red[2 * kPrepWaves + w];
+    tmin = fmin(tmin, red[3 * kPrepWaves + w]);
+  }
+  PrepConst k;
+  k.mu = center == 0 ? swy / sw : (center == 1 ? sy / (double)n : 0.0);
+  k.tref = tref_mode == 0 ? 0.0 : (tref_mode == 1 ? tmin : t_ref);
+  double ay = 0.0;
+  for (int i = th; i < n; i += kPrepThreads) {
+    const double d = dy[i];
+    const double w = 1.0 / (d * d);
+    ay += fabs(w * (y[i] - k.mu));
+  }
+  ay = wave_sum_all(ay);
+  if (lane == 0) red[4 * kPrepWaves + wave] = ay;
+  __syncthreads();
+  ay = red[4 * kPrepWaves];
+#pragma unroll
+  for (int w = 1; w < kPrepWaves; ++w) ay += red[4 * kPrepWaves + w];
+  k.s_w = (4294967296.0 - 2.0 - 2.0 * (double)n) / sw;
+  k.s_y = ay > 0.0 ? (2147483648.0 - 2.0 - (double)n) / ay : 1.0;
+  return k;
+}
+
+// The record of one observation: time offset in the phase mode's encoding,
+// fixed-point weight (at least 1, so that every occupied bin has W >= 1) and
+// weighted residual.
+__device__ __forceinline__ Rec make_rec(double t, double y, double dy, const PrepConst& k, int phase) {
+  const double w = 1.0 / (dy * dy);
+  const double wx = w * (y - k.mu);
+  const uint64_t wq = (uint64_t)fmax(1.0, rint(w * k.s_w));
+  const int64_t yq = (int64_t)rint(wx * k.s_y);
+  Rec r;
+  r.tau_bits = encode_tau(t - k.tref, phase);
+  r.pk = (wq << 32) + (uint64_t)yq;
+  return r;
+}
+
+__device__ __forceinline__ CurveConst make_curve_const(const PrepConst& k, double inv_alpha2, float stat_scale) {
+  CurveConst c;
+  c.kc = (float)(k.s_w / (k.s_y * k.s_y));
+  c.ia2q = (float)(inv_alpha2 * k.s_w);
+  c.scale = stat_scale;
+  c.pad = 0.f;
+  return c;
+}
+
 }  // namespace dev
 }  // namespace fpw

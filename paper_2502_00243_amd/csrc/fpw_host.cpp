@@ -120,6 +120,8 @@ struct fpw_plan_s {
   int bm_share = 1;   // waves per histogram of the baseline kernel
   int bm_source = 0;  // its point source: 0 scalar loads, 1 vector loads + DPP broadcast
   DevBuf bm_rec, bm_z, bm_const, bm_S;
+  // fused pass (small plans): prepare fused into the fold kernel, then the merge
+  bool fused = false;
   // profiling events: before prepare, after prepare, after batched, after merge
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool ev_recorded = false;
@@ -146,6 +148,9 @@ const int kShare4MinBins = 32;
 // one variant (their extra waves hide the scalar loads' waits up to M ~ 100).
 const int kDppMinBins = 32;
 const int kDppMinBinsShared = 128;
+// Largest plan that runs the fused pass by default, in items of 64
+// frequencies per CU: up to there every item gets a workgroup at once.
+const int kFusedItemsPerCu = 4;
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -193,6 +198,12 @@ fpw_status check_options(const fpw_options& o) {
   if (nvar > 1 && o.hist_share > 1 && o.phase >= FPW_PHASE_DF32)
     return fail(FPW_EUNSUPPORTED, "derived bin counts with a shared histogram are built for the FP64 phase modes");
   if (o.shared_kernel < 0 || o.shared_kernel > 2) return fail(FPW_EINVAL, "shared_kernel must be 0, 1 or 2");
+  if (o.fuse_prepare < -1 || o.fuse_prepare > 1) return fail(FPW_EINVAL, "fuse_prepare must be -1, 0 or 1");
+  if (o.fuse_prepare == 1 && (nvar > 1 || o.baseline_terms != 0))
+    return fail(FPW_EUNSUPPORTED, "the fused pass serves plans with one periodogram variant and no baseline terms");
+  if (o.fuse_prepare == 1 && (o.freqs_per_lane == 2 || o.point_source != 0 || o.waves_per_group == 1 ||
+                              o.waves_per_group == 2 || o.hist_share == 1 || o.hist_share == 2))
+    return fail(FPW_EUNSUPPORTED, "the fused pass runs four waves per histogram and its own point source");
   if (o.baseline_terms < 0) return fail(FPW_EINVAL, "baseline_terms must be >= 0");
   if (o.baseline_terms > FPW_MAX_BASELINE_TERMS)
     return fail(FPW_EUNSUPPORTED, "baseline_terms %d exceeds FPW_MAX_BASELINE_TERMS=%d", o.baseline_terms, FPW_MAX_BASELINE_TERMS);
@@ -541,11 +552,35 @@ fpw_status enqueue_bm_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hi
   return FPW_OK;
 }
 
+fpw::FusedArgs fused_args(const fpw_plan_s* p) {
+  fpw::FusedArgs o{};
+  o.t = p->t.as<double>();
+  o.y = p->y.as<double>();
+  o.dy = p->dy.as<double>();
+  o.center = p->opt.center;
+  o.tref_mode = p->opt.tref_mode;
+  o.t_ref = p->opt.t_ref;
+  o.inv_alpha2 = p->opt.inv_alpha2;
+  o.stat_scale = p->opt.stat_scale == FPW_STAT_LISTING_HALF ? 0.5f : 1.0f;
+  return o;
+}
+
 // One full pass: prepare, fold/bin/accumulate/reduce (+ fused peaks), merge.
 fpw_status enqueue_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipStream_t s) {
   if (p->mfma) return enqueue_shared_pass(p, S, idx, val, s);
   if (p->bm) return enqueue_bm_pass(p, S, idx, val, s);
   const bool prof = p->opt.profile != 0;
+  if (p->fused) {
+    // prepare runs inside the fold kernel: its time is reported as the batched kernel's
+    if (prof) FPW_HIP(hipEventRecord(p->ev[0], s), "event record");
+    if (prof) FPW_HIP(hipEventRecord(p->ev[1], s), "event record");
+    FPW_HIP(fpw::launch_fused(batch_args(p, S, p->items, p->n_items), fused_args(p), p->opt.phase, s), "fused kernel");
+    if (prof) FPW_HIP(hipEventRecord(p->ev[2], s), "event record");
+    if (idx != nullptr) FPW_HIP(fpw::launch_merge(merge_args(p, idx, val), s, true), "merge kernel");
+    if (prof) FPW_HIP(hipEventRecord(p->ev[3], s), "event record");
+    p->ev_merge = idx != nullptr;
+    return FPW_OK;
+  }
   if (prof) FPW_HIP(hipEventRecord(p->ev[0], s), "event record");
   FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
   if (prof) FPW_HIP(hipEventRecord(p->ev[1], s), "event record");
@@ -812,7 +847,24 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     const int fl = (src == 1 || p->var.n > 1 || share > 1) ? 1 : (o.freqs_per_lane ? o.freqs_per_lane : 1);
     const int wpg = share > 1 ? share : (o.waves_per_group ? o.waves_per_group : 1);
     fpw::Shape sh{fl, wpg, o.chunk_freqs, src, share};
-    if (o.autotune && !o.freqs_per_lane && !o.waves_per_group && !o.chunk_freqs && !o.point_source && !o.hist_share) {
+    // The fused pass for small plans (at most kFusedItemsPerCu items of 64
+    // frequencies per CU) unless a launch shape was asked for.
+    const int64_t items64 = n_curves * ((n_freq + kWave - 1) / kWave);
+    const bool overrides = o.freqs_per_lane || o.waves_per_group || o.chunk_freqs || o.point_source || o.hist_share;
+    const bool fused_ok = p->var.n == 1 && o.baseline_terms == 0 &&
+                          fpw::fused_lds_bytes(o.n_bins) + 1024 <= (size_t)160 * 1024;
+    p->fused = fused_ok && (o.fuse_prepare == 1 ||
+                            (o.fuse_prepare == 0 && !overrides && items64 <= (int64_t)kFusedItemsPerCu * p->n_cu));
+    if (p->fused) {
+      // items of 64 frequencies, or longer ones where a forced plan would exceed the per-CU budget
+      const int64_t budget = (int64_t)kFusedItemsPerCu * p->n_cu;
+      const int64_t per_curve = std::max<int64_t>(1, budget / n_curves);
+      int64_t chunk = o.chunk_freqs ? o.chunk_freqs : (n_freq + per_curve - 1) / per_curve;
+      chunk = std::min<int64_t>(std::max<int64_t>(chunk, kWave), std::max<int64_t>(n_freq, kWave));
+      p->shape = fpw::Shape{1, fpw::fused_waves(), round_up(chunk, kWave), 0, fpw::fused_waves()};
+      p->lds_bytes = fpw::fused_lds_bytes(o.n_bins);
+      st = FPW_OK;
+    } else if (o.autotune && !overrides) {
       st = autotune(p, s);
     } else {
       st = configure_shape(p, sh);
@@ -820,6 +872,7 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     if (st != FPW_OK) return st;
     st = upload_items(p);
     if (st != FPW_OK) return st;
+    if (p->fused) p->grid_groups = p->n_items;
     if (o.baseline_terms > 0) {
       p->bm = true;
       FPW_HIP(p->bm_rec.alloc(np * sizeof(fpw::Rec)), "alloc baseline records");
@@ -932,7 +985,7 @@ fpw_status fpw_eval_batch(fpw_plan_t p, float* S_dev, int32_t* topk_idx, float* 
   try {
     // Profiling records plain stream events, so a profiled pass is launched
     // directly rather than replayed from the graph.
-    if (p->opt.use_graph && p->graph_ok && !p->opt.profile) {
+    if (p->opt.use_graph && p->graph_ok && !p->opt.profile && !p->fused) {
       fpw_plan_s::Graph* hit = nullptr;
       for (fpw_plan_s::Graph& e : p->graphs)
         if (e.S == S_dev && e.idx == topk_idx && e.val == topk_val) hit = &e;
@@ -1113,6 +1166,8 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   info->n_variants = p->var.n;
   info->kernel = p->mfma ? 1 : (p->bm ? 2 : 0);
   info->hist_share = p->shape.share;
+  info->fuse_prepare = p->fused && !p->mfma ? 1 : 0;
+  if (info->fuse_prepare) info->point_source = 3;
   if (p->bm) {
     info->grid_groups = p->bm_grid;
     info->waves_per_group = p->bm_share;

@@ -83,6 +83,18 @@ struct BatchArgs {
   uint32_t* queue;        // [2]: next item, finished waves (self-resetting)
 };
 
+// Raw inputs of the fused pass, whose fold kernel prepares every curve itself.
+struct FusedArgs {
+  const double* t;
+  const double* y;
+  const double* dy;
+  int center;        // FPW_CENTER_*
+  int tref_mode;     // FPW_TREF_*
+  double t_ref;
+  double inv_alpha2;
+  float stat_scale;
+};
+
 struct MergeArgs {
   const float* cand_val;
   const int32_t* cand_idx;
@@ -250,7 +262,14 @@ struct Shape {
 hipError_t launch_prepare(const PrepArgs& a, hipStream_t s);
 hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int grid_groups,
                           size_t lds_bytes, hipStream_t s);  // n_var > 1 needs one frequency per lane
-hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s, bool group = false);
+// Fused pass of a small plan: prepare + fold/bin/accumulate/reduce + peaks
+// in workgroups of fused_waves() waves, one per item of a.items (a.n_items
+// of them); then launch_merge with `group` set merges each curve's peaks
+// with one workgroup of four waves.
+hipError_t launch_fused(const BatchArgs& a, const FusedArgs& o, int phase, hipStream_t s);
+size_t fused_lds_bytes(int n_bins);
+int fused_waves();
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
 hipError_t launch_fp64(const Fp64Args& a, hipStream_t s);
 hipError_t launch_bins(const BinsArgs& a, hipStream_t s);

@@ -60,6 +60,7 @@ class Options(ctypes.Structure):
         ("baseline_terms", ctypes.c_int32),
         ("baseline_scale", ctypes.c_double),
         ("hist_share", ctypes.c_int32),
+        ("fuse_prepare", ctypes.c_int32),
     ]
 
 
@@ -83,6 +84,7 @@ class PlanInfo(ctypes.Structure):
         ("n_variants", ctypes.c_int32),
         ("kernel", ctypes.c_int32),
         ("hist_share", ctypes.c_int32),
+        ("fuse_prepare", ctypes.c_int32),
     ]
 
 
@@ -160,7 +162,8 @@ def default_options() -> Options:
 def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="fp64", stat_scale="eq1", topk=0,
                  inv_alpha2=0.0, autotune=False, use_graph=True, freqs_per_lane=0, waves_per_group=0, chunk_freqs=0,
                  tune_cache=None, profile=False, point_source=0, derived_bins=(), all_offsets=False,
-                 shared_kernel=0, baseline_terms=0, baseline_scale=1.0, hist_share=0) -> Options:
+                 shared_kernel=0, baseline_terms=0, baseline_scale=1.0, hist_share=0,
+                 fuse_prepare=0) -> Options:
     o = default_options()
     o.n_bins = int(n_bins)
     o.center = CENTER[center] if isinstance(center, str) else int(center)
@@ -187,6 +190,7 @@ def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="
     o.baseline_terms = int(baseline_terms)
     o.baseline_scale = float(baseline_scale)
     o.hist_share = int(hist_share)
+    o.fuse_prepare = int(fuse_prepare)
     return o
 
 

@@ -40,7 +40,14 @@ hipError_t hipStreamDestroy(hipStream_t s) { std::free(s); return hipSuccess; }
 namespace fpw {
 hipError_t launch_prepare(const PrepArgs&, hipStream_t) { return hipSuccess; }
 hipError_t launch_batched(const BatchArgs&, const Shape&, int, int, size_t, hipStream_t) { return hipSuccess; }
-hipError_t launch_merge(const MergeArgs&, hipStream_t) { return hipSuccess; }
+hipError_t launch_merge(const MergeArgs&, hipStream_t, bool) { return hipSuccess; }
+hipError_t launch_fused(const BatchArgs& a, const FusedArgs& o, int, hipStream_t) {
+  // one workgroup per item
+  if (a.n_items < 1 || a.items == nullptr || o.t == nullptr) return hipErrorInvalidValue;
+  return hipSuccess;
+}
+size_t fused_lds_bytes(int n_bins) { return (size_t)(n_bins + 1) * 512 + 1024; }
+int fused_waves() { return 4; }
 hipError_t launch_topk(const TopkArgs&, hipStream_t) { return hipSuccess; }
 hipError_t launch_fp64(const Fp64Args&, hipStream_t) { return hipSuccess; }
 hipError_t launch_bins(const BinsArgs&, hipStream_t) { return hipSuccess; }

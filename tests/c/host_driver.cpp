@@ -135,6 +135,19 @@ int main(int argc, char** argv) {
     o.profile = 1;
     run(b, o, "phase plan");
   }
+  // the fused pass: forced, refused, with a chunk override, two phase modes
+  for (int single : {-1, 0, 1})
+    for (int phase : {0, 3})
+      for (int chunk : {0, 100}) {
+        fpw_options_default(&o);
+        o.n_bins = 20;
+        o.phase = phase;
+        o.fuse_prepare = single;
+        o.chunk_freqs = chunk;
+        o.topk = 4;
+        o.profile = chunk != 0;
+        run(b, o, "fused plan");
+      }
   fpw_options_default(&o);
   o.n_bins = 20;
   o.freqs_per_lane = 2;
@@ -149,6 +162,7 @@ int main(int argc, char** argv) {
       o.n_bins = 40;
       o.topk = 5;
       o.autotune = 1;
+      o.fuse_prepare = -1;  // small enough for the fused pass, which is not tuned
       o.tune_cache = argv[1];
       run(b, o, "autotune plan");
     }

@@ -36,7 +36,7 @@ def test_options_defaults():
     o = fpw.default_options()
     assert (o.n_bins, o.center, o.tref_mode, o.phase, o.stat_scale, o.topk) == (10, 0, 0, 0, 0, 0)
     assert o.inv_alpha2 == 0.0 and o.use_graph == 1 and o.autotune == 0
-    assert o.hist_share == 0 and o.baseline_terms == 0 and o.baseline_scale == 1.0
+    assert o.hist_share == 0 and o.baseline_terms == 0 and o.baseline_scale == 1.0 and o.fuse_prepare == 0
     assert fpw.load().fpw_version().decode().startswith("fpw ")
 
 
@@ -82,6 +82,12 @@ CASES = [
     ("negative hist share", dict(opts=dict(hist_share=-2)), fpw.EINVAL),
     ("hist share with other waves per group", dict(opts=dict(hist_share=2, waves_per_group=4)), fpw.EINVAL),
     ("hist share with two freqs per lane", dict(opts=dict(hist_share=2, freqs_per_lane=2)), fpw.EUNSUPPORTED),
+    ("bad fuse prepare", dict(opts=dict(fuse_prepare=2)), fpw.EINVAL),
+    ("fused pass with variants", dict(n_bins=12, opts=dict(fuse_prepare=1, derived_bins=(6,))), fpw.EUNSUPPORTED),
+    ("fused pass with baseline", dict(opts=dict(fuse_prepare=1, baseline_terms=1)), fpw.EUNSUPPORTED),
+    ("fused pass with a point source", dict(opts=dict(fuse_prepare=1, point_source=2)), fpw.EUNSUPPORTED),
+    ("fused pass with private histograms", dict(opts=dict(fuse_prepare=1, hist_share=1)), fpw.EUNSUPPORTED),
+    ("fused pass with two waves", dict(opts=dict(fuse_prepare=1, waves_per_group=2)), fpw.EUNSUPPORTED),
     ("hist share in df32 with variants", dict(n_bins=12, opts=dict(hist_share=4, phase="df32", derived_bins=(6,))),
      fpw.EUNSUPPORTED),
 ]

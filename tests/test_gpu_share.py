@@ -149,25 +149,26 @@ def test_shared_histogram_multi_m(share):
 def test_default_share_by_bin_count():
     _say("default share by M")
     b = synth.random_batch(90, 6, 20, 100, np.linspace(0.1, 5.0, 200), 10)
+    one = dict(fuse_prepare=-1)  # a batch this small would otherwise run the fused pass
     # M: (waves per histogram, point source 1 scalar / 2 DPP)
     expect = {10: (1, 1), 15: (1, 1), 16: (2, 1), 31: (2, 1), 32: (4, 1), 127: (4, 1), 128: (4, 2), 255: (4, 2)}
     for M, (sh, src) in expect.items():
-        p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, M)
+        p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, M, **one)
         assert (p.info().hist_share, p.info().point_source) == (sh, src), M
         p.close()
-    p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, hist_share=1)
+    p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, hist_share=1, **one)
     assert p.info().point_source == 2  # private histograms at large M: DPP source
     p.close()
     # private where no shared form is built or another group shape was asked for
     for opts in (dict(phase="df32", derived_bins=(20,)), dict(waves_per_group=2), dict(freqs_per_lane=2)):
-        p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, **opts)
+        p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, **opts, **one)
         assert p.info().hist_share == 1, opts
         p.close()
-    p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, derived_bins=(20,))
+    p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, derived_bins=(20,), **one)
     assert (p.info().hist_share, p.info().point_source) == (4, 2)  # derived bin counts share too, DPP source
     p.close()
     for phase in ("df32", "fp32"):  # the study modes share with one variant
-        p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, phase=phase)
+        p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, phase=phase, **one)
         assert p.info().hist_share == 4, phase
         p.close()
 
@@ -193,7 +194,7 @@ def test_stress_shape_with_shared_histograms_sampled():
     b = synth.stress_batch(8)
     fi = np.sort(np.random.default_rng(3).choice(len(b.freqs), 400, replace=False))
     freqs = b.freqs[fi]
-    p = fpw.Plan(b.offsets, b.t, b.y, b.dy, freqs, b.n_bins, topk=5)
-    assert p.info().hist_share == 4
+    p = fpw.Plan(b.offsets, b.t, b.y, b.dy, freqs, b.n_bins, topk=5, fuse_prepare=-1)
+    assert p.info().hist_share == 4 and p.info().fuse_prepare == 0
     _check_against_oracle(p, b.offsets, b.t, b.y, b.dy, freqs, b.n_bins, {}, False)
     p.close()
