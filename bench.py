@@ -118,13 +118,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--workload", default="ztf1000",
-                    choices=["ztf1000", "uneven", "stress", "precision", "sweep", "shared", "baseline"],
+                    choices=["ztf1000", "uneven", "stress", "precision", "sweep", "shared", "baseline", "latency"],
                     help="ztf1000: the headline line (default); uneven: 1e5 uneven curves, 2e5 freqs, "
                          "M in {10,20,40}, top-5; stress: 2e4 x 3000-point curves, 1e6 freqs, M=50, top-5; "
                          "precision: phase-arithmetic study on the ztf1000 data; "
                          "sweep: launch shapes x M on the ztf1000 data; "
                          "shared: 1000 curves at 500 common epochs, 1e5 freqs, M=20, matrix-core vs general kernel; "
-                         "baseline: the ztf1000 data with a marginalised 3-term baseline (App. A general case)")
+                         "baseline: the ztf1000 data with a marginalised 3-term baseline (App. A general case); "
+                         "latency: one curve of 200 points, 1e4 freqs, M=10, fused vs three-kernel pass")
     ap.add_argument("--curves", type=int, default=0, help="curve count override for uneven/stress")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -143,6 +144,8 @@ def main():
         return bench_shared(args)
     if args.workload == "baseline":
         return bench_baseline(args)
+    if args.workload == "latency":
+        return bench_latency(args)
 
     import numpy as np
 
@@ -233,27 +236,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    # single-curve latency (1 curve, 200 points, 1e4 frequencies, M = 10), outputs preallocated
-    # (the default plan runs the fused pass; the three-kernel pass is timed beside it)
     lat_us = lat3_us = None
     if not args.no_latency:
-        b1 = synth.single_curve()
-        S1 = torch.empty((1, len(b1.freqs)), dtype=torch.float32, device="cuda")
-        i1 = torch.empty((1, 1), dtype=torch.int32, device="cuda")
-        v1 = torch.empty((1, 1), dtype=torch.float32, device="cuda")
-        lats = []
-        for fuse in (0, -1):
-            p1 = fpw.Plan.from_batch(b1, topk=1, fuse_prepare=fuse)
-            for _ in range(3):
-                p1.eval(S_out=S1, idx_out=i1, val_out=v1)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(50):
-                p1.eval(S_out=S1, idx_out=i1, val_out=v1)
-            torch.cuda.synchronize()
-            lats.append((time.perf_counter() - t1) / 50 * 1e6)
-            p1.close()
-        lat_us, lat3_us = lats
+        lat_us, lat3_us = single_curve_latency(50)
 
     out = {
         "metric": METRIC,
@@ -526,6 +511,43 @@ def bench_stress(args):
                                     "fp64_plain": fp, "speedup": (sub.evals() / wall_s / 1e9) / fp["value"]},
                       "cpu_baseline": cpu}),
           flush=True)
+
+
+def single_curve_latency(passes):
+    """Back-to-back µs per pass of one curve (200 points, 1e4 frequencies, M = 10, top-1), outputs
+    preallocated: (default plan = fused pass, three-kernel pass)."""
+    import torch
+
+    from paper_2502_00243_amd import fpw, synth
+
+    b1 = synth.single_curve()
+    S1 = torch.empty((1, len(b1.freqs)), dtype=torch.float32, device="cuda")
+    i1 = torch.empty((1, 1), dtype=torch.int32, device="cuda")
+    v1 = torch.empty((1, 1), dtype=torch.float32, device="cuda")
+    lats = []
+    for fuse in (0, -1):
+        p1 = fpw.Plan.from_batch(b1, topk=1, fuse_prepare=fuse)
+        for _ in range(3):
+            p1.eval(S_out=S1, idx_out=i1, val_out=v1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(passes):
+            p1.eval(S_out=S1, idx_out=i1, val_out=v1)
+        torch.cuda.synchronize()
+        lats.append((time.perf_counter() - t1) / passes * 1e6)
+        p1.close()
+    return lats[0], lats[1]
+
+
+def bench_latency(args):
+    import torch
+
+    torch.cuda.set_device(0)
+    fused, three = single_curve_latency(max(50, args.steps * 10))
+    print(json.dumps({"workload": "single light curve: 200 points over 1000 d, 1e4 frequencies 0.01-10 /d, M=10, "
+                                  "S + top-1, outputs preallocated, passes back to back",
+                      "latency_us": fused, "latency_three_kernels_us": three, "unit": "us per pass",
+                      "passes": max(50, args.steps * 10)}), flush=True)
 
 
 def bench_precision(args):

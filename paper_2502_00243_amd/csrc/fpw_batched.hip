@@ -71,7 +71,8 @@ struct RecSource {
   __device__ __forceinline__ Rec operator()(int i) const { return rc[i]; }
 };
 // SRC_LANES: the wave takes the blocks of 64 observations that start at
-// first, first + stride, ... (below n_all) of a curve.
+// first, first + stride, ... (below n_all) of a curve; `r0` is the lane's
+// record of the first block, formed beforehand.
 template <int PH>
 struct LaneSource {
   const double* __restrict__ t;
@@ -79,6 +80,7 @@ struct LaneSource {
   const double* __restrict__ dy;
   PrepConst k;
   int first, stride, n_all;
+  Rec r0;
   __device__ __forceinline__ Rec operator()(int i) const { return make_rec(t[i], y[i], dy[i], k, PH); }
 };
 
@@ -94,7 +96,7 @@ __device__ __forceinline__ void accumulate(const Src& src, int n, const Folder<P
   if constexpr (SRC == SRC_LANES) {
     for (int base = src.first; base < src.n_all; base += src.stride) {
       const int cnt = min(kWave, src.n_all - base);  // wave-uniform
-      const Rec r = src(base + (lane < cnt ? lane : cnt - 1));
+      const Rec r = base == src.first ? src.r0 : src(base + (lane < cnt ? lane : cnt - 1));
       int q = 0;
       for (; q + 4 <= cnt; q += 4) {
         // four bins formed side by side before their atomics, so the FP64 chains overlap
@@ -466,10 +468,12 @@ __device__ __forceinline__ int slice_size(int wave, int n_all) {
 
 // One work item: `src` yields this wave's n observations of the item's
 // curve, `cc` holds the curve's constants.
+// `f_first`, if set, holds the lane's frequency of the item's first
+// sub-tile (loaded early by the caller).
 template <int PH, int FL, int PK, int SRC, int NV, int SH, class Src>
 __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, const Item& item, const CurveConst cc,
                                              const Src& src, int n, uint64_t* hist, int lane, int wave, float* part,
-                                             uint64_t* totals, float* var_sums) {
+                                             uint64_t* totals, float* var_sums, const double* f_first = nullptr) {
   static_assert(SH == 1 || FL == 1, "a shared histogram serves one frequency per lane");
   static_assert(kSumParts % SH == 0, "each wave owns whole parts of the sum");
   const int M = a.n_bins;
@@ -493,7 +497,7 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
 #pragma unroll
     for (int j = 0; j < FL; ++j) {
       const int k = kt + j * kWave + lane;
-      fo[j].init(ro.freqs[k < k1 ? k : k1 - 1], M);
+      fo[j].init(f_first != nullptr && FL == 1 && kt == k0 ? *f_first : ro.freqs[k < k1 ? k : k1 - 1], M);
       h[j] = hist + (j * slots) * kWave + lane;
     }
     // fold, bin and accumulate every observation of the curve (of this wave's slice)
@@ -650,12 +654,19 @@ __global__ __launch_bounds__(kFusedShare * kWave) void fused_kernel(BatchArgs a,
   float* part = reinterpret_cast<float*>(lds + (size_t)slots * kWave);
   for (int s = wave; s < slots; s += kFusedShare) hist[s * kWave + lane] = 0;
   // (the barriers of curve_prep order the clearing before any accumulation)
-  const PrepConst k = curve_prep(o.t + p0, o.y + p0, o.dy + p0, n_all, o.center, o.tref_mode, o.t_ref, red);
-  const LaneSource<PH> src{o.t + p0, o.y + p0, o.dy + p0, k, wave * kWave, kFusedShare * kWave, n_all};
+  // the first sub-tile's frequency, loaded while the curve is reduced
+  const double f0 = a.freqs[min(item.k0 + lane, item.k1 - 1)];
+  // thread t = 64 w + lane reads observation t in curve_prep, which is this
+  // lane's observation of wave w's first block: its record needs no reload
+  double keep[3];
+  const PrepConst k = curve_prep(o.t + p0, o.y + p0, o.dy + p0, n_all, o.center, o.tref_mode, o.t_ref, red, keep);
+  const LaneSource<PH> src{o.t + p0, o.y + p0, o.dy + p0, k, wave * kWave, kFusedShare * kWave, n_all,
+                           make_rec(keep[0], keep[1], keep[2], k, PH)};
   const RO ro{nullptr, a.offsets, nullptr, a.freqs};
   // (the count passed only tells whether this wave has observations)
   process_item<PH, 1, PK, SRC_LANES, 1, kFusedShare>(a, ro, item, make_curve_const(k, o.inv_alpha2, o.stat_scale), src,
-                                                     n_all - wave * kWave, hist, lane, wave, part, nullptr, nullptr);
+                                                     n_all - wave * kWave, hist, lane, wave, part, nullptr, nullptr,
+                                                     &f0);
 }
 
 void* fused_fn(int phase, int pk) {

@@ -450,24 +450,36 @@ __device__ __forceinline__ double wave_min_all(double v) {
 }
 
 // Every thread of the workgroup must call it (it holds barriers); `red` is
-// kPrepRed doubles of LDS.  Weights w = 1/dy^2; the centre is the weighted
+// kPrepRed doubles of LDS.  If `keep` is set, thread t also returns the
+// (t, y, dy) of observation t there (0, 0, 1 where t >= n).  Weights w = 1/dy^2; the centre is the weighted
 // mean, the plain mean or 0 (center 0, 1, 2); the reference time 0, min(t)
 // or t_ref (tref_mode 0, 1, 2).  Fixed-point scales: the sum of the weights
 // of any subset of points stays below 2^32 and the sum of |w x| below 2^31,
 // so no bin sum can leave its 32-bit field.
 __device__ __forceinline__ PrepConst curve_prep(const double* __restrict__ t, const double* __restrict__ y,
                                                 const double* __restrict__ dy, int n, int center, int tref_mode,
-                                                double t_ref, double* red) {
+                                                double t_ref, double* red, double* keep = nullptr) {
   const int th = threadIdx.x, lane = th & (kWave - 1), wave = th / kWave;
   double sw = 0.0, swy = 0.0, sy = 0.0, tmin = INFINITY;
+  if (keep != nullptr) {
+    keep[0] = 0.0;
+    keep[1] = 0.0;
+    keep[2] = 1.0;
+  }
   for (int i = th; i < n; i += kPrepThreads) {
     const double d = dy[i];
     const double w = 1.0 / (d * d);
     const double yy = y[i];
+    const double tt = t[i];
+    if (keep != nullptr && i == th) {
+      keep[0] = tt;
+      keep[1] = yy;
+      keep[2] = d;
+    }
     sw += w;
     swy += w * yy;
     sy += yy;
-    tmin = fmin(tmin, t[i]);
+    tmin = fmin(tmin, tt);
   }
   sw = wave_sum_all(sw);
   swy = wave_sum_all(swy);
