@@ -256,9 +256,20 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const Rec* __r
     if (NZ == NZ_PAIR) hz[m * SW] = 0;
     if (NZ == NZ_ONE) hz32[m * kWave] = 0;
   }
-  for (;;) {
+  // With at most one item per consumer (a wave, or a workgroup sharing a
+  // histogram), consumer c takes item c and no atomics are needed.
+  // Otherwise every item is popped from the queue, whose counter the pass's
+  // prepare kernel has zeroed: popping the first item too staggers the
+  // consumers' starts, which keeps their later pops apart (taking the first
+  // item by index measured 4.8 % slower on 1000 curves x 1e5 frequencies).
+  const int per_group = SH > 1 ? 1 : (int)(blockDim.x / kWave);
+  const bool by_index = a.n_items <= (int)gridDim.x * per_group;
+  for (int round = 0;; ++round) {
     int it = 0;
-    if (SH > 1) {
+    if (by_index) {
+      if (round > 0) break;
+      it = (int)blockIdx.x * per_group + (SH > 1 ? 0 : wave);
+    } else if (SH > 1) {
       // one pop per workgroup; the previous item's barriers order this write
       // after every wave's read of the previous index
       if (threadIdx.x == 0) *group_item = (int)atomicAdd(a.queue, 1u);
@@ -308,14 +319,6 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const Rec* __r
           if (k < k1) a.S[(int64_t)c * a.n_freq + k] = (float)(bm_statistic(sums, bc) * bc.scale);
         }
       }
-    }
-  }
-  if (lane == 0) {
-    __threadfence();
-    const uint32_t total = gridDim.x * SH;
-    if (atomicAdd(a.queue + 1, 1u) == total - 1) {
-      atomicExch(a.queue, 0u);
-      atomicExch(a.queue + 1, 0u);
     }
   }
 }

@@ -21,7 +21,8 @@
 //    comes out of the low word of one more FP64 fma, so a fold costs three
 //    FP64 instructions plus the LDS address;
 //  * work is a queue of (curve, frequency chunk) items, longest curves first,
-//    popped by persistent waves (or groups of waves) with one atomic each;
+//    popped by persistent waves (or groups of waves) with one atomic each
+//    (small plans: one item per wave or group, taken by index);
 //    the peak selection is fused so that large periodograms never reach HBM;
 //  * for large M a histogram per wave leaves room for few waves per CU, so
 //    SH > 1 waves of a workgroup share one: each folds a contiguous slice of
@@ -592,9 +593,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
   } else {
     for (int s = 0; s < FL * slots; ++s) hist[s * kWave + lane] = 0;
   }
-  for (;;) {
+  // With at most one item per consumer (a wave, or a workgroup sharing a
+  // histogram), consumer c takes item c and no atomics are needed.
+  // Otherwise every item is popped from the queue, whose counter the pass's
+  // prepare kernel has zeroed: popping the first item too staggers the
+  // consumers' starts, which keeps their later pops apart (taking the first
+  // item by index measured 4.8 % slower on 1000 curves x 1e5 frequencies).
+  const int per_group = SH > 1 ? 1 : (int)(blockDim.x / kWave);
+  const bool by_index = a.n_items <= (int)gridDim.x * per_group;
+  for (int round = 0;; ++round) {
     int it = 0;
-    if (SH > 1) {
+    if (by_index) {
+      if (round > 0) break;
+      it = (int)blockIdx.x * per_group + (SH > 1 ? 0 : wave);
+    } else if (SH > 1) {
       // one pop per workgroup; the previous item's barriers order this write
       // after every wave's read of the previous index
       if (threadIdx.x == 0) *group_item = (int)atomicAdd(a.queue, 1u);
@@ -612,16 +624,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
     const RecSource src{ro.rec + p0 + lo};
     process_item<PH, FL, PK, SRC, NV, SH>(a, ro, item, ro.cc[item.curve], src, slice_size<SH>(wave, n_all), hist,
                                           lane, wave, part, totals, var_sums);
-  }
-  // The last wave out resets the queue, so the next launch (or graph replay)
-  // starts from zero without a memset.
-  if (lane == 0) {
-    __threadfence();
-    const uint32_t total = gridDim.x * (blockDim.x / kWave);
-    if (atomicAdd(a.queue + 1, 1u) == total - 1) {
-      atomicExch(a.queue, 0u);
-      atomicExch(a.queue + 1, 0u);
-    }
   }
 }
 

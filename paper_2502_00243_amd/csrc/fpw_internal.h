@@ -42,6 +42,7 @@ struct PrepArgs {
   double* tau64;         // [n_points] FP64 arrays for the plain comparator
   double* w64;
   double* wx64;
+  uint32_t* queue;       // work-queue counter of the pass's fold kernel, zeroed here (or null)
 };
 
 // Work item: curve, frequency range [k0, k1), output slot (natural order).
@@ -80,7 +81,7 @@ struct BatchArgs {
   float* cand_val;        // [(n_slots * n_var) * topk]
   int32_t* cand_idx;      // [(n_slots * n_var) * topk]
   float* edge;            // [(n_slots * n_var) * 4]: S at k0, k0+1, k1-2, k1-1 (-inf if absent)
-  uint32_t* queue;        // [2]: next item, finished waves (self-resetting)
+  uint32_t* queue;        // [1]: items popped after the statically assigned ones; zeroed by the prepare kernel
 };
 
 // Raw inputs of the fused pass, whose fold kernel prepares every curve itself.
@@ -227,6 +228,7 @@ struct BmPrepArgs {
   uint64_t* z64;    // [n_points] when n_terms == 3
   uint32_t* z32;    // [n_points] when n_terms == 2
   BaseConst* bc;    // [n_curves]
+  uint32_t* queue;  // work-queue counter of the pass's baseline kernel, zeroed here (or null)
 };
 
 struct BmArgs {
@@ -241,7 +243,7 @@ struct BmArgs {
   int32_t share;     // waves per histogram (1, 2, 4): the workgroup size in waves
   int32_t source;    // observations: 0 scalar loads, 1 vector loads + DPP broadcast
   float* S;          // [n_curves * n_freq]
-  uint32_t* queue;   // [2], self-resetting as for the batched kernel
+  uint32_t* queue;   // [1], zeroed by the baseline prepare kernel, as for the batched kernel
 };
 
 hipError_t launch_bm_prepare(const BmPrepArgs& a, hipStream_t s);

@@ -174,7 +174,8 @@ def test_default_share_by_bin_count():
 
 
 def test_shared_histogram_repeated_passes_and_graph_replays():
-    """The per-group queue resets itself: back-to-back passes (graph replays and plain launches) agree."""
+    """Each pass restarts the queue (its prepare kernel zeroes the counter): back-to-back passes (graph replays
+    and plain launches) agree."""
     _say("shared histogram repeated passes")
     b = synth.random_batch(91, 30, 50, 500, np.linspace(0.05, 15.0, 2000), 50)
     for use_graph in (True, False):
