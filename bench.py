@@ -118,14 +118,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--workload", default="ztf1000",
-                    choices=["ztf1000", "uneven", "stress", "precision", "sweep", "shared", "baseline", "latency"],
+                    choices=["ztf1000", "uneven", "stress", "precision", "sweep", "shared", "baseline", "latency",
+                             "small"],
                     help="ztf1000: the headline line (default); uneven: 1e5 uneven curves, 2e5 freqs, "
                          "M in {10,20,40}, top-5; stress: 2e4 x 3000-point curves, 1e6 freqs, M=50, top-5; "
                          "precision: phase-arithmetic study on the ztf1000 data; "
                          "sweep: launch shapes x M on the ztf1000 data; "
                          "shared: 1000 curves at 500 common epochs, 1e5 freqs, M=20, matrix-core vs general kernel; "
                          "baseline: the ztf1000 data with a marginalised 3-term baseline (App. A general case); "
-                         "latency: one curve of 200 points, 1e4 freqs, M=10, fused vs three-kernel pass")
+                         "latency: one curve of 200 points, 1e4 freqs, M=10, fused vs three-kernel pass; "
+                         "small: plans of 1-1000 curves x 1e3-1e5 freqs, fused vs three-kernel pass")
     ap.add_argument("--curves", type=int, default=0, help="curve count override for uneven/stress")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -146,6 +148,8 @@ def main():
         return bench_baseline(args)
     if args.workload == "latency":
         return bench_latency(args)
+    if args.workload == "small":
+        return bench_small(args)
 
     import numpy as np
 
@@ -548,6 +552,47 @@ def bench_latency(args):
                                   "S + top-1, outputs preallocated, passes back to back",
                       "latency_us": fused, "latency_three_kernels_us": three, "unit": "us per pass",
                       "passes": max(50, args.steps * 10)}), flush=True)
+
+
+def bench_small(args):
+    """Small and mid-size plans (N ~ U(100, 1000), M = 20, S + top-5): µs per pass back to back with
+    the fused pass forced on and off; one JSON line per plan size."""
+    import numpy as np
+    import torch
+
+    from paper_2502_00243_amd import fpw, synth
+
+    torch.cuda.set_device(0)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    for C in (1, 4, 16, 64, 256, 1000):
+        for nf in (1000, 10000, 100000):
+            if C * nf > 2e7:
+                continue
+            freqs = np.linspace(0.05, 50.0, nf)
+            b = synth.random_batch(5, C, 100, 1000, freqs, 20)
+            us = {}
+            for fuse in (1, -1):
+                p = fpw.Plan.from_batch(b, topk=5, fuse_prepare=fuse)
+                S = torch.empty((C, nf), dtype=torch.float32, device="cuda")
+                i = torch.empty((C, 5), dtype=torch.int32, device="cuda")
+                v = torch.empty((C, 5), dtype=torch.float32, device="cuda")
+                for _ in range(3):
+                    p.eval(S_out=S, idx_out=i, val_out=v)
+                torch.cuda.synchronize()
+                reps = 20 if C * nf < 1e6 else 5
+                t = time.perf_counter()
+                for _ in range(reps):
+                    p.eval(S_out=S, idx_out=i, val_out=v)
+                torch.cuda.synchronize()
+                us[fuse] = (time.perf_counter() - t) / reps * 1e6
+                p.close()
+            default = fpw.Plan.from_batch(b, topk=5)
+            chosen = "fused" if default.info().fuse_prepare else "three-kernel"
+            default.close()
+            items64 = C * ((nf + 63) // 64)
+            print(json.dumps({"workload": "small", "n_curves": C, "n_freq": nf, "n_points": int(b.n_points),
+                              "evals": int(b.n_points) * nf, "items64_per_cu": items64 / n_cu,
+                              "fused_us": us[1], "three_kernel_us": us[-1], "default": chosen}), flush=True)
 
 
 def bench_precision(args):
