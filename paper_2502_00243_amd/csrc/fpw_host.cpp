@@ -710,7 +710,7 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
     }
     double tmin = INFINITY;
     for (int rep = 0; rep < 3; ++rep) {
-      FPW_HIP(hipMemsetAsync(p->queue.p, 0, sizeof(uint32_t), s), "clear queue");  // (no prepare kernel runs here)
+      FPW_HIP(hipMemsetAsync(p->queue.p, 0, p->queue.bytes, s), "clear queue");  // (no prepare kernel runs here)
       FPW_HIP(hipEventRecord(e0, s), "event");
       FPW_HIP(fpw::launch_batched(a, p->shape, p->opt.phase, launch_groups(p, (int)q.size()), p->lds_bytes, s),
               "tune launch");
@@ -833,8 +833,8 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     FPW_HIP(p->wx64.alloc(np * sizeof(double)), "alloc wx64");
     if (o.profile)
       for (hipEvent_t& e : p->ev) FPW_HIP(hipEventCreate(&e), "event create");
-    FPW_HIP(p->queue.alloc(sizeof(uint32_t)), "alloc queue");
-    FPW_HIP(hipMemsetAsync(p->queue.p, 0, sizeof(uint32_t), s), "clear queue");
+    FPW_HIP(p->queue.alloc(fpw::kQueueWords * sizeof(uint32_t)), "alloc queue");
+    FPW_HIP(hipMemsetAsync(p->queue.p, 0, p->queue.bytes, s), "clear queue");
     // prepared records are needed by autotune, fpw_eval_fp64 and fpw_debug_bins
     FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
     // Large M leaves room for few waves per CU; their scalar-load waits then
@@ -853,13 +853,13 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     const int wpg = share > 1 ? share : (o.waves_per_group ? o.waves_per_group : 1);
     fpw::Shape sh{fl, wpg, o.chunk_freqs, src, share};
     // The fused pass for small plans (at most kFusedItemsPerCu items of 64
-    // frequencies per CU) unless a launch shape was asked for.
+    // frequencies per CU) unless a launch shape or its tuning was asked for.
     const int64_t items64 = n_curves * ((n_freq + kWave - 1) / kWave);
     const bool overrides = o.freqs_per_lane || o.waves_per_group || o.chunk_freqs || o.point_source || o.hist_share;
     const bool fused_ok = p->var.n == 1 && o.baseline_terms == 0 &&
                           fpw::fused_lds_bytes(o.n_bins) + 1024 <= (size_t)160 * 1024;
-    p->fused = fused_ok && (o.fuse_prepare == 1 ||
-                            (o.fuse_prepare == 0 && !overrides && items64 <= (int64_t)kFusedItemsPerCu * p->n_cu));
+    p->fused = fused_ok && (o.fuse_prepare == 1 || (o.fuse_prepare == 0 && !overrides && !o.autotune &&
+                                                    items64 <= (int64_t)kFusedItemsPerCu * p->n_cu));
     if (p->fused) {
       // items of 64 frequencies, or longer ones where a forced plan would exceed the per-CU budget
       const int64_t budget = (int64_t)kFusedItemsPerCu * p->n_cu;

@@ -162,7 +162,6 @@ int main(int argc, char** argv) {
       o.n_bins = 40;
       o.topk = 5;
       o.autotune = 1;
-      o.fuse_prepare = -1;  // small enough for the fused pass, which is not tuned
       o.tune_cache = argv[1];
       run(b, o, "autotune plan");
     }

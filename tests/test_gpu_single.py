@@ -194,7 +194,7 @@ def test_default_size_rule():
         assert p.info().fuse_prepare == expect, (len(freqs), n_cu)
         p.close()
     for opts in (dict(hist_share=1), dict(point_source="scalar"), dict(chunk_freqs=128), dict(derived_bins=(5,)),
-                 dict(baseline_terms=1)):
+                 dict(baseline_terms=1), dict(autotune=True)):
         p = fpw.Plan(b.offsets, b.t, b.y, b.dy, at, 10, topk=2, **opts)
         assert p.info().fuse_prepare == 0, opts
         p.close()
