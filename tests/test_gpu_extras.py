@@ -47,12 +47,13 @@ def test_autotuned_plan_matches_default_and_caches(tmp_path):
         p.close()
 
 
-@pytest.mark.parametrize("k", [1, 5, 16])
-def test_standalone_topk_matches_fused(k):
-    """fpw_topk over a stored periodogram equals the fused selection and the peak rule."""
-    _say(f"standalone top-k k={k}")
+@pytest.mark.parametrize("k,fuse", [(1, 0), (5, 0), (16, 0), (5, -1), (16, -1)])
+def test_standalone_topk_matches_fused(k, fuse):
+    """fpw_topk over a stored periodogram equals the fused selection and the peak rule (fused pass
+    of this small plan, and the three-kernel pass)."""
+    _say(f"standalone top-k k={k} fuse_prepare={fuse}")
     b = synth.random_batch(72, 25, 1, 400, FREQS, 12)
-    plan = fpw.Plan.from_batch(b, topk=k)
+    plan = fpw.Plan.from_batch(b, topk=k, fuse_prepare=fuse)
     S, idx, val = plan.eval()
     i2, v2 = plan.topk(S, k)
     torch.cuda.synchronize()
@@ -113,11 +114,12 @@ def test_graph_cache_with_alternating_and_many_output_buffers():
     replays into alternating and into more buffer sets than are kept all match a direct pass."""
     _say("graph cache")
     b = synth.random_batch(75, 30, 20, 300, FREQS, 16)
-    ref_plan = fpw.Plan.from_batch(b, topk=3, use_graph=False)
+    # (three-kernel passes: the fused pass of a plan this small is never captured)
+    ref_plan = fpw.Plan.from_batch(b, topk=3, use_graph=False, fuse_prepare=-1)
     S0, i0, v0 = ref_plan.eval()
     torch.cuda.synchronize()
     S0, i0, v0 = S0.cpu().numpy(), i0.cpu().numpy(), v0.cpu().numpy()
-    plan = fpw.Plan.from_batch(b, topk=3)
+    plan = fpw.Plan.from_batch(b, topk=3, fuse_prepare=-1)
     bufs = [(torch.empty_like(torch.from_numpy(S0)).cuda(), torch.empty((b.n_curves, 3), dtype=torch.int32, device="cuda"),
              torch.empty((b.n_curves, 3), dtype=torch.float32, device="cuda")) for _ in range(6)]
     order = [0, 1, 0, 1, 2, 3, 4, 5, 0, 5, 1]

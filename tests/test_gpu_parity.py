@@ -159,7 +159,7 @@ def test_graph_replays_are_identical():
     _say("graph replays")
     freqs = np.linspace(0.05, 20.0, 999)
     b = synth.random_batch(41, 9, 50, 500, freqs, 20)
-    plan = fpw.Plan.from_batch(b, topk=5)
+    plan = fpw.Plan.from_batch(b, topk=5, fuse_prepare=-1)  # (the fused pass of small plans is not captured)
     outs = []
     for _ in range(3):
         S, idx, val = plan.eval()
@@ -170,7 +170,7 @@ def test_graph_replays_are_identical():
     for o in outs[1:]:
         for a, b_ in zip(outs[0], o):
             np.testing.assert_array_equal(a, b_)
-    plan2 = fpw.Plan.from_batch(b, topk=5, use_graph=False)
+    plan2 = fpw.Plan.from_batch(b, topk=5, use_graph=False, fuse_prepare=-1)
     S2, i2, v2 = plan2.eval()
     torch.cuda.synchronize()
     np.testing.assert_array_equal(S2.cpu().numpy(), outs[0][0])

@@ -120,6 +120,27 @@ def test_fused_equals_three_kernels(case):
     three.close()
 
 
+@pytest.mark.parametrize("nf,M", [(1, 5), (2, 5), (65, 255), (130, 64)])
+def test_fused_edge_cases(nf, M):
+    """One and two frequencies, curves of one point, M at its maximum: fused pass against the oracle
+    and the three-kernel pass."""
+    _say(f"fused edge case nf={nf} M={M}")
+    freqs = np.linspace(0.3, 5.0, nf)
+    b = synth.random_batch(30 + nf, 4, 1, 40, freqs, M)
+    k = min(3, nf)
+    one, three = _both(b.offsets, b.t, b.y, b.dy, freqs, M, topk=k)
+    S, idx, val = _same(one, three, True)
+    parity.assert_topk_matches_rule(S, idx, val, k)
+    opt = parity.oracle_options()
+    for c in range(b.n_curves):
+        t, y, dy = b.curve(c)
+        gb = one.debug_bins(c, 0, nf).cpu().numpy()
+        S_ref, S_abs, _ = parity.reference_for_curve(t, y, dy, freqs, M, opt, gpu_bins=gb)
+        parity.assert_s_close(S[c], S_ref, S_abs, what=f"curve {c}")
+    one.close()
+    three.close()
+
+
 @pytest.mark.parametrize(
     "opts",
     [

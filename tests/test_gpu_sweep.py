@@ -52,9 +52,13 @@ def _compare_general_like(b, plan, opts, exact):
     return S
 
 
-def _shape(rng):
-    """A random launch shape: waves per histogram and point source (defaults included)."""
-    return dict(hist_share=int(rng.choice([0, 1, 2, 4])), point_source=str(rng.choice(["auto", "scalar", "dpp"])))
+def _shape(rng, fused=True):
+    """A random launch shape: waves per histogram and point source (defaults included), and where
+    it allows the fused pass, that pass by default, forced or refused."""
+    shape = dict(hist_share=int(rng.choice([0, 1, 2, 4])), point_source=str(rng.choice(["auto", "scalar", "dpp"])))
+    if fused and shape["hist_share"] in (0, 4) and shape["point_source"] == "auto":
+        shape["fuse_prepare"] = int(rng.choice([0, 1, -1]))
+    return shape
 
 
 @pytest.mark.parametrize("seed", range(16))
@@ -92,7 +96,7 @@ def test_shared_random(seed):
 @pytest.mark.parametrize("seed", range(20, 30))
 def test_baseline_random(seed):
     rng, freqs, opts, phase, M = _draw(seed, max_freq=200)
-    opts.update(_shape(rng))
+    opts.update(_shape(rng, fused=False))
     K = int(rng.integers(1, 4))
     beta = float(10 ** rng.uniform(-2, 2))
     C = int(rng.integers(1, 8))
