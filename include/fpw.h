@@ -269,7 +269,9 @@ fpw_status fpw_debug_bins(fpw_plan_t plan, int32_t phase, int64_t curve, int64_t
  * Kernel durations of the most recent fpw_eval_batch of a plan made with
  * opt.profile = 1, in milliseconds, measured with HIP events recorded on the
  * stream the kernels ran on: ms[0] prepare, ms[1] fold/bin/accumulate/reduce
- * (+ fused peaks), ms[2] peak merge (0 if not run).  Waits for that pass to
+ * (+ fused peaks), ms[2] peak merge (0 if not run).  In the fused pass of a
+ * small plan (fuse_prepare) the fold kernel prepares its curves itself:
+ * ms[0] is then ~0 and ms[1] includes the preparation.  Waits for that pass to
  * finish.  FPW_ESTATE if profiling is off or no pass has run.
  */
 fpw_status fpw_pass_timings(fpw_plan_t plan, float ms[3]);
