@@ -106,9 +106,12 @@ struct Folder<PH_DF32> {
     const float c = __builtin_fmaf(mf, pl, ul);
     const float b0 = floorf(uh);
     const float r = (uh - b0) + c;           // uh - b0 exact
-    int b = (int)b0 + (int)floorf(r);
-    b = b % m;
-    return b < 0 ? b + m : b;
+    // b = floor(M (fr + pl)) with fr in [0, 1) and |pl| < 3/4 (the plan
+    // keeps tau f below 2^22 cycles, so ulp(ph) <= 1/2 and each cross term
+    // is below 1/4): b lies in [-M, 2M - 1] and one compare each way folds
+    // it into [0, M) instead of an integer remainder
+    const int b = (int)b0 + (int)floorf(r);
+    return b >= m ? b - m : (b < 0 ? b + m : b);
   }
 };
 
