@@ -100,7 +100,7 @@ struct Folder<PH_DF32> {
     float pl = __builtin_fmaf(th, fh, -ph);
     pl = __builtin_fmaf(th, fl, pl);
     pl = __builtin_fmaf(tl, fh, pl);
-    const float fr = ph - floorf(ph);        // exact: ph < 2^23
+    const float fr = __builtin_amdgcn_fractf(ph);  // ph - floor(ph), exact: 0 <= ph < 2^23
     const float uh = mf * fr;
     const float ul = __builtin_fmaf(mf, fr, -uh);  // uh + ul = M*fr exactly
     const float c = __builtin_fmaf(mf, pl, ul);
@@ -110,7 +110,7 @@ struct Folder<PH_DF32> {
     // keeps tau f below 2^22 cycles, so ulp(ph) <= 1/2 and each cross term
     // is below 1/4): b lies in [-M, 2M - 1] and one compare each way folds
     // it into [0, M) instead of an integer remainder
-    const int b = (int)b0 + (int)floorf(r);
+    const int b = (int)(b0 + floorf(r));  // a sum of small integers: exact
     return b >= m ? b - m : (b < 0 ? b + m : b);
   }
 };
