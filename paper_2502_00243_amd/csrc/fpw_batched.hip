@@ -59,14 +59,14 @@ struct RO {
 //    Only vector-memory counters are waited on, so LDS atomics stay in
 //    flight; this suits large M, where the histograms leave room for few
 //    waves per CU.
-//  SRC_LANES (one-launch pass): each lane forms the record of one
+//  SRC_LANES (fused pass of small plans): each lane forms the record of one
 //    observation of a block of 64 and the wave broadcasts them one by one
 //    with readlane, so the fold waits on no memory at all.
 enum { SRC_SCALAR = 0, SRC_DPP = 1, SRC_LANES = 2 };
 
-// The observations of a wave: the prepared records (every source), or, in
-// the one-launch pass, records formed on the fly from the raw inputs and the
-// curve's constants (DPP source only: each lane forms the record it loads).
+// The observations of a wave: the prepared records (scalar and DPP
+// sources), or, in the fused pass, records formed on the fly from the raw
+// inputs and the curve's constants (SRC_LANES).
 struct RecSource {
   const Rec* __restrict__ rc;
   __device__ __forceinline__ Rec operator()(int i) const { return rc[i]; }

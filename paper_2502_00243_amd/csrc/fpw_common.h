@@ -454,7 +454,7 @@ __device__ __forceinline__ int queue_pop(uint32_t* queue, int n_items, QueueCurs
 }
 
 // ---------------------------------------------------------------- per-curve preparation
-// Used by the prepare kernel and by the one-launch pass, so that both derive
+// Used by the prepare kernel and by the fused pass, so that both derive
 // identical constants and records from the same inputs.  A workgroup of
 // kPrepThreads threads handles one curve: thread t visits points t,
 // t + kPrepThreads, ... in order; each wave reduces with an xor butterfly
