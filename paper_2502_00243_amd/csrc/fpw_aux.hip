@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kTopkWaves * kWave) void topk_kernel(TopkArgs a) {
 __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepArgs a) {
   __shared__ double red[kPrepRed];
   const int t = threadIdx.x;
-  if (a.queue != nullptr && blockIdx.x == 0 && t < kQueues) a.queue[t * kQueueStride] = 0u;  // the next fold kernel's queue
+  if (a.queue != nullptr && blockIdx.x == 0 && t == 0) *a.queue = 0u;  // the next fold kernel's queue counter
   for (int64_t c = blockIdx.x; c < a.n_curves; c += gridDim.x) {
     const int64_t p0 = a.offsets[c];
     const int n = (int)(a.offsets[c + 1] - p0);
@@ -216,7 +216,7 @@ __device__ __forceinline__ double block_max(double v, double* red) { return -blo
 __global__ __launch_bounds__(kPrepThreads) void bm_prepare_kernel(BmPrepArgs a) {
   __shared__ double red[kPrepThreads];
   const int t = threadIdx.x;
-  if (a.queue != nullptr && blockIdx.x == 0 && t < kQueues) a.queue[t * kQueueStride] = 0u;  // the next fold kernel's queue
+  if (a.queue != nullptr && blockIdx.x == 0 && t == 0) *a.queue = 0u;  // the next fold kernel's queue counter
   for (int64_t c = blockIdx.x; c < a.n_curves; c += gridDim.x) {
     const int64_t p0 = a.offsets[c];
     const int n = (int)(a.offsets[c + 1] - p0);

@@ -258,27 +258,25 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const Rec* __r
   }
   // With at most one item per consumer (a wave, or a workgroup sharing a
   // histogram), consumer c takes item c and no atomics are needed.
-  // Otherwise every item is popped from the queue (queue_pop), the first one
-  // too: that staggers the consumers' starts, which keeps their later pops
-  // apart (taking the first item by index measured 4.8 % slower on 1000
-  // curves x 1e5 frequencies).
+  // Otherwise every item is popped from the queue, whose counter the pass's
+  // prepare kernel has zeroed, the first one too: that staggers the
+  // consumers' starts, which keeps their later pops apart (taking the first
+  // item by index measured 4.8 % slower on 1000 curves x 1e5 frequencies).
   const int per_group = SH > 1 ? 1 : (int)(blockDim.x / kWave);
-  const int consumer = (int)blockIdx.x * per_group + (SH > 1 ? 0 : wave);
   const bool by_index = a.n_items <= (int)gridDim.x * per_group;
-  QueueCursor cursor{consumer % kQueues, 0};
   for (int round = 0;; ++round) {
     int it = 0;
     if (by_index) {
       if (round > 0) break;
-      it = consumer;
+      it = (int)blockIdx.x * per_group + (SH > 1 ? 0 : wave);
     } else if (SH > 1) {
       // one pop per workgroup; the previous item's barriers order this write
       // after every wave's read of the previous index
-      if (threadIdx.x == 0) *group_item = queue_pop(a.queue, a.n_items, cursor);
+      if (threadIdx.x == 0) *group_item = (int)atomicAdd(a.queue, 1u);
       __syncthreads();
       it = __builtin_amdgcn_readfirstlane(*group_item);
     } else {
-      if (lane == 0) it = queue_pop(a.queue, a.n_items, cursor);
+      if (lane == 0) it = (int)atomicAdd(a.queue, 1u);
       it = __builtin_amdgcn_readfirstlane(it);
     }
     if (it >= a.n_items) break;

@@ -595,27 +595,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
   }
   // With at most one item per consumer (a wave, or a workgroup sharing a
   // histogram), consumer c takes item c and no atomics are needed.
-  // Otherwise every item is popped from the queue (queue_pop), the first one
-  // too: that staggers the consumers' starts, which keeps their later pops
-  // apart (taking the first item by index measured 4.8 % slower on 1000
-  // curves x 1e5 frequencies).
+  // Otherwise every item is popped from the queue, whose counter the pass's
+  // prepare kernel has zeroed, the first one too: that staggers the
+  // consumers' starts, which keeps their later pops apart (taking the first
+  // item by index measured 4.8 % slower on 1000 curves x 1e5 frequencies).
   const int per_group = SH > 1 ? 1 : (int)(blockDim.x / kWave);
-  const int consumer = (int)blockIdx.x * per_group + (SH > 1 ? 0 : wave);
   const bool by_index = a.n_items <= (int)gridDim.x * per_group;
-  QueueCursor cursor{consumer % kQueues, 0};
   for (int round = 0;; ++round) {
     int it = 0;
     if (by_index) {
       if (round > 0) break;
-      it = consumer;
+      it = (int)blockIdx.x * per_group + (SH > 1 ? 0 : wave);
     } else if (SH > 1) {
       // one pop per workgroup; the previous item's barriers order this write
       // after every wave's read of the previous index
-      if (threadIdx.x == 0) *group_item = queue_pop(a.queue, a.n_items, cursor);
+      if (threadIdx.x == 0) *group_item = (int)atomicAdd(a.queue, 1u);
       __syncthreads();
       it = __builtin_amdgcn_readfirstlane(*group_item);
     } else {
-      if (lane == 0) it = queue_pop(a.queue, a.n_items, cursor);
+      if (lane == 0) it = (int)atomicAdd(a.queue, 1u);
       it = __builtin_amdgcn_readfirstlane(it);
     }
     if (it >= a.n_items) break;
@@ -705,13 +703,16 @@ void* batched_ptr_src(int fl, int pk, int src, int nv, int share) {
       return src == SRC_DPP ? batched_ptr_sh<PH, SRC_DPP, 1>(pk, share) : batched_ptr_sh<PH, SRC_SCALAR, 1>(pk, share);
     } else {
       if (fl != 1) return nullptr;
-      if (nv > 1) return src == SRC_DPP ? batched_ptr_sh<PH, SRC_DPP, kMaxVariants>(pk, share)
+      if (nv > 4) return src == SRC_DPP ? batched_ptr_sh<PH, SRC_DPP, kMaxVariants>(pk, share)
                                         : batched_ptr_sh<PH, SRC_SCALAR, kMaxVariants>(pk, share);
+      if (nv > 1) return src == SRC_DPP ? batched_ptr_sh<PH, SRC_DPP, 4>(pk, share)
+                                        : batched_ptr_sh<PH, SRC_SCALAR, 4>(pk, share);
       return src == SRC_DPP ? batched_ptr_sh<PH, SRC_DPP, 1>(pk, share) : batched_ptr_sh<PH, SRC_SCALAR, 1>(pk, share);
     }
   }
-  if (nv > 1) return src == SRC_DPP ? batched_ptr_k<PH, 1, SRC_DPP, kMaxVariants>(pk)
+  if (nv > 4) return src == SRC_DPP ? batched_ptr_k<PH, 1, SRC_DPP, kMaxVariants>(pk)
                                     : batched_ptr_k<PH, 1, SRC_SCALAR, kMaxVariants>(pk);
+  if (nv > 1) return src == SRC_DPP ? batched_ptr_k<PH, 1, SRC_DPP, 4>(pk) : batched_ptr_k<PH, 1, SRC_SCALAR, 4>(pk);
   if (src == SRC_DPP) return batched_ptr_k<PH, 1, SRC_DPP, 1>(pk);
   if (PH == PH_DF32 || PH == PH_FP32) return batched_ptr_k<PH, 1, SRC_SCALAR, 1>(pk);
   return fl == 2 ? batched_ptr_k<PH, 2, SRC_SCALAR, 1>(pk) : batched_ptr_k<PH, 1, SRC_SCALAR, 1>(pk);
@@ -719,9 +720,11 @@ void* batched_ptr_src(int fl, int pk, int src, int nv, int share) {
 
 // Instantiated shapes: two frequencies per lane exist for the FP64 folds with
 // scalar point loads and one variant only; several variants take one
-// frequency per lane; shared histograms (2 or 4 waves) take one frequency
-// per lane, and with the FP32-based folds one variant.  Null for a shape that
-// is not built.
+// frequency per lane, with room for 4 variants (for 2-4 of them) or 8 (the
+// smaller instance holds fewer registers: measured 20 % faster with 2 or 3
+// variants); shared histograms (2 or 4 waves) take one frequency per lane,
+// and with the FP32-based folds one variant.  Null for a shape that is not
+// built.
 void* batched_fn(int phase, int fl, int pk, int src, int nv, int share) {
   switch (phase) {
     case PH_FP64: return batched_ptr_src<PH_FP64>(fl, pk, src, nv, share);

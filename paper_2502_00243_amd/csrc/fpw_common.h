@@ -424,35 +424,6 @@ __device__ __forceinline__ void merge_curve_group(const MergeArgs& a, int c, int
   }
 }
 
-// ---------------------------------------------------------------- work queue
-// The queue is spread over kQueues counters, each on its own 64-byte line:
-// counter q hands out items q, q + kQueues, q + 2 kQueues, ... (in the
-// items' order, so every counter serves the longest curves first).  A
-// consumer starts at counter (its index mod kQueues) and moves to the next
-// one when a counter runs dry, so each counter takes 1/kQueues of the
-// atomics.  The pass's prepare kernel zeroes the counters.
-constexpr int kQueues = 16;
-constexpr int kQueueStride = 16;  // uint32 words from one counter to the next
-static_assert(kQueues * kQueueStride == kQueueWords, "queue buffer size");
-
-struct QueueCursor {
-  int q;      // counter in use
-  int tried;  // counters found empty so far
-};
-
-// Next item for the calling lane (one lane per consumer), or n_items when
-// every counter is dry.
-__device__ __forceinline__ int queue_pop(uint32_t* queue, int n_items, QueueCursor& cur) {
-  while (cur.tried < kQueues) {
-    const int j = (int)atomicAdd(queue + cur.q * kQueueStride, 1u);
-    const int it = cur.q + j * kQueues;
-    if (it < n_items) return it;
-    cur.q = cur.q + 1 == kQueues ? 0 : cur.q + 1;
-    ++cur.tried;
-  }
-  return n_items;
-}
-
 // ---------------------------------------------------------------- per-curve preparation
 // Used by the prepare kernel and by the fused pass, so that both derive
 // identical constants and records from the same inputs.  A workgroup of

@@ -710,7 +710,7 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
     }
     double tmin = INFINITY;
     for (int rep = 0; rep < 3; ++rep) {
-      FPW_HIP(hipMemsetAsync(p->queue.p, 0, p->queue.bytes, s), "clear queue");  // (no prepare kernel runs here)
+      FPW_HIP(hipMemsetAsync(p->queue.p, 0, sizeof(uint32_t), s), "clear queue");  // (no prepare kernel runs here)
       FPW_HIP(hipEventRecord(e0, s), "event");
       FPW_HIP(fpw::launch_batched(a, p->shape, p->opt.phase, launch_groups(p, (int)q.size()), p->lds_bytes, s),
               "tune launch");
@@ -833,8 +833,8 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     FPW_HIP(p->wx64.alloc(np * sizeof(double)), "alloc wx64");
     if (o.profile)
       for (hipEvent_t& e : p->ev) FPW_HIP(hipEventCreate(&e), "event create");
-    FPW_HIP(p->queue.alloc(fpw::kQueueWords * sizeof(uint32_t)), "alloc queue");
-    FPW_HIP(hipMemsetAsync(p->queue.p, 0, p->queue.bytes, s), "clear queue");
+    FPW_HIP(p->queue.alloc(sizeof(uint32_t)), "alloc queue");
+    FPW_HIP(hipMemsetAsync(p->queue.p, 0, sizeof(uint32_t), s), "clear queue");
     // prepared records are needed by autotune, fpw_eval_fp64 and fpw_debug_bins
     FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
     // Large M leaves room for few waves per CU; their scalar-load waits then

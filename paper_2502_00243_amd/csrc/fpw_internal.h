@@ -42,11 +42,8 @@ struct PrepArgs {
   double* tau64;         // [n_points] FP64 arrays for the plain comparator
   double* w64;
   double* wx64;
-  uint32_t* queue;       // work-queue counters of the pass's fold kernel, zeroed here (or null)
+  uint32_t* queue;       // work-queue counter of the pass's fold kernel, zeroed here (or null)
 };
-
-// Words of the work-queue buffer: 16 counters, 64 bytes apart.
-constexpr int kQueueWords = 16 * 16;
 
 // Work item: curve, frequency range [k0, k1), output slot (natural order).
 struct alignas(16) Item {
@@ -84,7 +81,7 @@ struct BatchArgs {
   float* cand_val;        // [(n_slots * n_var) * topk]
   int32_t* cand_idx;      // [(n_slots * n_var) * topk]
   float* edge;            // [(n_slots * n_var) * 4]: S at k0, k0+1, k1-2, k1-1 (-inf if absent)
-  uint32_t* queue;        // [kQueueWords]: the work-queue counters (see queue_pop); zeroed by the prepare kernel
+  uint32_t* queue;        // [1]: the work-queue counter; zeroed by the prepare kernel
 };
 
 // Raw inputs of the fused pass, whose fold kernel prepares every curve itself.
@@ -231,7 +228,7 @@ struct BmPrepArgs {
   uint64_t* z64;    // [n_points] when n_terms == 3
   uint32_t* z32;    // [n_points] when n_terms == 2
   BaseConst* bc;    // [n_curves]
-  uint32_t* queue;  // work-queue counters of the pass's baseline kernel, zeroed here (or null)
+  uint32_t* queue;  // work-queue counter of the pass's baseline kernel, zeroed here (or null)
 };
 
 struct BmArgs {
@@ -246,7 +243,7 @@ struct BmArgs {
   int32_t share;     // waves per histogram (1, 2, 4): the workgroup size in waves
   int32_t source;    // observations: 0 scalar loads, 1 vector loads + DPP broadcast
   float* S;          // [n_curves * n_freq]
-  uint32_t* queue;   // [kQueueWords], zeroed by the baseline prepare kernel, as for the batched kernel
+  uint32_t* queue;   // [1], zeroed by the baseline prepare kernel, as for the batched kernel
 };
 
 hipError_t launch_bm_prepare(const BmPrepArgs& a, hipStream_t s);
