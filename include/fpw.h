@@ -143,7 +143,7 @@ typedef struct {
                              summed in one fixed order for every launch shape, so results are
                              bit-identical to private histograms.  With baseline_terms > 0 it
                              sets the baseline kernel's sharing instead; 0 = by histogram size
-                             per wave (1 below 8704 bytes, else 4). */
+                             per wave (1 below 8704 bytes, 2 below 12288, else 4). */
   int32_t fuse_prepare;   /* fused pass for small plans: the fold kernel prepares its curve
                              itself (each work item's workgroup of four waves reduces the
                              curve's constants and forms its records in registers), then

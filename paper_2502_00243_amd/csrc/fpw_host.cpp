@@ -886,10 +886,12 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
       FPW_HIP(p->bm_const.alloc((size_t)n_curves * sizeof(fpw::BaseConst)), "alloc baseline constants");
       FPW_HIP(p->bm_S.alloc((size_t)n_curves * (size_t)n_freq * sizeof(float)), "alloc baseline periodogram");
       int per_cu = 0;
-      // histograms of ~8.5 KiB or more per wave are shared by four waves (measured at M = 20, K = 1..3:
-      // four waves beat two and private ones every time); scalar point loads unless asked otherwise
+      // histograms of ~8.5 KiB or more per wave are shared by two waves, from 12 KiB by four (measured
+      // at M = 20: K = 1, 10.5 KiB, two waves 2 % faster than four; K = 2, 3, 16 and 21 KiB, four
+      // waves faster than two by 2 and 6 %; private ones slowest every time); scalar point loads
+      // unless asked otherwise
       const size_t hb = fpw::bm_lds_bytes(o.n_bins, o.baseline_terms, 1);
-      p->bm_share = o.hist_share ? o.hist_share : (hb >= 8704 ? 4 : 1);
+      p->bm_share = o.hist_share ? o.hist_share : (hb >= 12288 ? 4 : (hb >= 8704 ? 2 : 1));
       p->bm_source = o.point_source == 2 ? 1 : 0;
       FPW_HIP(fpw::bm_groups_per_cu(o.phase, o.n_bins, o.baseline_terms, p->bm_share, p->bm_source, &per_cu),
               "baseline kernel occupancy");

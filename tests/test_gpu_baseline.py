@@ -203,9 +203,9 @@ def test_baseline_kernel_shared_histograms(M, K, share, n_max, src):
 def test_baseline_default_share_by_histogram_size():
     _say("baseline default share")
     b = synth.random_batch(67, 4, 20, 80, FREQS, 10)
-    # histogram bytes per wave: (8, 12, 16 for K = 1, 2, 3) x (M + 1) x 64; four waves from 8704
-    for M, K, sh in [(15, 1, 1), (16, 1, 4), (20, 1, 4), (20, 2, 4), (20, 3, 4), (10, 2, 1), (11, 2, 4),
-                     (32, 1, 4), (7, 3, 1), (8, 3, 4), (64, 2, 4)]:
+    # histogram bytes per wave: (8, 12, 16 for K = 1, 2, 3) x (M + 1) x 64; two waves from 8704, four from 12288
+    for M, K, sh in [(15, 1, 1), (16, 1, 2), (20, 1, 2), (22, 1, 2), (23, 1, 4), (20, 2, 4), (20, 3, 4), (10, 2, 1),
+                     (11, 2, 2), (15, 2, 4), (32, 1, 4), (7, 3, 1), (8, 3, 2), (11, 3, 4), (64, 2, 4)]:
         p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, M, baseline_terms=K)
         assert (p.info().hist_share, p.info().point_source) == (sh, 1), (M, K)
         p.close()
