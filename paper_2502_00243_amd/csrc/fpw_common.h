@@ -296,6 +296,40 @@ __device__ __forceinline__ int int_from_lane_below(int v) {
 // entry r (best first), the other lanes hold (-inf, INT_MAX).  Two VGPRs per
 // list, however large k is; insertions run as a wave-uniform loop over the
 // candidate lanes, which are few once the list has filled.
+template <int CTRL>
+__device__ __forceinline__ void best_from_dpp(float& v, int& i) {
+  // the pair CTRL brings in, or (-inf, INT_MAX) where it brings none
+  const float ov = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v), CTRL, 0xf, 0xf, false));
+  const int oi = __builtin_amdgcn_update_dpp(INT_MAX, i, CTRL, 0xf, 0xf, false);
+  if (better(ov, oi, v, i)) {
+    v = ov;
+    i = oi;
+  }
+}
+
+// The best (value, index) among the lanes where `pred` holds, in every lane
+// ((-inf, INT_MAX) if none): row_shr by 1, 2, 4 and 8 leaves each row's best
+// in its last lane, and the four row results are compared in order.
+__device__ __forceinline__ void wave_best(float s, int idx, bool pred, float& bv, int& bi) {
+  float v = pred ? s : -INFINITY;
+  int i = pred ? idx : INT_MAX;
+  best_from_dpp<0x111>(v, i);
+  best_from_dpp<0x112>(v, i);
+  best_from_dpp<0x114>(v, i);
+  best_from_dpp<0x118>(v, i);
+  bv = lane_value(v, 15);
+  bi = __builtin_amdgcn_readlane(i, 15);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const float ov = lane_value(v, 16 * r + 15);
+    const int oi = __builtin_amdgcn_readlane(i, 16 * r + 15);
+    if (better(ov, oi, bv, bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+}
+
 struct WaveTop {
   float v;
   int i;
@@ -303,28 +337,46 @@ struct WaveTop {
     v = -INFINITY;
     i = INT_MAX;
   }
-  // Offers (s, idx) of every lane where `pred` holds; k = list length.
+  // Puts (cs, ci) into the list if it beats the k-th entry.
+  __device__ __forceinline__ bool insert(float cs, int ci, int k, int lane) {
+    if (!better(cs, ci, lane_value(v, k - 1), __builtin_amdgcn_readlane(i, k - 1))) return false;
+    // entries better than the candidate form a prefix of length p
+    const int p = __popcll(__ballot(lane < k && better(v, i, cs, ci)));
+    const float vb = from_lane_below(v);
+    const int ib = int_from_lane_below(i);
+    if (lane == p) {
+      v = cs;
+      i = ci;
+    } else if (lane > p && lane < k) {
+      v = vb;
+      i = ib;
+    }
+    return true;
+  }
+  // Offers (s, idx) of every lane where `pred` holds; k = list length.  The
+  // indices of the lanes are distinct.  The list becomes the k best of the
+  // list and the offers, whatever order they are taken in: lane by lane
+  // when they are few, best first (at most k can enter) when there are
+  // more than 2k of them.
   __device__ __forceinline__ void offer(float s, int idx, bool pred, int k, int lane) {
     const float tv = lane_value(v, k - 1);
     const int ti = __builtin_amdgcn_readlane(i, k - 1);
-    uint64_t m = __ballot(pred && better(s, idx, tv, ti));
+    bool cand = pred && better(s, idx, tv, ti);
+    uint64_t m = __ballot(cand);
+    if (__popcll(m) > 2 * k) {
+      for (int r = 0; r < k; ++r) {
+        float cs;
+        int ci;
+        wave_best(s, idx, cand, cs, ci);
+        if (!insert(cs, ci, k, lane)) break;
+        cand = cand && idx != ci;
+      }
+      return;
+    }
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      const float cs = lane_value(s, l);
-      const int ci = __builtin_amdgcn_readlane(idx, l);
-      if (!better(cs, ci, lane_value(v, k - 1), __builtin_amdgcn_readlane(i, k - 1))) continue;
-      // entries better than the candidate form a prefix of length p
-      const int p = __popcll(__ballot(lane < k && better(v, i, cs, ci)));
-      const float vb = from_lane_below(v);
-      const int ib = int_from_lane_below(i);
-      if (lane == p) {
-        v = cs;
-        i = ci;
-      } else if (lane > p && lane < k) {
-        v = vb;
-        i = ib;
-      }
+      insert(lane_value(s, l), __builtin_amdgcn_readlane(idx, l), k, lane);
     }
   }
   // Writes the list: (value, index) for r < k, index -1 where the value is -inf.
