@@ -393,17 +393,9 @@ struct WaveTop {
 template <int K>
 __device__ __forceinline__ void wave_select(TopList<K>& l, int k, float* out_v, int32_t* out_i, int lane) {
   for (int r = 0; r < k; ++r) {
-    float bv = l.v[0];
-    int bi = l.i[0];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const float ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
-      if (better(ov, oi, bv, bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
+    float bv;
+    int bi;
+    wave_best(l.v[0], l.i[0], true, bv, bi);  // the best head of the 64 lists
     const bool none = bv == -INFINITY;
     if (lane == 0) {
       out_v[r] = bv;
