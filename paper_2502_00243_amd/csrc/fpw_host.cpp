@@ -153,6 +153,10 @@ const int kDppMinBinsShared = 128;
 // is 1.2-2x faster up to 6 items per CU, 0.86x at 10; beyond ~100 the
 // persistent kernel is up to 2.3x faster).
 const int kFusedItemsPerCu = 8;
+// Smallest work item of the persistent kernel, in evaluations per wave (a
+// pop of the queue's counter costs ~20 ns serialised, so ~3300 consumers
+// popping together need items of ~70 us to keep the counter off the path).
+const double kMinItemEvalsPerWave = 6.0e4;
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -316,11 +320,18 @@ int round_up(int64_t v, int64_t m) { return (int)(((v + m - 1) / m) * m); }
 
 // Default chunk: about twelve work items per persistent wave (enough for the
 // queue to even out the tail), at least one sweep of the wave, at most 16384
-// frequencies.
+// frequencies.  On mid-size plans that rule makes items so small that the
+// queue's atomics (one per item, serialised on one counter) bind instead of
+// the folding, so an item also gets at least ~6e4 evaluations per wave,
+// unless that would leave consumers without an item.
 int default_chunk(const fpw_plan_s* p, const fpw::Shape& s, int total_waves) {
   const int sweep = s.freqs_per_lane * kWave;
   const double per_curve_items = std::max(1.0, 12.0 * total_waves / (double)p->n_curves);
   int64_t chunk = (int64_t)std::ceil((double)p->n_freq / per_curve_items);
+  const double points_per_wave = std::max(1.0, (double)p->n_points / p->n_curves / std::max(1, s.share));
+  const int64_t pop_floor = (int64_t)std::ceil(kMinItemEvalsPerWave / points_per_wave);
+  const int64_t fill_cap = (int64_t)std::ceil((double)p->n_freq * p->n_curves / total_waves);
+  chunk = std::max<int64_t>(chunk, std::min(pop_floor, fill_cap));
   chunk = std::max<int64_t>(chunk, sweep);
   chunk = std::min<int64_t>(chunk, 16384);
   return round_up(chunk, sweep);
