@@ -3,7 +3,8 @@
 // bin counts, shared histograms, both point sources, shared timestamps), and
 // through the other entry points (stored-S peaks, FP64 comparator, bins hook,
 // phase entropy, profiled passes, autotune with its cache file, the captured
-// pass cache cycling through more output buffers than it keeps), for use
+// pass cache cycling through more output buffers than it keeps) and the
+// default chunk rule, for use
 // with the HIP stand-ins in hip_stub.cpp under the sanitizers.  argv[1]: a
 // scratch path for the autotune cache.  Prints "failures: 0" when every call
 // returned what it should.
@@ -93,6 +94,40 @@ void run(const Batch& b, const fpw_options& o, const char* what) {
   auto H = buf<float>((size_t)C * 2), E = buf<float>((size_t)C * 2), V = buf<float>((size_t)C * 2);
   auto fi = buf<int32_t>((size_t)C * 2);
   expect(fpw_phase_entropy(p, fi.data(), 2, H.data(), E.data(), V.data(), nullptr), FPW_OK, "entropy");
+  fpw_plan_destroy(p);
+}
+
+// The default chunk of a three-kernel plan of C curves of N observations and
+// F frequencies, M = 20 (two waves per histogram), under the stand-ins' 256
+// CUs x 4 groups: 1024 consumers.
+void expect_chunk(int C, int N, int F, int want, const char* what) {
+  Batch b;
+  b.off.assign(C + 1, 0);
+  for (int c = 0; c < C; ++c) {
+    for (int i = 0; i < N; ++i) {
+      b.t.push_back(i * 1.9 + c);
+      b.y.push_back(std::cos(i * 0.2));
+      b.dy.push_back(0.03);
+    }
+    b.off[c + 1] = (int64_t)b.t.size();
+  }
+  for (int i = 0; i < F; ++i) b.f.push_back(0.05 + i * 0.005);
+  fpw_options o;
+  fpw_options_default(&o);
+  o.n_bins = 20;
+  o.topk = 5;
+  o.fuse_prepare = -1;
+  fpw_plan_t p = nullptr;
+  fpw_status st = fpw_plan(&p, C, b.off.data(), b.t.data(), b.y.data(), b.dy.data(), F, b.f.data(), &o, nullptr);
+  expect(st, FPW_OK, what);
+  if (st != FPW_OK) return;
+  ++plans;
+  fpw_plan_info info;
+  expect(fpw_get_plan_info(p, &info), FPW_OK, "info");
+  if (info.hist_share != 2 || info.chunk_freqs != want) {
+    std::printf("FAIL %s: share %d chunk %d (want 2, %d)\n", what, info.hist_share, info.chunk_freqs, want);
+    ++failures;
+  }
   fpw_plan_destroy(p);
 }
 
@@ -207,6 +242,13 @@ int main(int argc, char** argv) {
       passes(p, o, C, F, 1);
       fpw_plan_destroy(p);
     }
+  // default chunks: ~12 items per consumer, raised to >= 6e4 evaluations per wave and item (550 / 2
+  // observations per wave: 219 frequencies) unless that leaves consumers idle, in sweeps of 64
+  expect_chunk(64, 550, 10000, 256, "chunk floor");        // 12 per consumer: 53; floor 219
+  expect_chunk(16, 550, 10000, 192, "chunk fill cap");     // floor 219 > 16 * 1e4 / 1024 = 157
+  expect_chunk(4000, 4, 4096, 16000, "chunk tiny curves");  // floor 3e4 > fill cap 4096 * 4000 / 1024 = 16000
+  expect_chunk(1200, 550, 40000, 3968, "chunk 12 per consumer");  // 4e4 / (12 * 1024 / 1200) = 3907 > 219
+  expect_chunk(3000, 550, 1000, 256, "chunk four items per curve");  // 1000 / (12 * 1024 / 3000) = 245 > 219
   std::printf("plans: %d, failures: %d\n", plans, failures);
   return failures != 0;
 }
