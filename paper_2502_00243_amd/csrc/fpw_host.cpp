@@ -153,10 +153,12 @@ const int kDppMinBinsShared = 128;
 // is 1.2-2x faster up to 6 items per CU, 0.86x at 10; beyond ~100 the
 // persistent kernel is up to 2.3x faster).
 const int kFusedItemsPerCu = 8;
-// Smallest work item of the persistent kernel, in evaluations per wave (a
-// pop of the queue's counter costs ~20 ns serialised, so ~3300 consumers
-// popping together need items of ~70 us to keep the counter off the path).
-const double kMinItemEvalsPerWave = 6.0e4;
+// Smallest work item of the persistent kernel, in evaluations per wave: a
+// pop of the queue's one counter costs ~20 ns serialised, so with ~3300
+// waves popping an item has to keep its wave busy ~70 us (~1.2e5
+// evaluations) for the counter to stay off the critical path (measured on
+// mid-size plans: 3e4, 6e4, 1.2e5, 2.4e5 -> 1.2e5 best or within noise).
+const double kMinItemEvalsPerWave = 1.2e5;
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -322,7 +324,7 @@ int round_up(int64_t v, int64_t m) { return (int)(((v + m - 1) / m) * m); }
 // queue to even out the tail), at least one sweep of the wave, at most 16384
 // frequencies.  On mid-size plans that rule makes items so small that the
 // queue's atomics (one per item, serialised on one counter) bind instead of
-// the folding, so an item also gets at least ~6e4 evaluations per wave,
+// the folding, so an item also gets at least kMinItemEvalsPerWave,
 // unless that would leave consumers without an item.
 int default_chunk(const fpw_plan_s* p, const fpw::Shape& s, int total_waves) {
   const int sweep = s.freqs_per_lane * kWave;

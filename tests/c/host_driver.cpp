@@ -242,13 +242,13 @@ int main(int argc, char** argv) {
       passes(p, o, C, F, 1);
       fpw_plan_destroy(p);
     }
-  // default chunks: ~12 items per consumer, raised to >= 6e4 evaluations per wave and item (550 / 2
-  // observations per wave: 219 frequencies) unless that leaves consumers idle, in sweeps of 64
-  expect_chunk(64, 550, 10000, 256, "chunk floor");        // 12 per consumer: 53; floor 219
-  expect_chunk(16, 550, 10000, 192, "chunk fill cap");     // floor 219 > 16 * 1e4 / 1024 = 157
-  expect_chunk(4000, 4, 4096, 16000, "chunk tiny curves");  // floor 3e4 > fill cap 4096 * 4000 / 1024 = 16000
-  expect_chunk(1200, 550, 40000, 3968, "chunk 12 per consumer");  // 4e4 / (12 * 1024 / 1200) = 3907 > 219
-  expect_chunk(3000, 550, 1000, 256, "chunk four items per curve");  // 1000 / (12 * 1024 / 3000) = 245 > 219
+  // default chunks: ~12 items per consumer, raised to >= 1.2e5 evaluations per wave and item (550 / 2
+  // observations per wave: 437 frequencies) unless that leaves consumers idle, in sweeps of 64
+  expect_chunk(64, 550, 10000, 448, "chunk floor");        // 12 per consumer: 53; floor 437
+  expect_chunk(16, 550, 10000, 192, "chunk fill cap");     // floor 437 > 16 * 1e4 / 1024 = 157
+  expect_chunk(4000, 4, 4096, 16000, "chunk tiny curves");  // floor 6e4 > fill cap 4096 * 4000 / 1024 = 16000
+  expect_chunk(1200, 550, 40000, 3968, "chunk 12 per consumer");  // 4e4 / (12 * 1024 / 1200) = 3907 > 437
+  expect_chunk(3000, 550, 1000, 448, "chunk floor over 12 per consumer");  // 1000 / (12 * 1024 / 3000) = 245 < 437
   std::printf("plans: %d, failures: %d\n", plans, failures);
   return failures != 0;
 }
