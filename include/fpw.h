@@ -104,7 +104,12 @@ typedef struct {
                           for the fused pass of small plans, see fuse_prepare) */
   int32_t freqs_per_lane; /* launch shape override, 0 = default: frequencies per lane (1, 2) */
   int32_t waves_per_group;/* launch shape override, 0 = default: waves per workgroup (1, 2, 4) */
-  int32_t chunk_freqs;    /* launch shape override, 0 = default: frequencies per work item */
+  int32_t chunk_freqs;    /* launch shape override, 0 = default: frequencies per work item
+                             (rounded up to a whole sweep of the wave).  The default
+                             aims at ~12 items per persistent wave or group, raised
+                             so an item carries >= 1.2e5 observation x frequency
+                             evaluations per wave while every wave still gets an
+                             item, within [one sweep, 16384]. */
   const char* tune_cache; /* path of a text cache of autotune results; NULL = none */
   int32_t point_source;   /* launch shape override: how a wave fetches observations.
                              0 = default (by M and the kind of plan; scalar loads for
