@@ -138,8 +138,10 @@ typedef struct {
   double baseline_scale;  /* prior standard deviation of each baseline coefficient, in flux
                              units (> 0, finite; default 1) */
   int32_t hist_share;     /* launch shape override: waves that share one LDS histogram.
-                             0 = default: by M (1 below 16 bins, 2 up to 31, 4 from 32)
-                             when freqs_per_lane and waves_per_group are 0 (and, with derived
+                             0 = default: by M (1 below 16 bins, 2 up to 31, 4 from 32;
+                             4 also from 16 for one variant when n_points x n_freq is
+                             below 1.5e8 per CU) when freqs_per_lane and waves_per_group
+                             are 0 (and, with derived
                              bin counts, the phase mode is FP64), else 1.  1 = one private
                              histogram per wave.  2 or 4 = a workgroup of that many waves folds
                              disjoint slices of each curve's observations into one histogram

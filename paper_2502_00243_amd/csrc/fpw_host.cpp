@@ -143,6 +143,12 @@ const int kWave = 64;
 // M = 20 +10 % with two waves, M = 50 +73 % with four, M = 10 even).
 const int kShare2MinBins = 16;
 const int kShare4MinBins = 32;
+// Below this many evaluations (n_points x n_freq) per CU, one variant with
+// 16 <= M < 32 takes four waves per histogram instead of two: fewer, longer
+// items even out the tail of a short pass (measured with N ~ U(100, 1000),
+// M = 20: 7-15 % faster up to 1.6e10 evaluations on 256 CUs, even at 5e10,
+// two waves 1 % faster on the 5.5e10 of 1000 ZTF-like curves).
+const double kShare4SmallPlanEvalsPerCu = 1.5e8;
 // Smallest M for which the default point source is the DPP broadcast, with
 // private histograms (or several variants) and with shared histograms and
 // one variant (their extra waves hide the scalar loads' waits up to M ~ 100).
@@ -857,6 +863,7 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
       const bool can = (o.phase <= FPW_PHASE_FP64_LISTING || p->var.n == 1) && o.freqs_per_lane != 2 &&
                        o.waves_per_group == 0;
       share = !can ? 1 : (o.n_bins >= kShare4MinBins ? 4 : (o.n_bins >= kShare2MinBins ? 2 : 1));
+      if (share == 2 && p->var.n == 1 && (double)np * (double)n_freq < kShare4SmallPlanEvalsPerCu * p->n_cu) share = 4;
     }
     // with several variants the scalar source loses to the DPP broadcast even with shared
     // histograms (measured: M = 40 -> 20, 10 on 1000 ZTF-like curves, 20.1 vs 17.8 ms)

@@ -117,6 +117,7 @@ void expect_chunk(int C, int N, int F, int want, const char* what) {
   o.n_bins = 20;
   o.topk = 5;
   o.fuse_prepare = -1;
+  o.hist_share = 2;  // plans this small would take four waves per histogram by default
   fpw_plan_t p = nullptr;
   fpw_status st = fpw_plan(&p, C, b.off.data(), b.t.data(), b.y.data(), b.dy.data(), F, b.f.data(), &o, nullptr);
   expect(st, FPW_OK, what);

@@ -151,7 +151,8 @@ def test_default_share_by_bin_count():
     b = synth.random_batch(90, 6, 20, 100, np.linspace(0.1, 5.0, 200), 10)
     one = dict(fuse_prepare=-1)  # a batch this small would otherwise run the fused pass
     # M: (waves per histogram, point source 1 scalar / 2 DPP)
-    expect = {10: (1, 1), 15: (1, 1), 16: (2, 1), 31: (2, 1), 32: (4, 1), 127: (4, 1), 128: (4, 2), 255: (4, 2)}
+    # (a plan this small takes four waves from M = 16: below 1.5e8 evaluations per CU)
+    expect = {10: (1, 1), 15: (1, 1), 16: (4, 1), 31: (4, 1), 32: (4, 1), 127: (4, 1), 128: (4, 2), 255: (4, 2)}
     for M, (sh, src) in expect.items():
         p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, M, **one)
         assert (p.info().hist_share, p.info().point_source) == (sh, src), M
@@ -164,6 +165,9 @@ def test_default_share_by_bin_count():
         p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, **opts, **one)
         assert p.info().hist_share == 1, opts
         p.close()
+    p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 20, derived_bins=(10,), **one)
+    assert p.info().hist_share == 2  # the small-plan rule takes one variant only
+    p.close()
     p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, derived_bins=(20,), **one)
     assert (p.info().hist_share, p.info().point_source) == (4, 2)  # derived bin counts share too, DPP source
     p.close()
@@ -199,3 +203,19 @@ def test_stress_shape_with_shared_histograms_sampled():
     assert p.info().hist_share == 4 and p.info().fuse_prepare == 0
     _check_against_oracle(p, b.offsets, b.t, b.y, b.dy, freqs, b.n_bins, {}, False)
     p.close()
+
+
+def test_default_share_by_plan_size():
+    """16 <= M < 32: four waves per histogram below 1.5e8 evaluations per CU, two from there."""
+    _say("default share by plan size")
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    nf = 100000
+    freqs = np.linspace(0.05, 50.0, nf)
+    for evals_per_cu, want in ((1.4e8, 4), (1.6e8, 2)):
+        C = int(np.ceil(evals_per_cu * n_cu / (nf * 100)))
+        b = synth.random_batch(7, C, 100, 100, freqs[:10], 20)
+        assert b.n_points == 100 * C
+        p = fpw.Plan(b.offsets, b.t, b.y, b.dy, freqs, 20, topk=5)
+        info = p.info()
+        assert (info.fuse_prepare, info.hist_share) == (0, want), (C, n_cu)
+        p.close()
