@@ -64,9 +64,14 @@ enum {
 
 /* Arithmetic that forms the phase and the bin (the only step whose rounding decides bins). */
 enum {
-  FPW_PHASE_FP64 = 0,         /* FP64 fused form: phase = frac(fma(tau, f, -1/(2M))), bin =
-                                 round(M * phase) with bin M folded onto 0.  Bins equal the
-                                 exact ones except within ~1e-8 bin widths of an edge. */
+  FPW_PHASE_FP64 = 0,         /* FP64 fused form: phase = frac(fma(tau, f, -(1/(2M) - delta))),
+                                 bin = round(M * phase) with bin M folded onto 0; delta (set per
+                                 plan from its largest tau * f) makes a point exactly on an edge
+                                 take the upper bin, as floor does.  Bins equal
+                                 floor(M frac(tau f)) on and off the edges except for points less
+                                 than 1e-7 bin widths below an edge.  Where the plan's fold range
+                                 would widen that band, the plan folds in the listing order
+                                 instead and fpw_get_plan_info reports FPW_PHASE_FP64_LISTING. */
   FPW_PHASE_FP64_LISTING = 1, /* FP64 in the listing's order: p = fl(tau f), phi = p - floor(p),
                                  bin = floor(fl(phi M)).  Bit-exact with a plain FP64 loop. */
   FPW_PHASE_DF32 = 2,         /* compensated FP32: tau and f split hi+lo, error-free product,
@@ -241,6 +246,9 @@ fpw_status fpw_plan_shared(fpw_plan_t* out, int64_t n_curves, int64_t n_points, 
  *             Both NULL, or both non-NULL with opt.topk > 0 (else FPW_EINVAL).
  * Peak rule: index k is a peak iff S[k] > S[k-1] and S[k] >= S[k+1], with
  * S[-1] = S[n_freq] = -inf.
+ * A plan owns its prepared records, queue counter and peak scratch, and every
+ * pass rewrites them: passes of one plan must not overlap (enqueue them on one
+ * stream, or synchronise between the streams used).
  */
 fpw_status fpw_eval_batch(fpw_plan_t plan, float* S_dev, int32_t* topk_idx, float* topk_val,
                           void* stream);

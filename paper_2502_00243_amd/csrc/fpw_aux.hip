@@ -323,7 +323,7 @@ __global__ __launch_bounds__(64) void fp64_kernel(Fp64Args a) {
   }
   const int k = blockIdx.x * kWave + lane;
   Folder<PH_LISTING> fo;
-  fo.init(a.freqs[k < a.n_freq ? k : a.n_freq - 1], M);
+  fo.init(a.freqs[k < a.n_freq ? k : a.n_freq - 1], M, 0.0);
   const double* tau = a.tau + a.p0;
   const double* w = a.w + a.p0;
   const double* wx = a.wx + a.p0;
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void bins_kernel(BinsArgs a) {
     const int64_t fi = g / a.n;
     const int i = (int)(g - fi * a.n);
     Folder<PH> fo;
-    fo.init(a.freqs[a.f_begin + fi], a.n_bins);
+    fo.init(a.freqs[a.f_begin + fi], a.n_bins, a.fold_nh);
     int b = fo.bin(encode_tau(a.tau64[a.p0 + i], PH));
     if (PH == PH_FP64 && b == a.n_bins) b = 0;
     a.out[g] = b;
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kEntropyWaves * 64) void entropy_kernel(EntropyArgs
   const int64_t p0 = a.offsets[c];
   const int n = (int)(a.offsets[c + 1] - p0);
   Folder<PH> fo;
-  fo.init(a.freqs[idx], M);
+  fo.init(a.freqs[idx], M, a.fold_nh);
   for (int i = lane; i < n; i += kWave) {
     int b = fo.bin(encode_tau(a.tau64[p0 + i], PH));
     if (b >= M) b = 0;  // the fused fold files phases just below 1 as M

@@ -256,6 +256,9 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const Rec* __r
     if (NZ == NZ_PAIR) hz[m * SW] = 0;
     if (NZ == NZ_ONE) hz32[m * kWave] = 0;
   }
+  // the waves of a shared histogram clear their own slots but fold into
+  // all of them: clearing completes before any wave's first atomic
+  if (SH > 1) __syncthreads();
   // With at most one item per consumer (a wave, or a workgroup sharing a
   // histogram), consumer c takes item c and no atomics are needed.
   // Otherwise every item is popped from the queue, whose counter the pass's
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(kWave * SH) void bm_kernel(BmArgs a, const Rec* __r
       const int k = kt + lane;
       if (n > 0) {
         Folder<PH> fo;
-        fo.init(freqs[k < k1 ? k : k1 - 1], M);
+        fo.init(freqs[k < k1 ? k : k1 - 1], M, a.fold_nh);
         bm_accumulate<PH, NZ, SRC>(rc, zc, n, fo, hw, hz, hz32, lane);
       }
       if constexpr (SH == 1) {

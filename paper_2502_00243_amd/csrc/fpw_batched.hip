@@ -498,7 +498,7 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
 #pragma unroll
     for (int j = 0; j < FL; ++j) {
       const int k = kt + j * kWave + lane;
-      fo[j].init(f_first != nullptr && FL == 1 && kt == k0 ? *f_first : ro.freqs[k < k1 ? k : k1 - 1], M);
+      fo[j].init(f_first != nullptr && FL == 1 && kt == k0 ? *f_first : ro.freqs[k < k1 ? k : k1 - 1], M, a.fold_nh);
       h[j] = hist + (j * slots) * kWave + lane;
     }
     // fold, bin and accumulate every observation of the curve (of this wave's slice)
@@ -590,6 +590,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
   int* group_item = reinterpret_cast<int*>(var_sums + (NV > 1 ? NV * kWave : 0));
   if (SH > 1) {
     for (int s = wave; s < slots; s += SH) hist[s * kWave + lane] = 0;
+    // every wave clears its own slots but folds into all of them: the
+    // clearing must be complete before any wave's first atomic (the queue
+    // path has a barrier after its pop; taking items by index has none)
+    __syncthreads();
   } else {
     for (int s = 0; s < FL * slots; ++s) hist[s * kWave + lane] = 0;
   }

@@ -41,18 +41,24 @@ __device__ __forceinline__ uint64_t encode_tau(double tau, int phase) {
 template <int PH>
 struct Folder;
 
-// FP64, fused: the fold is shifted by half a bin, phase' = frac(tau f - 1/(2M)),
-// and round(M phase') (one fma into the magic constant) equals
-// floor(M frac(tau f)) except within rounding of an edge; phase' just below 1
-// rounds to M, which is bin 0.  tau f - 1/(2M) is formed with one rounding
-// (fma), so the bin is exact up to ~M * ulp(tau f) bin widths.
+// FP64, fused: the fold is shifted by just under half a bin,
+// phase' = frac(fma(tau, f, nh)) with nh = -(1/(2M) - delta), and
+// round(M phase') (one fma into the magic constant) is the bin.  Off the
+// edges that equals floor(M frac(tau f)).  delta (set per plan, at least
+// twice the largest rounding error of the first fma over the plan's fold
+// range) makes a point exactly on an edge land above the rounding midpoint,
+// so it takes the upper bin, as floor does, instead of following
+// round-half-to-even; the price is that points within ~1.4 M delta bin
+// widths below an edge also move up (the plan keeps that under 1e-7 bin
+// widths, else it folds in the listing order).  phase' just below 1 rounds
+// to M, which is bin 0.
 template <>
 struct Folder<PH_FP64> {
   double f, nh, md;
-  __device__ __forceinline__ void init(double freq, int M) {
+  __device__ __forceinline__ void init(double freq, int M, double shift) {
     f = freq;
     md = (double)M;
-    nh = -0.5 / (double)M;
+    nh = shift;
   }
   __device__ __forceinline__ int bin(uint64_t tb) const {
     const double tau = __longlong_as_double((long long)tb);
@@ -66,7 +72,7 @@ struct Folder<PH_FP64> {
 template <>
 struct Folder<PH_LISTING> {
   double f, md;
-  __device__ __forceinline__ void init(double freq, int M) {
+  __device__ __forceinline__ void init(double freq, int M, double) {
     f = freq;
     md = (double)M;
   }
@@ -87,7 +93,7 @@ template <>
 struct Folder<PH_DF32> {
   float fh, fl, mf;
   int m;
-  __device__ __forceinline__ void init(double freq, int M) {
+  __device__ __forceinline__ void init(double freq, int M, double) {
     fh = (float)freq;
     fl = (float)(freq - (double)fh);
     mf = (float)M;
@@ -120,7 +126,7 @@ template <>
 struct Folder<PH_FP32> {
   float f, mf;
   int m;
-  __device__ __forceinline__ void init(double freq, int M) {
+  __device__ __forceinline__ void init(double freq, int M, double) {
     f = (float)freq;
     mf = (float)M;
     m = M;

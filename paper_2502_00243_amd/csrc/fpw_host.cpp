@@ -79,6 +79,10 @@ struct fpw_plan_s {
   DevBuf items, queue, cand_val, cand_idx, edge, slot_k0, curve_slot;
   fpw::Shape shape{1, 1, 4096, 0, 1};
   fpw::Variants var{};        // periodogram variants (multi-M reuse); var.n >= 1
+  // shift of the fused FP64 fold (see fused_fold_shift); fused_fold is false
+  // when the plan's fold range made it fold in the listing order instead
+  double fold_nh = 0.0;
+  bool fused_fold = true;
   std::vector<int32_t> var_bins;  // bin count of each variant
   int grid_groups = 0;
   size_t lds_bytes = 0;
@@ -167,6 +171,24 @@ const int kFusedItemsPerCu = 8;
 const double kMinItemEvalsPerWave = 1.2e5;
 
 bool finite(double v) { return std::isfinite(v); }
+
+// The fused FP64 fold forms phase' = frac(fma(tau, f, nh)) and takes
+// round(M phase') as the bin.  nh = -(1/(2M) - delta): with delta = 2^(e-52),
+// where 2^e exceeds every |tau f| of the plan, delta is at least four times
+// the rounding error of that fma, so a point exactly on a bin edge lies above
+// the rounding midpoint and takes the upper bin, as floor() does (App. A
+// phase-bin equation), rather than following round-half-to-even.  The cost:
+// points less than ~1.375 M delta bin widths below an edge move up too.  The
+// fused fold is used while that band stays under 1e-7 bin widths (a tenth of
+// the near-edge tolerance); *ok is false beyond, and the plan then folds in
+// the listing order.
+double fused_fold_shift(int M, double max_cycles, bool* ok) {
+  int ex = 0;
+  (void)std::frexp(std::max(max_cycles, 1.0), &ex);  // 2^ex > max_cycles
+  const double delta = std::ldexp(1.0, ex - 52);
+  *ok = 1.375 * (double)M * delta <= 1e-7;
+  return -(0.5 / (double)M - delta);
+}
 
 fpw_status check_options(const fpw_options& o) {
   if (o.n_bins < 1) return fail(FPW_EINVAL, "n_bins must be >= 1 (got %d)", o.n_bins);
@@ -268,10 +290,10 @@ fpw_status validate(int64_t n_curves, const int64_t* offsets, const double* t, c
     *max_f = std::max(*max_f, freqs[k]);
   }
   if (o.topk > n_freq) return fail(FPW_EINVAL, "topk %d exceeds n_freq %lld", o.topk, (long long)n_freq);
-  // Range of the fold for each phase encoding.
+  // Range of the fold for each phase encoding (the fused FP64 fold hands over
+  // to the listing order itself where its range would blur the edges).
   const double cycles = *max_tau * *max_f;
-  if (o.phase == FPW_PHASE_FP64 && cycles * o.n_bins >= 4.0e15)
-    return fail(FPW_EUNSUPPORTED, "tau*f*M = %g too large for the fused FP64 fold", cycles * o.n_bins);
+  if (!finite(cycles)) return fail(FPW_EUNSUPPORTED, "tau*f overflows (max tau %g, max f %g)", *max_tau, *max_f);
   if ((o.phase == FPW_PHASE_DF32 || o.phase == FPW_PHASE_FP32) && cycles >= 4194304.0)
     return fail(FPW_EUNSUPPORTED, "tau*f = %g cycles too large for the FP32 phase encodings (< 2^22)", cycles);
   return FPW_OK;
@@ -412,6 +434,7 @@ fpw::BatchArgs batch_args(const fpw_plan_s* p, float* S, const DevBuf& items, in
   a.topk = p->opt.topk;
   a.n_curves = (int32_t)p->n_curves;
   a.var = p->var;
+  a.fold_nh = p->fold_nh;
   a.S = S;
   a.cand_val = p->cand_val.as<float>();
   a.cand_idx = p->cand_idx.as<int32_t>();
@@ -487,6 +510,7 @@ fpw::SharedArgs shared_args(const fpw_plan_s* p, float* S) {
   a.fw = p->sh_fw;
   a.rounds = p->sh_rounds;
   a.priv_bytes = p->sh_priv;
+  a.fold_nh = p->fold_nh;
   a.S = S;
   return a;
 }
@@ -556,6 +580,7 @@ fpw_status enqueue_bm_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hi
   a.n_terms = p->opt.baseline_terms;
   a.share = p->bm_share;
   a.source = p->bm_source;
+  a.fold_nh = p->fold_nh;
   a.S = Sd;
   a.queue = p->queue.as<uint32_t>();
   FPW_HIP(fpw::launch_bm(a, p->opt.phase, p->bm_grid, s), "baseline kernel");
@@ -801,11 +826,16 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
   double max_tau = 0, max_f = 0;
   st = validate(n_curves, offsets, t, y, dy, n_freq, freqs, o, &max_tau, &max_f);
   if (st != FPW_OK) return st;
+  bool fused_fold = true;
+  const double fold_nh = fused_fold_shift(o.n_bins, max_tau * max_f, &fused_fold);
+  if (o.phase == FPW_PHASE_FP64 && !fused_fold) o.phase = FPW_PHASE_FP64_LISTING;
   // ---- all checks passed: from here on HIP calls are made
   try {
     fpw_plan_s* p = new fpw_plan_s();
     std::unique_ptr<fpw_plan_s> guard(p);
     p->opt = o;
+    p->fold_nh = fold_nh;
+    p->fused_fold = fused_fold;
     p->n_curves = n_curves;
     p->n_freq = n_freq;
     p->n_points = offsets[n_curves];
@@ -1117,7 +1147,9 @@ fpw_status fpw_debug_bins(fpw_plan_t p, int32_t phase, int64_t curve, int64_t f_
   a.f_begin = (int32_t)f_begin;
   a.f_end = (int32_t)f_end;
   a.n_bins = p->opt.n_bins;
-  a.phase = phase;
+  // FP64 on a plan whose fold range made it fold in the listing order
+  a.phase = phase == FPW_PHASE_FP64 && !p->fused_fold ? FPW_PHASE_FP64_LISTING : phase;
+  a.fold_nh = p->fold_nh;
   a.out = bins_dev;
   FPW_HIP(fpw::launch_bins(a, (hipStream_t)stream), "bins kernel");
   return FPW_OK;
@@ -1156,6 +1188,7 @@ fpw_status fpw_phase_entropy(fpw_plan_t p, const int32_t* freq_idx_dev, int32_t 
   a.n_freq = (int32_t)p->n_freq;
   a.n_bins = p->opt.n_bins;
   a.phase = p->opt.phase;
+  a.fold_nh = p->fold_nh;
   a.H = H_dev;
   a.E = E_dev;
   a.V = V_dev;

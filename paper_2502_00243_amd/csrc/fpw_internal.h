@@ -77,6 +77,7 @@ struct BatchArgs {
   int32_t topk;           // 0 = no peak selection
   int32_t n_curves;
   Variants var;
+  double fold_nh;         // shift of the fused FP64 fold: -(1/(2M) - delta), set per plan
   float* S;               // [n_var * n_curves * n_freq] or null
   float* cand_val;        // [(n_slots * n_var) * topk]
   int32_t* cand_idx;      // [(n_slots * n_var) * topk]
@@ -142,6 +143,7 @@ struct BinsArgs {
   int32_t f_begin, f_end;
   int32_t n_bins;
   int32_t phase;
+  double fold_nh;   // as in BatchArgs
   int32_t* out;
 };
 
@@ -151,6 +153,7 @@ struct EntropyArgs {
   const double* freqs;
   const int32_t* freq_idx;  // [n_curves * k]
   int32_t n_curves, k, n_freq, n_bins, phase;
+  double fold_nh;   // as in BatchArgs
   float* H;
   float* E;
   float* V;
@@ -195,6 +198,7 @@ struct SharedArgs {
   int32_t fw;              // frequencies per wave per round (fw * n_bins <= 32 * B tiles)
   int32_t rounds;          // rounds per workgroup (8 waves x fw frequencies each)
   int32_t priv_bytes;      // LDS bytes private to each wave
+  double fold_nh;          // as in BatchArgs
   float* S;                // [n_curves * n_freq]
 };
 
@@ -242,6 +246,7 @@ struct BmArgs {
   int32_t n_terms;   // baseline terms K (1..3); K = 1 needs no second sum
   int32_t share;     // waves per histogram (1, 2, 4): the workgroup size in waves
   int32_t source;    // observations: 0 scalar loads, 1 vector loads + DPP broadcast
+  double fold_nh;    // as in BatchArgs
   float* S;          // [n_curves * n_freq]
   uint32_t* queue;   // [1], zeroed by the baseline prepare kernel, as for the batched kernel
 };

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
       }
       for (int fl = 0; fl < a.fw; ++fl) {
         Folder<PH> fo;
-        fo.init(a.freqs[min(f0 + fl, a.n_freq - 1)], M);
+        fo.init(a.freqs[min(f0 + fl, a.n_freq - 1)], M, a.fold_nh);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           const int d = lane + kWave * j;

@@ -25,7 +25,8 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _check_plan_against_oracle(b, plan, opts, curves=None, exact_bins=False, freq_idx=None):
+def _check_plan_against_oracle(b, plan, opts, curves=None, exact_bins=False, freq_idx=None,
+                               max_guard=parity.MAX_GUARD_FRACTION):
     """Compares S (and bins) of the selected curves with the oracle; returns the guard-hit fraction."""
     S_gpu, _, _ = plan.eval(topk=False)
     torch.cuda.synchronize()
@@ -39,7 +40,8 @@ def _check_plan_against_oracle(b, plan, opts, curves=None, exact_bins=False, fre
         gb = plan.debug_bins(c, 0, len(b.freqs)).cpu().numpy()[fi]
         S_ref, S_abs, _ = parity.reference_for_curve(t, y, dy, b.freqs[fi], plan.n_bins, opt, gpu_bins=gb,
                                                      exact_bins=exact_bins)
-        guard.append(parity.assert_s_close(S_gpu[c, fi], S_ref, S_abs, what=f"curve {c}"))
+        guard.append(parity.assert_s_close(S_gpu[c, fi], S_ref, S_abs, what=f"curve {c}", max_guard=max_guard))
+    _say(f"  guard fraction {np.mean(guard):.2e} (max per curve {np.max(guard):.2e})")
     return float(np.mean(guard)), S_gpu
 
 
@@ -89,7 +91,11 @@ def test_ragged_batch(case):
                                point_source=src)
     if src != "auto":
         assert plan.info().point_source == (1 if src == "scalar" else 2)
-    _check_plan_against_oracle(b, plan, {}, exact_bins=phase == "fp64_listing")
+    # with M <= 3 the bin sums of weighted-centred data nearly cancel at a few
+    # frequencies per curve (for M = 2, Y_1 = -Y_0 exactly), where only the
+    # guard can apply
+    _check_plan_against_oracle(b, plan, {}, exact_bins=phase == "fp64_listing",
+                               max_guard=1e-2 if M <= 3 else parity.MAX_GUARD_FRACTION)
     S, idx, val = plan.eval()
     torch.cuda.synchronize()
     S = S.cpu().numpy()
