@@ -186,6 +186,149 @@ def test_exact_rational_statistic_small():
         assert abs(S - float(Sx)) <= 1e-13 * max(1.0, abs(float(Sx))), (trial, S, float(Sx))
 
 
+def _rational_statistic(t, y, dy, f, M, ia2, center, t_ref):
+    """S of Eq. 1 in exact rationals, straight from the definitions, with the centre and t_ref given as rationals."""
+    w = [1 / (Fraction(d) * Fraction(d)) for d in dy]
+    x = [Fraction(yi) - center for yi in y]
+    Wb = [Fraction(0)] * M
+    Yb = [Fraction(0)] * M
+    for i in range(len(t)):
+        p = (Fraction(t[i]) - t_ref) * Fraction(f)
+        assert p >= 0
+        b = math.floor((p - math.floor(p)) * M)
+        Wb[b] += w[i]
+        Yb[b] += w[i] * x[i]
+    return sum((Yb[m] ** 2 / (Wb[m] + Fraction(ia2)) for m in range(M) if Wb[m] + Fraction(ia2) > 0), Fraction(0))
+
+
+@pytest.mark.parametrize("center", ["weighted", "mean", "none"])
+@pytest.mark.parametrize("tref", ["zero", "first", "given"])
+def test_exact_rational_statistic_every_centre_and_reference_time(center, tref):
+    """Every centring (Eq. 1: x is mean-subtracted; Sec. 3.5: the average value) and every reference
+    time (App. A: t_ref, often the first observation) against exact rational arithmetic.
+
+    The centre is the weighted mean sum(w y)/sum(w), the plain average sum(y)/n, or 0; t_ref is 0, the
+    earliest time of the curve (inputs are given unsorted, so the first array element is not it), or
+    the given value.  Times sit on a dyadic grid, so tau = t - t_ref is exact in FP64.
+    """
+    rng = np.random.default_rng({"weighted": 1, "mean": 2, "none": 3}[center] * 10 + {"zero": 1, "first": 2, "given": 3}[tref])
+    for trial in range(25):
+        n = int(rng.integers(1, 10))
+        M = int(rng.integers(1, 7))
+        t = rng.integers(0, 4096, n) / 16.0 + 300.0
+        rng.shuffle(t)
+        y = rng.integers(-64, 64, n) / 32.0 + 0.75
+        dy = rng.integers(1, 8, n) / 8.0
+        f = int(rng.integers(1, 512)) / 128.0
+        ia2 = int(rng.integers(0, 4)) / 4.0
+        t0 = int(rng.integers(-800, 300)) / 4.0 if tref == "given" else 0.0
+        opt = OracleOptions(inv_alpha2=ia2, center=center, tref=tref, t_ref=t0)
+        S = oracle.curve_periodogram(t, y, dy, [f], M, opt)[0]
+        w = [1 / (Fraction(d) * Fraction(d)) for d in dy]
+        if center == "weighted":
+            mu = sum(wi * Fraction(yi) for wi, yi in zip(w, y)) / sum(w)
+        elif center == "mean":
+            mu = sum(Fraction(yi) for yi in y) / n
+        else:
+            mu = Fraction(0)
+        tr = {"zero": Fraction(0), "first": min(Fraction(ti) for ti in t), "given": Fraction(t0)}[tref]
+        Sx = _rational_statistic(t, y, dy, f, M, ia2, mu, tr)
+        assert abs(S - float(Sx)) <= 1e-13 * max(1.0, abs(float(Sx))), (trial, S, float(Sx))
+
+
+def test_plain_mean_centring_closed_form_with_one_bin():
+    """With one bin S = (sum w (y - ybar))^2 / sum w for the plain average ybar (Sec. 3.5): nonzero in
+    general, whereas the weighted mean makes it vanish (the degree of freedom it removes)."""
+    rng = np.random.default_rng(31)
+    for _ in range(20):
+        n = int(rng.integers(2, 40))
+        t = rng.uniform(0, 100, n)
+        y = rng.normal(0.0, 1.0, n) + 5.0
+        dy = rng.uniform(0.1, 2.0, n)
+        w = 1.0 / dy**2
+        Sm = oracle.curve_periodogram(t, y, dy, [0.37], 1, OracleOptions(center="mean"))[0]
+        ybar = math.fsum(y) / n
+        closed = math.fsum(w * (y - ybar)) ** 2 / math.fsum(w)
+        assert abs(Sm - closed) <= 1e-9 * max(closed, 1e-12), (Sm, closed)
+        assert closed > 1e-6
+        Sw = oracle.curve_periodogram(t, y, dy, [0.37], 1, OracleOptions(center="weighted"))[0]
+        assert Sw <= 1e-12 * closed
+
+
+def test_plain_and_weighted_means_agree_for_equal_errors():
+    """Equal errors make the weighted mean the plain average (Eq. 1 definitions)."""
+    rng = np.random.default_rng(32)
+    t = rng.uniform(0, 500, 80)
+    y = rng.normal(0, 1, 80)
+    dy = np.full(80, 0.25)
+    freqs = np.linspace(0.1, 3.0, 50)
+    Sm = oracle.curve_periodogram(t, y, dy, freqs, 7, OracleOptions(center="mean"))
+    Sw = oracle.curve_periodogram(t, y, dy, freqs, 7, OracleOptions(center="weighted"))
+    np.testing.assert_allclose(Sm, Sw, rtol=1e-12)
+    # and with unequal errors they differ
+    dy2 = rng.uniform(0.05, 1.0, 80)
+    Sm2 = oracle.curve_periodogram(t, y, dy2, freqs, 7, OracleOptions(center="mean"))
+    Sw2 = oracle.curve_periodogram(t, y, dy2, freqs, 7, OracleOptions(center="weighted"))
+    assert np.max(np.abs(Sm2 - Sw2) / Sw2) > 1e-3
+
+
+def test_centred_statistics_ignore_a_constant_offset():
+    """Any mean removal makes S blind to a constant added to every flux; without centring the change is
+    c^2 W + 2 c sum(w x), the same at every frequency (App. B: the constant model)."""
+    rng = np.random.default_rng(33)
+    t = np.sort(rng.uniform(0, 300, 60))
+    y = rng.integers(-64, 64, 60) / 32.0
+    dy = rng.integers(1, 8, 60) / 8.0
+    freqs = np.linspace(0.05, 2.0, 40)
+    c = 12.5
+    for center in ("weighted", "mean"):
+        a = oracle.curve_periodogram(t, y, dy, freqs, 6, OracleOptions(center=center))
+        b = oracle.curve_periodogram(t, y + c, dy, freqs, 6, OracleOptions(center=center))
+        np.testing.assert_allclose(a, b, rtol=1e-10, atol=1e-10)
+    a = oracle.curve_periodogram(t, y, dy, freqs, 6, OracleOptions(center="none"))
+    b = oracle.curve_periodogram(t, y + c, dy, freqs, 6, OracleOptions(center="none"))
+    w = 1.0 / dy**2
+    np.testing.assert_allclose(b - a, c * c * w.sum() + 2 * c * np.sum(w * y), rtol=1e-10)
+
+
+def test_first_observation_reference_is_shift_and_order_invariant():
+    """t_ref = the first (earliest) observation (App. A): S does not change when every time moves by any
+    dyadic offset or when the observations are listed in another order, and equals t_ref = 0 on t - min(t);
+    the earliest point sits at phase 0, i.e. in bin 0, at every frequency."""
+    rng = np.random.default_rng(34)
+    t = rng.integers(0, 2**14, 70) / 8.0 + 1000.0
+    y = rng.normal(0, 1, 70)
+    dy = rng.uniform(0.05, 0.5, 70)
+    freqs = np.linspace(0.013, 7.0, 300)
+    first = OracleOptions(tref="first")
+    S = oracle.curve_periodogram(t, y, dy, freqs, 9, first)
+    for shift in (-1000.0, 37.125, 2.0**20):
+        np.testing.assert_array_equal(oracle.curve_periodogram(t + shift, y, dy, freqs, 9, first), S)
+    p = rng.permutation(70)
+    np.testing.assert_allclose(oracle.curve_periodogram(t[p], y[p], dy[p], freqs, 9, first), S, rtol=1e-12)
+    np.testing.assert_array_equal(oracle.curve_periodogram(t - t.min(), y, dy, freqs, 9), S)
+    bins = oracle.curve_bins(t, freqs, 9, first)
+    assert np.all(bins[:, np.argmin(t)] == 0)
+
+
+def test_given_reference_time_equals_shifted_times_and_whole_periods():
+    """A given t_ref folds t - t_ref (App. A): the same S as t_ref = 0 on the shifted times, and a t_ref
+    moved by a whole number of periods of a dyadic trial frequency leaves every bin unchanged."""
+    rng = np.random.default_rng(35)
+    t = rng.integers(0, 2**14, 50) / 8.0
+    y = rng.normal(0, 1, 50)
+    dy = rng.uniform(0.05, 0.5, 50)
+    freqs = np.arange(1, 65) / 16.0
+    t0 = -123.625
+    S = oracle.curve_periodogram(t, y, dy, freqs, 8, OracleOptions(tref="given", t_ref=t0))
+    np.testing.assert_array_equal(S, oracle.curve_periodogram(t - t0, y, dy, freqs, 8))
+    # 16 days is a whole number of periods of every f = k/16
+    S2 = oracle.curve_periodogram(t, y, dy, freqs, 8, OracleOptions(tref="given", t_ref=t0 - 16.0 * 5))
+    np.testing.assert_array_equal(S, S2)
+    with pytest.raises(ValueError):
+        oracle.validate([0, 50], t, y, dy, freqs, 8, OracleOptions(tref="given", t_ref=float(t.min()) + 0.5))
+
+
 def _exact_bins(t, f, M):
     return np.array([exact_bin(float(ti), f, M)[0] for ti in t])
 
