@@ -93,6 +93,7 @@ enum {
 #define FPW_MAX_CURVE_POINTS (1 << 24)
 #define FPW_MAX_BASELINE_TERMS 3  /* Chebyshev terms of the marginalised baseline */
 #define FPW_MAX_BASELINE_BINS 64  /* largest M with a marginalised baseline (LDS) */
+#define FPW_MAX_WIDE_BINS 156     /* largest M for curves whose bin sums take the wide format (LDS) */
 
 typedef struct {
   int32_t n_bins;      /* M >= 1; > FPW_MAX_BINS -> FPW_EUNSUPPORTED.  Default 10. */
@@ -169,7 +170,43 @@ typedef struct {
                              override and no autotune is set.  -1 = never.  1 = always (FPW_EUNSUPPORTED with
                              derived bin counts, baseline terms, or a shape override other
                              than chunk_freqs and four waves per group). */
+  int32_t sum_format;     /* FPW_SUMS_*: fixed-point format of the per-bin sums, see below.
+                             Default AUTO. */
 } fpw_options;
+
+/*
+ * Per-bin sums.  The bin sums W_m and Y_m are accumulated exactly as
+ * integers after each point's w and w x are rounded once to a per-curve
+ * fixed-point unit; the unit is Sum(w) / 2^B of weight and Sum|w x| / 2^(B-1)
+ * of residual, so a light point's value carries a relative rounding error of
+ * up to unit / (2 w).  fpw_plan measures, per curve,
+ *   e_w   = W unit / (2 min w): the largest relative error of any bin's W,
+ *   e_dup = W unit / (2 w) for the smallest weight w that at least
+ *           max(2, N / (4 M)) points share (up to a quarter unit): such points
+ *           round alike, so a bin filled with them keeps that error without
+ *           averaging,
+ *   e_y   = sqrt(Sum(1/w) (Sum(w) + M/alpha^2)) / 2^B: the rounding of the
+ *           residual sums against the cancellation guard sum|w x|^2 / W,
+ * and gives each curve one of two formats:
+ *   narrow: one 64-bit word per bin, B = 32 (weight) / 31 (residual), when
+ *           e_w <= 1e-4, e_dup <= 5e-6 and e_y <= 4e-6.  The W bound is a
+ *           worst case reached only by a bin holding nothing but the lightest
+ *           points with same-signed rounding; where weights differ the
+ *           rounding errors are independent and S stays within ~1e-6.
+ *   wide:   two 64-bit words per bin, B = 64 / 63 (scales 2^-11 below the
+ *           limits), when e_w <= 1e-6 and e_y <= 1e-6 there: every bin within
+ *           1e-6 of its exact sum.  About twice the LDS atomics per
+ *           evaluation; FP64 phase modes, one periodogram variant.
+ * A curve that fits neither (or a plan that needs the narrow format for every
+ * curve: derived bin counts, baseline terms, the FPW_PHASE_DF32/FP32 modes,
+ * the fused pass) makes fpw_plan return FPW_EUNSUPPORTED; so does a dy whose
+ * 1/dy^2 is not a finite normal double.  fpw_get_plan_info reports how many
+ * curves took the wide format.
+ */
+enum {
+  FPW_SUMS_AUTO = 0,  /* per curve, as above */
+  FPW_SUMS_WIDE = 1   /* every curve in the wide format */
+};
 
 /* Kernel of a shared-timestamp plan (fpw_plan_shared). */
 enum {
@@ -330,6 +367,7 @@ typedef struct {
   int32_t hist_share;     /* waves per LDS histogram (1, 2, 4) of the general batched kernel
                              or of the baseline kernel; 0 for the matrix-core kernel */
   int32_t fuse_prepare;   /* 1 if the plan runs the fused pass (see fpw_options) */
+  int32_t n_wide_curves;  /* curves whose bin sums take the wide format (see FPW_SUMS_*) */
 } fpw_plan_info;
 
 fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);

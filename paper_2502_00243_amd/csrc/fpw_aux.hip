@@ -74,24 +74,33 @@ __global__ __launch_bounds__(kTopkWaves * kWave) void topk_kernel(TopkArgs a) {
 // One workgroup per curve: inverse variances, centring, time offsets and the
 // fixed-point scales (curve_prep), then the packed records and the FP64
 // arrays of the plain comparator.
+// Curves in the wide format (fmt) also get their 32-byte records and FP64
+// constants.
 __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepArgs a) {
   __shared__ double red[kPrepRed];
   const int t = threadIdx.x;
-  if (a.queue != nullptr && blockIdx.x == 0 && t == 0) *a.queue = 0u;  // the next fold kernel's queue counter
+  // the queue counters of the pass's fold kernels
+  if (a.queue != nullptr && blockIdx.x == 0 && t < a.n_queues) a.queue[t] = 0u;
   for (int64_t c = blockIdx.x; c < a.n_curves; c += gridDim.x) {
     const int64_t p0 = a.offsets[c];
     const int n = (int)(a.offsets[c + 1] - p0);
     const PrepConst k = curve_prep(a.t + p0, a.y + p0, a.dy + p0, n, a.center, a.tref_mode, a.t_ref, red);
+    const bool wide = a.fmt != nullptr && a.fmt[c] == FMT_WIDE;  // workgroup-uniform
+    const int64_t q0 = wide ? a.offw[c] : 0;
     for (int i = t; i < n; i += kPrepThreads) {
       const int64_t p = p0 + i;
       a.rec[p] = make_rec(a.t[p], a.y[p], a.dy[p], k, a.phase);
+      if (wide) a.recw[q0 + i] = make_wrec(a.t[p], a.y[p], a.dy[p], k, a.phase);
       const double d = a.dy[p];
       const double w = 1.0 / (d * d);
       a.tau64[p] = a.t[p] - k.tref;
       a.w64[p] = w;
       a.wx64[p] = w * (a.y[p] - k.mu);
     }
-    if (t == 0) a.cc[c] = make_curve_const(k, a.inv_alpha2, a.stat_scale);
+    if (t == 0) {
+      a.cc[c] = make_curve_const(k, a.inv_alpha2, a.stat_scale);
+      if (wide) a.wc[c] = make_wide_const(k, a.inv_alpha2, a.stat_scale);
+    }
   }
 }
 

@@ -631,6 +631,146 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
   }
 }
 
+// ---------------------------------------------------------------- wide-format kernel
+// Curves whose weights span too wide a range for the packed 32-bit fields
+// (fpw_plan decides per curve) keep their per-bin sums in two 64-bit words:
+// the weight and the weighted residual each take their own ds_add_u64 (the
+// second at a 512-byte offset from the first), and the epilogue decodes them
+// to FP64.  Otherwise the kernel works as the batched one: one lane per
+// frequency, wave-uniform scalar loads of the records (four 32-byte records
+// per batch), items taken from the second queue counter, SH waves sharing a
+// histogram, the bin terms summed in the same fixed part order, fused peaks.
+
+template <int PH>
+__device__ __forceinline__ void accumulate_wide(const WRec* __restrict__ rc, int n, const Folder<PH>& fo, uint64_t* h) {
+  constexpr int kWideBatch = 4;
+  int i = 0;
+  for (; i + kWideBatch <= n; i += kWideBatch) {
+    WRec r[kWideBatch];
+#pragma unroll
+    for (int q = 0; q < kWideBatch; ++q) r[q] = rc[i + q];
+#pragma unroll
+    for (int q = 0; q < kWideBatch; ++q) {
+      uint64_t* sl = h + fo.bin(r[q].tau_bits) * kWideSlotWords;
+      lds_add(sl, uniform_to_vgpr(r[q].wq));
+      lds_add(sl + kWave, uniform_to_vgpr(r[q].yq));
+    }
+  }
+  for (; i < n; ++i) {
+    const WRec r = rc[i];
+    uint64_t* sl = h + fo.bin(r.tau_bits) * kWideSlotWords;
+    lds_add(sl, uniform_to_vgpr(r.wq));
+    lds_add(sl + kWave, uniform_to_vgpr(r.yq));
+  }
+}
+
+// One work item of a wide-format curve; `rc` holds this wave's n records.
+template <int PH, int PK, int SH>
+__device__ __forceinline__ void process_item_wide(const BatchArgs& a, const double* __restrict__ freqs, const Item& item,
+                                                  const WideConst wc, const WRec* __restrict__ rc, int n,
+                                                  uint64_t* hist, int lane, int wave, double* part) {
+  static_assert(kSumParts % SH == 0, "each wave owns whole parts of the sum");
+  const int M = a.n_bins;
+  const int c = item.curve, k0 = item.k0, k1 = item.k1;
+  const bool lead = SH == 1 || wave == 0;
+  uint64_t* h = hist + lane;
+  PeakState peaks;
+  if (PK) peaks.init();
+  bool pend = false;
+  for (int kb = k0; kb < k1; kb += kWave) {
+    const int k = kb + lane;
+    Folder<PH> fo;
+    fo.init(freqs[k < k1 ? k : k1 - 1], M, a.fold_nh);
+    if (SH == 1 || n > 0) accumulate_wide<PH>(rc, n, fo, h);
+    double sum = 0.0;
+    if constexpr (SH > 1) {
+      constexpr int NP = kSumParts / SH;
+      __syncthreads();  // every slice is in the histogram
+      double ps[NP];
+      wide_parts<PH, NP>(h, M, wave * NP, wc, ps);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) part[(wave * NP + q) * kWave + lane] = ps[q];
+      __syncthreads();  // part sums visible, histogram clear for the next sub-tile
+      if (!lead) continue;
+#pragma unroll
+      for (int p = 0; p < kSumParts; ++p) sum += part[p * kWave + lane];
+    } else {
+      double ps[kSumParts];
+      wide_parts<PH, kSumParts>(h, M, 0, wc, ps);
+#pragma unroll
+      for (int p = 0; p < kSumParts; ++p) sum += ps[p];
+    }
+    const float sv = (float)(sum * wc.scale);
+    if (a.S != nullptr && k < k1) a.S[(int64_t)c * a.n_freq + k] = sv;
+    if (PK) peaks.step(sv, kb, k0, k1, a.n_freq, pend, a.topk, a.edge + (int64_t)item.slot * 4, lane);
+    pend = kb + kWave - 1 < k1 - 1;
+  }
+  if (PK && lead) {
+    const int64_t o = (int64_t)item.slot * a.topk;
+    peaks.top.store(a.topk, a.cand_val + o, a.cand_idx + o, lane);
+  }
+}
+
+// LDS: SH == 1: one wave per workgroup, its histogram [slot][2][lane];
+// SH > 1: the group's histogram, then the part sums [kSumParts][lane]
+// (FP64) and the group's item index.
+template <int PH, int PK, int SH>
+__global__ __launch_bounds__(64 * SH) void wide_kernel(BatchArgs a, const WRec* __restrict__ recw,
+                                                       const int64_t* __restrict__ offw,
+                                                       const WideConst* __restrict__ wcs,
+                                                       const double* __restrict__ freqs,
+                                                       const Item* __restrict__ items) {
+  extern __shared__ __align__(16) uint64_t lds[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // uniform: keeps slice loads scalar
+  const int slots = a.n_bins + 1;
+  uint64_t* hist = lds;
+  double* part = reinterpret_cast<double*>(lds + (size_t)slots * kWideSlotWords);
+  int* group_item = reinterpret_cast<int*>(part + kSumParts * kWave);
+  for (int sl = wave; sl < slots; sl += SH) {
+    hist[sl * kWideSlotWords + lane] = 0;
+    hist[sl * kWideSlotWords + kWave + lane] = 0;
+  }
+  if (SH > 1) __syncthreads();  // every slot is clear before any wave folds into it
+  // as in the batched kernel: by index with at most one item per consumer,
+  // else every item (the first too) popped from this launch's counter
+  const bool by_index = a.n_items <= (int)gridDim.x;
+  for (int round = 0;; ++round) {
+    int it = 0;
+    if (by_index) {
+      if (round > 0) break;
+      it = (int)blockIdx.x;
+    } else if (SH > 1) {
+      if (threadIdx.x == 0) *group_item = (int)atomicAdd(a.queue, 1u);
+      __syncthreads();
+      it = __builtin_amdgcn_readfirstlane(*group_item);
+    } else {
+      if (lane == 0) it = (int)atomicAdd(a.queue, 1u);
+      it = __builtin_amdgcn_readfirstlane(it);
+    }
+    if (it >= a.n_items) break;
+    const Item item = items[it];
+    const int64_t p0 = offw[item.curve];
+    const int n_all = (int)(offw[item.curve + 1] - p0);
+    const int lo = slice_begin<SH>(wave, n_all);
+    process_item_wide<PH, PK, SH>(a, freqs, item, wcs[item.curve], recw + p0 + lo, slice_size<SH>(wave, n_all), hist,
+                                  lane, wave, part);
+  }
+}
+
+template <int PH, int PK>
+void* wide_ptr_sh(int share) {
+  return share == 4 ? (void*)&wide_kernel<PH, PK, 4>
+                    : (share == 2 ? (void*)&wide_kernel<PH, PK, 2> : (void*)&wide_kernel<PH, PK, 1>);
+}
+
+// Built for the FP64 folds (fused and listing order).
+void* wide_fn(int phase, int pk, int share) {
+  if (phase == PH_FP64) return pk ? wide_ptr_sh<PH_FP64, 1>(share) : wide_ptr_sh<PH_FP64, 0>(share);
+  if (phase == PH_LISTING) return pk ? wide_ptr_sh<PH_LISTING, 1>(share) : wide_ptr_sh<PH_LISTING, 0>(share);
+  return nullptr;
+}
+
 // ---------------------------------------------------------------- fused pass
 // For small plans the dependent launches of a pass cost more than their
 // work.  Here the prepare step is fused into the fold: one workgroup of four
@@ -793,6 +933,36 @@ hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int
   const Item* items = a.items;
   void* params[] = {&args, &rec, &offsets, &ccs, &freqs, &items};
   return hipLaunchKernel(fn, dim3(grid_groups), dim3(shape.waves_per_group * kWave), params, lds_bytes, s);
+}
+
+size_t wide_lds_bytes(int n_bins, int share) {
+  const size_t hist = (size_t)(n_bins + 1) * kWideSlotWords * sizeof(uint64_t);
+  return share > 1 ? hist + (size_t)kSumParts * kWave * sizeof(double) + 16 : hist;
+}
+
+hipError_t wide_groups_per_cu(int phase, int topk, int n_bins, int share, int* out) {
+  void* fn = wide_fn(phase, topk > 0, share);
+  if (fn == nullptr) return hipErrorInvalidDeviceFunction;
+  const size_t lds = wide_lds_bytes(n_bins, share);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, kWave * share, lds);
+}
+
+hipError_t launch_wide(const BatchArgs& a, int phase, int share, int grid_groups, hipStream_t s) {
+  void* fn = wide_fn(phase, a.topk > 0, share);
+  if (fn == nullptr) return hipErrorInvalidDeviceFunction;
+  const size_t lds = wide_lds_bytes(a.n_bins, share);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  BatchArgs args = a;
+  const WRec* recw = a.recw;
+  const int64_t* offw = a.offw;
+  const WideConst* wc = a.wc;
+  const double* freqs = a.freqs;
+  const Item* items = a.items;
+  void* params[] = {&args, &recw, &offw, &wc, &freqs, &items};
+  return hipLaunchKernel(fn, dim3(grid_groups), dim3(kWave * share), params, lds, s);
 }
 
 }  // namespace fpw

@@ -489,6 +489,7 @@ constexpr int kPrepRed = 5 * kPrepWaves;  // doubles of LDS the reduction needs
 // Centring, reference time and fixed-point scales of one curve.
 struct PrepConst {
   double mu, tref, s_w, s_y;
+  double sw, ay;  // sum of w and of |w x|: the wide format's scales derive from them
 };
 
 __device__ __forceinline__ double wave_sum_all(double v) {
@@ -574,6 +575,8 @@ __device__ __forceinline__ PrepConst curve_prep(const double* __restrict__ t, co
   for (int w = 1; w < kPrepWaves; ++w) ay += red[4 * kPrepWaves + w];
   k.s_w = (4294967296.0 - 2.0 - 2.0 * (double)n) / sw;
   k.s_y = ay > 0.0 ? (2147483648.0 - 2.0 - (double)n) / ay : 1.0;
+  k.sw = sw;
+  k.ay = ay;
   return k;
 }
 
@@ -589,6 +592,96 @@ __device__ __forceinline__ Rec make_rec(double t, double y, double dy, const Pre
   r.tau_bits = encode_tau(t - k.tref, phase);
   r.pk = (wq << 32) + (uint64_t)yq;
   return r;
+}
+
+// Wide format: 64-bit fields with the scales set a 2^-11 margin below the
+// field limits, so a sum of rounded values (each at most half a unit above
+// its exact product, and that product at most an ulp above) cannot reach
+// 2^64 (weights) or 2^63 in magnitude (weighted residuals) for any binning.
+// A unit is then Sum(w) / 2^64 of weight and Sum|w x| / 2^63 of residual,
+// and a value that large is held to ~2^-53 relative by the FP64 product
+// itself.
+constexpr double kWideScaleW = 18446744073709551616.0 * (1.0 - 1.0 / 2048.0);
+constexpr double kWideScaleY = 9223372036854775808.0 * (1.0 - 1.0 / 2048.0);
+
+__device__ __forceinline__ double wide_scale_w(const PrepConst& k) { return kWideScaleW / k.sw; }
+__device__ __forceinline__ double wide_scale_y(const PrepConst& k) { return k.ay > 0.0 ? kWideScaleY / k.ay : 1.0; }
+
+__device__ __forceinline__ WRec make_wrec(double t, double y, double dy, const PrepConst& k, int phase) {
+  const double w = 1.0 / (dy * dy);
+  const double wx = w * (y - k.mu);
+  WRec r;
+  r.tau_bits = encode_tau(t - k.tref, phase);
+  r.wq = (uint64_t)rint(w * wide_scale_w(k));
+  r.yq = (uint64_t)(int64_t)rint(wx * wide_scale_y(k));
+  r.pad = 0;
+  return r;
+}
+
+__device__ __forceinline__ WideConst make_wide_const(const PrepConst& k, double inv_alpha2, double stat_scale) {
+  WideConst c;
+  c.inv_sw = 1.0 / wide_scale_w(k);
+  c.inv_sy = 1.0 / wide_scale_y(k);
+  c.ia2 = inv_alpha2;
+  c.scale = stat_scale;
+  return c;
+}
+
+// The Eq. 1 term of one bin from its two wide words, in data units and FP64:
+// Y^2 / (W + 1/alpha^2), 0 for an empty bin with no prior.
+__device__ __forceinline__ double add_wide_term(double acc, uint64_t wq, uint64_t yq, const WideConst& k) {
+  const double W = (double)wq * k.inv_sw;
+  const double Y = (double)(int64_t)yq * k.inv_sy;
+  const double d = W + k.ia2;
+  return d > 0.0 ? acc + Y * (Y / d) : acc;
+}
+
+// A lane's wide histogram: slot m holds the weight word at h + 2 m 64 and the
+// residual word 64 words (512 bytes) further.
+constexpr int kWideSlotWords = 2 * kWave;
+
+// Reads and clears the wide slots of bins [m0, m0 + 8) (clamped to slot M,
+// which is empty by then).
+__device__ __forceinline__ void take_wide_block(uint64_t* h, int M, int m0, uint64_t (&fw)[kReduceBlock],
+                                                uint64_t (&fy)[kReduceBlock]) {
+#pragma unroll
+  for (int q = 0; q < kReduceBlock; ++q) {
+    uint64_t* sl = h + min(m0 + q, M) * kWideSlotWords;
+    fw[q] = lds_take(sl);
+    fy[q] = lds_take(sl + kWave);
+  }
+}
+
+// The part sums of the bins [part_block(p0), part_block(p1)) blocks of one
+// lane's wide histogram, in the fixed order of reduce_hist (each part from
+// zero, in bin order), written to out[p - p0]; the range holding block 0
+// also takes the wrap slot M of the fused FP64 fold.
+template <int PH, int NP>
+__device__ __forceinline__ void wide_parts(uint64_t* h, int M, int p0, const WideConst& k, double (&out)[NP]) {
+  const int nb = (M + kReduceBlock - 1) / kReduceBlock;
+  uint64_t ww = 0, wy = 0;
+  if (PH == PH_FP64 && part_block(p0, nb) == 0 && part_block(p0 + NP, nb) > 0) {
+    ww = lds_take(h + M * kWideSlotWords);
+    wy = lds_take(h + M * kWideSlotWords + kWave);
+  }
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) {
+    const int p = p0 + pp;
+    double acc = 0.0;
+    for (int b = part_block(p, nb); b < part_block(p + 1, nb); ++b) {
+      const int m0 = b * kReduceBlock;
+      uint64_t fw[kReduceBlock], fy[kReduceBlock];
+      take_wide_block(h, M, m0, fw, fy);
+      if (m0 == 0) {
+        fw[0] += ww;  // integer sums: adding the wrap slot is exact
+        fy[0] += wy;
+      }
+#pragma unroll
+      for (int q = 0; q < kReduceBlock; ++q)
+        if (m0 + q < M) acc = add_wide_term(acc, fw[q], fy[q], k);
+    }
+    out[pp] = acc;
+  }
 }
 
 __device__ __forceinline__ CurveConst make_curve_const(const PrepConst& k, double inv_alpha2, float stat_scale) {

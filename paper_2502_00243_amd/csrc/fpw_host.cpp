@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -16,6 +17,7 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fpw.h"
@@ -79,6 +81,14 @@ struct fpw_plan_s {
   DevBuf items, queue, cand_val, cand_idx, edge, slot_k0, curve_slot;
   fpw::Shape shape{1, 1, 4096, 0, 1};
   fpw::Variants var{};        // periodogram variants (multi-M reuse); var.n >= 1
+  // per-bin sum formats (fpw.h, "Per-bin sums"): fpw::FMT_* per curve, the
+  // first wide record of each curve, the wide queue and its launch shape
+  std::vector<uint8_t> h_fmt;
+  std::vector<int64_t> h_offw;
+  int64_t n_wide = 0;
+  DevBuf fmt, offw, recw, wc, items_w;
+  int n_items_w = 0;
+  int wide_share = 1, wide_grid = 0;
   // shift of the fused FP64 fold (see fused_fold_shift); fused_fold is false
   // when the plan's fold range made it fold in the listing order instead
   double fold_nh = 0.0;
@@ -190,6 +200,165 @@ double fused_fold_shift(int M, double max_cycles, bool* ok) {
   return -(0.5 / (double)M - delta);
 }
 
+// ---------------------------------------------------------------- per-bin sum formats
+// The bin sums are exact integers of values rounded once to a per-curve unit
+// (fpw.h, "Per-bin sums").  For one curve and a field capacity cap_w
+// (weights) / cap_y (residuals), with u = Sum(w) / cap_w:
+//   e_w   = u / (2 min w): the worst relative error of any bin's W (a bin's
+//           error over its weight is at most the largest error over weight
+//           of its points);
+//   e_dup = u / (2 w) for the smallest w of a run of at least
+//           max(2, ceil(N / (4 M))) weights (in sorted order) each closer
+//           than u / 4 to the next: points of (nearly) equal weight round
+//           alike, so a bin filled with them keeps that error instead of
+//           averaging it (a few such points are no worse than one point,
+//           which e_w covers);
+//   e_y   = sqrt(Sum(1/w) (Sum(w) + M/alpha^2)) / (2 cap_y): with |E_m| the
+//           rounding of a bin's residual sum, Sum_m E_m^2 / W_m <= Sum_i
+//           e_i^2 / w_i <= (v/2)^2 Sum(1/w), v = Sum|w x| / cap_y, against the
+//           guard scale S_abs >= Sum|w x|^2 / (Sum(w) + M/alpha^2).
+constexpr double kNarrowMaxW = 1e-4, kNarrowMaxDup = 5e-6, kNarrowMaxY = 4e-6;
+constexpr double kWideMax = 1e-6;
+constexpr double kWideCapW = 18446744073709551616.0 * (1.0 - 1.0 / 2048.0);  // as the prepare kernel's scales
+constexpr double kWideCapY = 9223372036854775808.0 * (1.0 - 1.0 / 2048.0);
+
+struct SumBounds {
+  double e_w = 0, e_dup = 0, e_y = 0;
+};
+
+// Per-curve quantities the bounds need: N, Sum(w), min w, Sum(1/w), Sum|w x|
+// and the weights in ascending order.
+struct CurveWeights {
+  int64_t n = 0;
+  double sw = 0, wmin = 0, h = 0, a = 0;
+  std::vector<double> w;  // sorted
+};
+
+void curve_weights(const double* y, const double* dy, int64_t n, int center, CurveWeights* cw) {
+  cw->n = n;
+  cw->w.resize((size_t)n);
+  double sw = 0, swy = 0, sy = 0, h = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double w = 1.0 / (dy[i] * dy[i]);
+    cw->w[(size_t)i] = w;
+    sw += w;
+    swy += w * y[i];
+    sy += y[i];
+    h += dy[i] * dy[i];
+  }
+  const double mu = center == FPW_CENTER_WEIGHTED ? swy / sw : (center == FPW_CENTER_MEAN ? sy / (double)n : 0.0);
+  double a = 0;
+  for (int64_t i = 0; i < n; ++i) a += std::fabs(cw->w[(size_t)i] * (y[i] - mu));
+  std::sort(cw->w.begin(), cw->w.end());
+  cw->sw = sw;
+  cw->wmin = cw->w[0];
+  cw->h = h;
+  cw->a = a;
+}
+
+SumBounds sum_bounds(const CurveWeights& cw, double cap_w, double cap_y, int M, double ia2, bool dup) {
+  SumBounds b;
+  const double u = cw.sw / cap_w;
+  b.e_w = u / (2.0 * cw.wmin);
+  b.e_y = std::sqrt(cw.h * (cw.sw + M * ia2)) / (2.0 * cap_y);
+  if (dup) {
+    const size_t k_min = (size_t)std::max<int64_t>(2, (cw.n + 4 * (int64_t)M - 1) / (4 * (int64_t)M));
+    for (size_t i = 0; i < cw.w.size();) {
+      size_t j = i + 1;
+      while (j < cw.w.size() && cw.w[j] - cw.w[j - 1] < 0.25 * u) ++j;
+      if (j - i >= k_min) {
+        b.e_dup = u / (2.0 * cw.w[i]);
+        break;
+      }
+      i = j;
+    }
+  }
+  return b;
+}
+
+bool narrow_fits(const CurveWeights& cw, int M, double ia2, double cap_w, double cap_y, SumBounds* b) {
+  *b = sum_bounds(cw, cap_w, cap_y, M, ia2, true);
+  return b->e_w <= kNarrowMaxW && b->e_dup <= kNarrowMaxDup && b->e_y <= kNarrowMaxY;
+}
+
+// The format of every curve (fpw::FMT_*): narrow where it fits, else wide
+// where that fits, else FPW_EUNSUPPORTED (also where the plan needs the
+// narrow format for every curve).  `cap_shift` 0 for the general kernels;
+// the baseline kernel's Z sums have 31-bit fields.  Curves are split over
+// host threads.
+fpw_status choose_formats(int64_t n_curves, const int64_t* offsets, const double* y, const double* dy,
+                          const fpw_options& o, int n_var, std::vector<uint8_t>* fmt, int64_t* n_wide) {
+  fmt->assign((size_t)n_curves, (uint8_t)fpw::FMT_NARROW);
+  const bool bm = o.baseline_terms > 0;
+  std::vector<int64_t> bad((size_t)n_curves, 0);  // 1 narrow impossible here, 2 no format fits
+  std::vector<SumBounds> why((size_t)n_curves);
+  const int64_t pts = offsets[n_curves];
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)std::max(1u, std::thread::hardware_concurrency()),
+                                                               (int64_t)16, 1 + pts / 200000}));
+  auto work = [&](int tid) {
+    CurveWeights cw;
+    for (int64_t c = tid; c < n_curves; c += nt) {
+      const int64_t a = offsets[c], n = offsets[c + 1] - offsets[c];
+      curve_weights(y + a, dy + a, n, o.center, &cw);
+      if (!std::isfinite(cw.sw) || !std::isfinite(cw.a)) {
+        bad[(size_t)c] = 3;
+        continue;
+      }
+      SumBounds b;
+      const double nd = (double)n;
+      const double cap_w = (bm ? 2147483648.0 - 2.0 - nd : 4294967296.0 - 2.0 - 2.0 * nd);
+      const double cap_y = 2147483648.0 - 2.0 - nd;
+      if (o.sum_format != FPW_SUMS_WIDE && narrow_fits(cw, o.n_bins, o.inv_alpha2, cap_w, cap_y, &b)) continue;
+      if (o.sum_format == FPW_SUMS_WIDE) b = sum_bounds(cw, cap_w, cap_y, o.n_bins, o.inv_alpha2, true);
+      why[(size_t)c] = b;
+      if (bm) {
+        bad[(size_t)c] = 1;
+        continue;
+      }
+      const SumBounds wb = sum_bounds(cw, kWideCapW, kWideCapY, o.n_bins, o.inv_alpha2, false);
+      if (std::max(wb.e_w, 0x1p-53) <= kWideMax && wb.e_y <= kWideMax) {
+        (*fmt)[(size_t)c] = (uint8_t)fpw::FMT_WIDE;
+      } else {
+        bad[(size_t)c] = 2;
+        why[(size_t)c] = wb;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int i = 1; i < nt; ++i) th.emplace_back(work, i);
+  work(0);
+  for (std::thread& t : th) t.join();
+  *n_wide = 0;
+  for (int64_t c = 0; c < n_curves; ++c) {
+    const SumBounds& b = why[(size_t)c];
+    if (bad[(size_t)c] == 3)
+      return fail(FPW_EUNSUPPORTED, "curve %lld: sum of 1/dy^2 or of |w x| overflows", (long long)c);
+    if (bad[(size_t)c] == 1)
+      return fail(FPW_EUNSUPPORTED,
+                  "curve %lld: its weights span too wide a range for the baseline kernel's 32-bit sums "
+                  "(e_w %.3g, e_dup %.3g, e_y %.3g; limits %g, %g, %g)",
+                  (long long)c, b.e_w, b.e_dup, b.e_y, kNarrowMaxW, kNarrowMaxDup, kNarrowMaxY);
+    if (bad[(size_t)c] == 2)
+      return fail(FPW_EUNSUPPORTED,
+                  "curve %lld: its weights span too wide a range even for the wide bin sums (e_w %.3g, e_y %.3g; "
+                  "limit %g)",
+                  (long long)c, b.e_w, b.e_y, kWideMax);
+    *n_wide += (*fmt)[(size_t)c] == fpw::FMT_WIDE;
+  }
+  if (*n_wide > 0) {
+    const char* why_narrow = n_var > 1 ? "derived bin counts"
+                             : (o.phase >= FPW_PHASE_DF32 ? "the FP32-based phase modes"
+                                                          : (o.fuse_prepare == 1 ? "the fused pass" : nullptr));
+    if (why_narrow)
+      return fail(FPW_EUNSUPPORTED, "%lld curve(s) need the wide bin sums, which %s do not support", (long long)*n_wide,
+                  why_narrow);
+    if (o.n_bins > FPW_MAX_WIDE_BINS)
+      return fail(FPW_EUNSUPPORTED, "%lld curve(s) need the wide bin sums, built for n_bins <= %d", (long long)*n_wide,
+                  FPW_MAX_WIDE_BINS);
+  }
+  return FPW_OK;
+}
+
 fpw_status check_options(const fpw_options& o) {
   if (o.n_bins < 1) return fail(FPW_EINVAL, "n_bins must be >= 1 (got %d)", o.n_bins);
   if (o.n_bins > FPW_MAX_BINS) return fail(FPW_EUNSUPPORTED, "n_bins %d exceeds FPW_MAX_BINS=%d", o.n_bins, FPW_MAX_BINS);
@@ -235,6 +404,10 @@ fpw_status check_options(const fpw_options& o) {
     return fail(FPW_EUNSUPPORTED, "derived bin counts with a shared histogram are built for the FP64 phase modes");
   if (o.shared_kernel < 0 || o.shared_kernel > 2) return fail(FPW_EINVAL, "shared_kernel must be 0, 1 or 2");
   if (o.fuse_prepare < -1 || o.fuse_prepare > 1) return fail(FPW_EINVAL, "fuse_prepare must be -1, 0 or 1");
+  if (o.sum_format != FPW_SUMS_AUTO && o.sum_format != FPW_SUMS_WIDE)
+    return fail(FPW_EINVAL, "sum_format must be FPW_SUMS_AUTO or FPW_SUMS_WIDE");
+  if (o.sum_format == FPW_SUMS_WIDE && o.baseline_terms > 0)
+    return fail(FPW_EUNSUPPORTED, "the baseline kernel keeps its sums in the narrow format");
   if (o.fuse_prepare == 1 && (nvar > 1 || o.baseline_terms != 0))
     return fail(FPW_EUNSUPPORTED, "the fused pass serves plans with one periodogram variant and no baseline terms");
   if (o.fuse_prepare == 1 && (o.freqs_per_lane == 2 || o.point_source != 0 || o.waves_per_group == 1 ||
@@ -276,6 +449,10 @@ fpw_status validate(int64_t n_curves, const int64_t* offsets, const double* t, c
       if (!finite(t[i]) || !finite(y[i]) || !finite(dy[i]))
         return fail(FPW_EINVAL, "non-finite t, y or dy at point %lld", (long long)i);
       if (!(dy[i] > 0)) return fail(FPW_EINVAL, "dy must be > 0 (point %lld)", (long long)i);
+      const double w = 1.0 / (dy[i] * dy[i]);
+      if (!(w >= DBL_MIN && w <= DBL_MAX))
+        return fail(FPW_EUNSUPPORTED, "1/dy^2 of point %lld (dy = %g) is not a finite normal double", (long long)i,
+                    dy[i]);
       tmin = std::min(tmin, t[i]);
       tmax = std::max(tmax, t[i]);
     }
@@ -393,11 +570,20 @@ fpw_status upload_items(fpw_plan_s* p) {
   std::vector<fpw::Item> nat;
   std::vector<int32_t> slot_k0, curve_slot;
   build_items(p, p->shape.chunk_freqs, &nat, &slot_k0, &curve_slot);
-  std::vector<fpw::Item> q = queue_order(p, nat);
+  // one queue per sum format, each longest curves first
+  std::vector<fpw::Item> q, qw;
+  for (const fpw::Item& it : queue_order(p, nat))
+    (p->n_wide > 0 && p->h_fmt[it.curve] == fpw::FMT_WIDE ? qw : q).push_back(it);
   p->n_items = (int)q.size();
+  p->n_items_w = (int)qw.size();
   p->h_items_nat = nat;
   FPW_HIP(p->items.alloc(q.size() * sizeof(fpw::Item)), "alloc items");
-  FPW_HIP(hipMemcpy(p->items.p, q.data(), q.size() * sizeof(fpw::Item), hipMemcpyHostToDevice), "upload items");
+  if (!q.empty())
+    FPW_HIP(hipMemcpy(p->items.p, q.data(), q.size() * sizeof(fpw::Item), hipMemcpyHostToDevice), "upload items");
+  FPW_HIP(p->items_w.alloc(qw.size() * sizeof(fpw::Item)), "alloc wide items");
+  if (!qw.empty())
+    FPW_HIP(hipMemcpy(p->items_w.p, qw.data(), qw.size() * sizeof(fpw::Item), hipMemcpyHostToDevice),
+            "upload wide items");
   FPW_HIP(p->slot_k0.alloc(slot_k0.size() * sizeof(int32_t)), "alloc slot_k0");
   FPW_HIP(hipMemcpy(p->slot_k0.p, slot_k0.data(), slot_k0.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload slot_k0");
   FPW_HIP(p->curve_slot.alloc(curve_slot.size() * sizeof(int32_t)), "alloc curve_slot");
@@ -462,6 +648,23 @@ fpw::PrepArgs prep_args(const fpw_plan_s* p) {
   a.w64 = p->w64.as<double>();
   a.wx64 = p->wx64.as<double>();
   a.queue = p->queue.as<uint32_t>();
+  a.n_queues = p->n_wide > 0 ? 2 : 1;
+  if (p->n_wide > 0) {
+    a.fmt = p->fmt.as<uint8_t>();
+    a.offw = p->offw.as<int64_t>();
+    a.recw = p->recw.as<fpw::WRec>();
+    a.wc = p->wc.as<fpw::WideConst>();
+  }
+  return a;
+}
+
+// Arguments of the wide-format fold kernel: its own queue and counter.
+fpw::BatchArgs wide_args(const fpw_plan_s* p, float* S) {
+  fpw::BatchArgs a = batch_args(p, S, p->items_w, p->n_items_w);
+  a.queue = p->queue.as<uint32_t>() + 1;
+  a.recw = p->recw.as<fpw::WRec>();
+  a.offw = p->offw.as<int64_t>();
+  a.wc = p->wc.as<fpw::WideConst>();
   return a;
 }
 
@@ -632,9 +835,12 @@ fpw_status enqueue_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipSt
   if (prof) FPW_HIP(hipEventRecord(p->ev[0], s), "event record");
   FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
   if (prof) FPW_HIP(hipEventRecord(p->ev[1], s), "event record");
-  FPW_HIP(fpw::launch_batched(batch_args(p, S, p->items, p->n_items), p->shape, p->opt.phase,
-                              launch_groups(p, p->n_items), p->lds_bytes, s),
-          "batched kernel");
+  if (p->n_items > 0)
+    FPW_HIP(fpw::launch_batched(batch_args(p, S, p->items, p->n_items), p->shape, p->opt.phase,
+                                launch_groups(p, p->n_items), p->lds_bytes, s),
+            "batched kernel");
+  if (p->n_items_w > 0)
+    FPW_HIP(fpw::launch_wide(wide_args(p, S), p->opt.phase, p->wide_share, p->wide_grid, s), "wide kernel");
   if (prof) FPW_HIP(hipEventRecord(p->ev[2], s), "event record");
   if (idx != nullptr) FPW_HIP(fpw::launch_merge(merge_args(p, idx, val), s), "merge kernel");
   if (prof) FPW_HIP(hipEventRecord(p->ev[3], s), "event record");
@@ -736,7 +942,8 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
     build_items(p, p->shape.chunk_freqs, &nat, &sk, &cs);
     std::vector<fpw::Item> q;
     for (const fpw::Item& it : queue_order(p, nat))
-      if (it.curve % stride == 0) q.push_back(it);
+      if (it.curve % stride == 0 && (p->n_wide == 0 || p->h_fmt[it.curve] == fpw::FMT_NARROW)) q.push_back(it);
+    if (q.empty()) continue;
     DevBuf items;
     FPW_HIP(items.alloc(q.size() * sizeof(fpw::Item)), "alloc tune items");
     FPW_HIP(hipMemcpy(items.p, q.data(), q.size() * sizeof(fpw::Item), hipMemcpyHostToDevice), "upload tune items");
@@ -829,6 +1036,18 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
   bool fused_fold = true;
   const double fold_nh = fused_fold_shift(o.n_bins, max_tau * max_f, &fused_fold);
   if (o.phase == FPW_PHASE_FP64 && !fused_fold) o.phase = FPW_PHASE_FP64_LISTING;
+  int n_var = 1;
+  for (int d = 0; d < FPW_MAX_DERIVED && o.derived_bins[d] != 0; ++d) n_var += o.all_offsets ? o.n_bins / o.derived_bins[d] : 1;
+  std::vector<uint8_t> fmt;
+  int64_t n_wide = 0;
+  try {
+    st = choose_formats(n_curves, offsets, y, dy, o, n_var, &fmt, &n_wide);
+  } catch (const std::bad_alloc&) {
+    return fail(FPW_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(FPW_EHIP, "unexpected exception");
+  }
+  if (st != FPW_OK) return st;
   // ---- all checks passed: from here on HIP calls are made
   try {
     fpw_plan_s* p = new fpw_plan_s();
@@ -836,6 +1055,8 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     p->opt = o;
     p->fold_nh = fold_nh;
     p->fused_fold = fused_fold;
+    p->h_fmt.swap(fmt);
+    p->n_wide = n_wide;
     p->n_curves = n_curves;
     p->n_freq = n_freq;
     p->n_points = offsets[n_curves];
@@ -882,8 +1103,20 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     FPW_HIP(p->wx64.alloc(np * sizeof(double)), "alloc wx64");
     if (o.profile)
       for (hipEvent_t& e : p->ev) FPW_HIP(hipEventCreate(&e), "event create");
-    FPW_HIP(p->queue.alloc(sizeof(uint32_t)), "alloc queue");
-    FPW_HIP(hipMemsetAsync(p->queue.p, 0, sizeof(uint32_t), s), "clear queue");
+    // one counter per fold kernel: the batched one, then the wide-format one
+    FPW_HIP(p->queue.alloc(2 * sizeof(uint32_t)), "alloc queue");
+    FPW_HIP(hipMemsetAsync(p->queue.p, 0, 2 * sizeof(uint32_t), s), "clear queue");
+    if (p->n_wide > 0) {
+      // wide records: the wide curves' points, packed in curve order
+      p->h_offw.assign((size_t)n_curves + 1, 0);
+      for (int64_t c = 0; c < n_curves; ++c)
+        p->h_offw[(size_t)c + 1] = p->h_offw[(size_t)c] + (p->h_fmt[(size_t)c] == fpw::FMT_WIDE ? offsets[c + 1] - offsets[c] : 0);
+      st = upload(p->fmt, p->h_fmt.data(), p->h_fmt.size(), s, "upload formats");
+      if (st == FPW_OK) st = upload(p->offw, p->h_offw.data(), p->h_offw.size(), s, "upload wide offsets");
+      if (st != FPW_OK) return st;
+      FPW_HIP(p->recw.alloc((size_t)p->h_offw[(size_t)n_curves] * sizeof(fpw::WRec)), "alloc wide records");
+      FPW_HIP(p->wc.alloc((size_t)n_curves * sizeof(fpw::WideConst)), "alloc wide constants");
+    }
     // prepared records are needed by autotune, fpw_eval_fp64 and fpw_debug_bins
     FPW_HIP(fpw::launch_prepare(prep_args(p), s), "prepare kernel");
     // Large M leaves room for few waves per CU; their scalar-load waits then
@@ -906,7 +1139,7 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     // frequencies per CU) unless a launch shape or its tuning was asked for.
     const int64_t items64 = n_curves * ((n_freq + kWave - 1) / kWave);
     const bool overrides = o.freqs_per_lane || o.waves_per_group || o.chunk_freqs || o.point_source || o.hist_share;
-    const bool fused_ok = p->var.n == 1 && o.baseline_terms == 0 &&
+    const bool fused_ok = p->var.n == 1 && o.baseline_terms == 0 && p->n_wide == 0 &&
                           fpw::fused_lds_bytes(o.n_bins) + 1024 <= (size_t)160 * 1024;
     p->fused = fused_ok && (o.fuse_prepare == 1 || (o.fuse_prepare == 0 && !overrides && !o.autotune &&
                                                     items64 <= (int64_t)kFusedItemsPerCu * p->n_cu));
@@ -928,6 +1161,15 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     st = upload_items(p);
     if (st != FPW_OK) return st;
     if (p->fused) p->grid_groups = p->n_items;
+    if (p->n_items_w > 0) {
+      // wide histograms take 16 bytes per bin and lane: shared by two waves
+      // from 8 bins, by four from 16
+      const int M = o.n_bins;
+      p->wide_share = M < 8 ? 1 : (M < 16 ? 2 : 4);
+      int per_cu = 0;
+      FPW_HIP(fpw::wide_groups_per_cu(o.phase, o.topk, M, p->wide_share, &per_cu), "wide kernel occupancy");
+      p->wide_grid = std::max(1, std::min(std::max(1, per_cu) * p->n_cu, p->n_items_w));
+    }
     if (o.baseline_terms > 0) {
       p->bm = true;
       FPW_HIP(p->bm_rec.alloc(np * sizeof(fpw::Rec)), "alloc baseline records");
@@ -979,7 +1221,34 @@ fpw_status fpw_plan_shared(fpw_plan_t* out, int64_t n_curves, int64_t n_points, 
   if (o.shared_kernel == FPW_SHARED_MATRIX && !fits)
     return fail(FPW_EUNSUPPORTED, "the matrix-core kernel needs n_bins <= %d, phase FP64 or FP64_LISTING, no derived bin "
                 "counts, no baseline terms, at most 1048560 curves and %d points", fpw::kSharedMaxBins, fpw::kSharedMaxPoints);
-  const bool mfma = fits && o.shared_kernel != FPW_SHARED_GENERAL;
+  // the matrix-core kernel's sums have 30-bit fields: every curve must fit the
+  // narrow bounds there (else the general kernel takes the plan, or, when the
+  // matrix-core kernel was asked for, the plan is refused)
+  bool digits_fit = o.sum_format == FPW_SUMS_AUTO;
+  if (fits && digits_fit && o.shared_kernel != FPW_SHARED_GENERAL) {
+    bool finite_ok = true;
+    for (int64_t i = 0; i < n_curves * n_points && finite_ok; ++i)
+      finite_ok = std::isfinite(y[i]) && std::isfinite(dy[i]) && dy[i] > 0 && 1.0 / (dy[i] * dy[i]) >= DBL_MIN &&
+                  1.0 / (dy[i] * dy[i]) <= DBL_MAX;
+    if (finite_ok) {  // (otherwise fpw_plan below reports the input)
+      try {
+        CurveWeights cw;
+        const double nd = (double)n_points;
+        for (int64_t c = 0; c < n_curves && digits_fit; ++c) {
+          SumBounds b;
+          curve_weights(y + c * n_points, dy + c * n_points, n_points, o.center, &cw);
+          digits_fit = std::isfinite(cw.sw) && std::isfinite(cw.a) &&
+                       narrow_fits(cw, o.n_bins, o.inv_alpha2, 1073741824.0 - 2.0 - 2.0 * nd, 1073741824.0 - 2.0 - nd, &b);
+        }
+      } catch (const std::bad_alloc&) {
+        return fail(FPW_ENOMEM, "host allocation failed");
+      }
+    }
+  }
+  if (o.shared_kernel == FPW_SHARED_MATRIX && !digits_fit)
+    return fail(FPW_EUNSUPPORTED, "a curve's weights span too wide a range for the matrix-core kernel's 30-bit sums "
+                "(or sum_format asks for the wide format)");
+  const bool mfma = fits && digits_fit && o.shared_kernel != FPW_SHARED_GENERAL;
   try {
     // the equivalent CSR batch: every curve holds the common times
     std::vector<int64_t> offs((size_t)n_curves + 1);
@@ -1219,7 +1488,8 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   info->waves_per_group = p->shape.waves_per_group;
   info->chunk_freqs = p->shape.chunk_freqs;
   info->grid_groups = p->grid_groups;
-  info->work_items = p->n_items;
+  info->work_items = p->n_items + p->n_items_w;
+  info->n_wide_curves = (int32_t)p->n_wide;
   info->lds_bytes = (int32_t)p->lds_bytes;
   info->tuned = p->tuned ? 1 : 0;
   info->point_source = p->shape.point_source + 1;

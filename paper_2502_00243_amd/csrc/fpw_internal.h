@@ -17,6 +17,29 @@ struct alignas(16) Rec {
   uint64_t pk;
 };
 
+// One prepared observation of a curve whose sums take the wide format, 32
+// bytes: the time offset as in Rec, then the fixed-point weight (unsigned 64
+// bits) and weighted residual (two's complement 64 bits), each added by its
+// own 64-bit LDS atomic.
+struct alignas(16) WRec {
+  uint64_t tau_bits;
+  uint64_t wq;
+  uint64_t yq;
+  uint64_t pad;
+};
+
+// Per-bin sum formats of a curve: one packed 64-bit word of 32-bit fields, or
+// two 64-bit words (fpw_plan chooses per curve from its weights).
+enum { FMT_NARROW = 0, FMT_WIDE = 1 };
+
+// Per-curve constants of a wide-format curve (FP64 epilogue).
+struct alignas(16) WideConst {
+  double inv_sw;  // data units of one weight unit
+  double inv_sy;  // data units of one weighted-residual unit
+  double ia2;     // 1 / alpha^2
+  double scale;   // 0.5 for the listing's half scale, else 1
+};
+
 // Per-curve constants produced by the prepare kernel.
 struct alignas(16) CurveConst {
   float kc;     // s_w / s_y^2: converts sum Y_q^2 / W_q back to data units
@@ -42,7 +65,12 @@ struct PrepArgs {
   double* tau64;         // [n_points] FP64 arrays for the plain comparator
   double* w64;
   double* wx64;
-  uint32_t* queue;       // work-queue counter of the pass's fold kernel, zeroed here (or null)
+  uint32_t* queue;       // work-queue counters of the pass's fold kernels, zeroed here (or null)
+  int n_queues;          // counters at queue (1, or 2 with wide-format curves)
+  const uint8_t* fmt;    // [n_curves] FMT_*, or null: every curve narrow
+  const int64_t* offw;   // [n_curves + 1]: first wide record of each curve (wide curves only)
+  WRec* recw;            // wide records
+  WideConst* wc;         // [n_curves] (wide curves only)
 };
 
 // Work item: curve, frequency range [k0, k1), output slot (natural order).
@@ -83,6 +111,10 @@ struct BatchArgs {
   int32_t* cand_idx;      // [(n_slots * n_var) * topk]
   float* edge;            // [(n_slots * n_var) * 4]: S at k0, k0+1, k1-2, k1-1 (-inf if absent)
   uint32_t* queue;        // [1]: the work-queue counter; zeroed by the prepare kernel
+  // wide-format launch only: its records, offsets into them and constants
+  const WRec* recw;
+  const int64_t* offw;
+  const WideConst* wc;
 };
 
 // Raw inputs of the fused pass, whose fold kernel prepares every curve itself.
@@ -269,6 +301,12 @@ struct Shape {
 hipError_t launch_prepare(const PrepArgs& a, hipStream_t s);
 hipError_t launch_batched(const BatchArgs& a, const Shape& shape, int phase, int grid_groups,
                           size_t lds_bytes, hipStream_t s);  // n_var > 1 needs one frequency per lane
+// The wide-format fold kernel over a.items (curves whose sums need two 64-bit
+// words), with `share` waves per histogram (1, 2 or 4), one frequency per lane
+// and scalar point loads; one periodogram variant.
+hipError_t launch_wide(const BatchArgs& a, int phase, int share, int grid_groups, hipStream_t s);
+size_t wide_lds_bytes(int n_bins, int share);
+hipError_t wide_groups_per_cu(int phase, int topk, int n_bins, int share, int* out);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s, bool group = false);
 // Fused pass of a small plan: prepare + fold/bin/accumulate/reduce + peaks
 // in workgroups of fused_waves() waves, one per item of a.items (a.n_items

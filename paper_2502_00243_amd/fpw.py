@@ -26,6 +26,7 @@ TREF = {"zero": 0, "first": 1, "given": 2}
 PHASE = {"fp64": 0, "fp64_listing": 1, "df32": 2, "fp32": 3}
 STAT = {"eq1": 0, "listing_half": 1}
 SHARED_KERNEL = {"auto": 0, "general": 1, "matrix": 2}
+SUM_FORMAT = {"auto": 0, "wide": 1}
 MAX_BINS = 255
 MAX_TOPK = 16
 
@@ -61,6 +62,7 @@ class Options(ctypes.Structure):
         ("baseline_scale", ctypes.c_double),
         ("hist_share", ctypes.c_int32),
         ("fuse_prepare", ctypes.c_int32),
+        ("sum_format", ctypes.c_int32),
     ]
 
 
@@ -85,6 +87,7 @@ class PlanInfo(ctypes.Structure):
         ("kernel", ctypes.c_int32),
         ("hist_share", ctypes.c_int32),
         ("fuse_prepare", ctypes.c_int32),
+        ("n_wide_curves", ctypes.c_int32),
     ]
 
 
@@ -163,7 +166,7 @@ def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="
                  inv_alpha2=0.0, autotune=False, use_graph=True, freqs_per_lane=0, waves_per_group=0, chunk_freqs=0,
                  tune_cache=None, profile=False, point_source=0, derived_bins=(), all_offsets=False,
                  shared_kernel=0, baseline_terms=0, baseline_scale=1.0, hist_share=0,
-                 fuse_prepare=0) -> Options:
+                 fuse_prepare=0, sum_format=0) -> Options:
     o = default_options()
     o.n_bins = int(n_bins)
     o.center = CENTER[center] if isinstance(center, str) else int(center)
@@ -191,6 +194,7 @@ def make_options(n_bins: int, center="weighted", tref="zero", t_ref=0.0, phase="
     o.baseline_scale = float(baseline_scale)
     o.hist_share = int(hist_share)
     o.fuse_prepare = int(fuse_prepare)
+    o.sum_format = SUM_FORMAT[sum_format] if isinstance(sum_format, str) else int(sum_format)
     return o
 
 

@@ -15,6 +15,9 @@
 
 #include "fpw.h"
 
+extern "C" void stub_fail(int kind, long nth);  // hip_stub.cpp: the nth call of a kind fails
+extern "C" int stub_failed(void);
+
 namespace {
 
 int failures = 0;
@@ -132,9 +135,217 @@ void expect_chunk(int C, int N, int F, int want, const char* what) {
   fpw_plan_destroy(p);
 }
 
+// A batch in which curve c (of `kinds`) holds its own weight pattern:
+// 0 ordinary lognormal-like errors, 1 one point 1e4 times more precise than
+// the rest (equal errors otherwise), 2 errors spread over 1e-5..1, 3 over
+// 1e-9..1 (beyond every format).
+Batch weight_batch(const std::vector<int>& kinds, int n_freq) {
+  Batch b;
+  b.off.assign(kinds.size() + 1, 0);
+  for (size_t c = 0; c < kinds.size(); ++c) {
+    const int n = 300;
+    for (int i = 0; i < n; ++i) {
+      double dy = 0.02 * std::exp(0.4 * std::sin(1.7 * i + (double)c));
+      if (kinds[c] == 1) dy = i == n / 2 ? 2e-6 : 0.02;
+      if (kinds[c] == 2) dy = std::pow(10.0, -5.0 * ((i * 37) % n) / (double)(n - 1));
+      if (kinds[c] == 3) dy = std::pow(10.0, -9.0 * ((i * 37) % n) / (double)(n - 1));
+      b.t.push_back(i * 4.1 + (double)c);
+      b.y.push_back(dy * std::sin(i * 0.9));
+      b.dy.push_back(dy);
+    }
+    b.off[c + 1] = (int64_t)b.t.size();
+  }
+  for (int i = 0; i < n_freq; ++i) b.f.push_back(0.05 + i * 0.02);
+  return b;
+}
+
+fpw_status plan_of(const Batch& b, const fpw_options& o, fpw_plan_t* p) {
+  const int64_t C = (int64_t)b.off.size() - 1;
+  return fpw_plan(p, C, b.off.data(), b.t.data(), b.y.data(), b.dy.data(), (int64_t)b.f.size(), b.f.data(), &o, nullptr);
+}
+
+// Per-bin sum formats: curves are routed by their weights, plans that need
+// the narrow format everywhere refuse wide curves, weights beyond both
+// formats are refused.
+void sum_formats() {
+  fpw_options o;
+  const Batch mixed = weight_batch({0, 1, 0, 2, 0, 1}, 300);
+  for (int M : {1, 7, 20, 64}) {
+    for (int topk : {0, 5}) {
+      fpw_options_default(&o);
+      o.n_bins = M;
+      o.topk = topk;
+      fpw_plan_t p = nullptr;
+      expect(plan_of(mixed, o, &p), FPW_OK, "mixed-weight plan");
+      if (!p) continue;
+      ++plans;
+      fpw_plan_info info;
+      expect(fpw_get_plan_info(p, &info), FPW_OK, "info");
+      if (info.n_wide_curves != 3 || info.fuse_prepare != 0) {
+        std::printf("FAIL mixed-weight plan M=%d: %d wide curves, fused %d (want 3, 0)\n", M, info.n_wide_curves,
+                    info.fuse_prepare);
+        ++failures;
+      }
+      passes(p, o, 6, 300, 1);
+      fpw_plan_destroy(p);
+    }
+  }
+  // every curve wide on request, ordinary weights included; a profiled pass
+  fpw_options_default(&o);
+  o.n_bins = 20;
+  o.topk = 3;
+  o.sum_format = FPW_SUMS_WIDE;
+  o.profile = 1;
+  fpw_plan_t p = nullptr;
+  expect(plan_of(mixed, o, &p), FPW_OK, "all-wide plan");
+  if (p) {
+    ++plans;
+    fpw_plan_info info;
+    expect(fpw_get_plan_info(p, &info), FPW_OK, "info");
+    if (info.n_wide_curves != 6) {
+      std::printf("FAIL all-wide plan: %d wide curves\n", info.n_wide_curves);
+      ++failures;
+    }
+    passes(p, o, 6, 300, 1);
+    fpw_plan_destroy(p);
+  }
+  // plans that keep every curve narrow refuse the wide ones
+  struct Refusal {
+    int terms, derived, phase, fuse, M;
+    const char* what;
+  };
+  for (const Refusal& r : {Refusal{2, 0, 0, 0, 20, "baseline"}, Refusal{0, 10, 0, 0, 20, "derived bins"},
+                           Refusal{0, 0, 2, 0, 20, "df32"}, Refusal{0, 0, 3, 0, 20, "fp32"},
+                           Refusal{0, 0, 0, 1, 20, "forced fused pass"}, Refusal{0, 0, 0, 0, 157, "M above wide max"}}) {
+    fpw_options_default(&o);
+    o.n_bins = r.M;
+    o.baseline_terms = r.terms;
+    o.derived_bins[0] = r.derived;
+    o.phase = r.phase;
+    o.fuse_prepare = r.fuse;
+    p = nullptr;
+    expect(plan_of(mixed, o, &p), FPW_EUNSUPPORTED, r.what);
+    if (p) fpw_plan_destroy(p);
+  }
+  fpw_options_default(&o);
+  o.n_bins = 20;
+  o.sum_format = FPW_SUMS_WIDE;
+  o.baseline_terms = 1;
+  p = nullptr;
+  expect(plan_of(weight_batch({0}, 50), o, &p), FPW_EUNSUPPORTED, "wide baseline");
+  if (p) fpw_plan_destroy(p);
+  // beyond both formats, and weights that are not finite normal doubles
+  fpw_options_default(&o);
+  o.n_bins = 20;
+  p = nullptr;
+  expect(plan_of(weight_batch({0, 3}, 50), o, &p), FPW_EUNSUPPORTED, "weights beyond the wide format");
+  if (p) fpw_plan_destroy(p);
+  Batch tiny = weight_batch({0}, 50);
+  tiny.dy[7] = 1e-170;
+  expect(plan_of(tiny, o, &p), FPW_EUNSUPPORTED, "1/dy^2 overflows");
+  tiny.dy[7] = 1e160;
+  expect(plan_of(tiny, o, &p), FPW_EUNSUPPORTED, "1/dy^2 underflows");
+  // a shared-timestamp plan with a wide curve: the matrix-core kernel refuses, auto takes the general one
+  const int C = 5, N = 64, F = 100;
+  std::vector<double> t(N), y((size_t)C * N), dy((size_t)C * N, 0.02), f(F);
+  for (int i = 0; i < N; ++i) t[i] = i * 7.3;
+  for (size_t i = 0; i < y.size(); ++i) y[i] = 0.02 * std::cos(0.7 * (double)i);
+  dy[2 * N + 10] = 2e-6;
+  for (int i = 0; i < F; ++i) f[i] = 0.1 + 0.03 * i;
+  for (int kernel : {0, 2}) {
+    fpw_options_default(&o);
+    o.n_bins = 20;
+    o.shared_kernel = kernel;
+    p = nullptr;
+    fpw_status st = fpw_plan_shared(&p, C, N, t.data(), y.data(), dy.data(), F, f.data(), &o, nullptr);
+    expect(st, kernel == 2 ? FPW_EUNSUPPORTED : FPW_OK, "shared plan with a wide curve");
+    if (!p) continue;
+    ++plans;
+    fpw_plan_info info;
+    expect(fpw_get_plan_info(p, &info), FPW_OK, "info");
+    if (info.kernel != 0 || info.n_wide_curves != 1) {
+      std::printf("FAIL shared plan with a wide curve: kernel %d, %d wide\n", info.kernel, info.n_wide_curves);
+      ++failures;
+    }
+    fpw_plan_destroy(p);
+  }
+}
+
+// Error paths: the n-th allocation, copy, launch or capture fails, for every
+// n up to the calls a plan and a pass make.  A failed call returns its status
+// (FPW_ENOMEM for allocations, FPW_EHIP otherwise; a failed capture only
+// turns the graph off), leaves no plan behind, sets a message, and leaks
+// nothing (AddressSanitizer's leak check runs at exit).
+void failure_paths() {
+  struct Case {
+    const char* what;
+    int kind;
+  };
+  const Batch small = make_batch(6, 300);
+  const Batch mixed = weight_batch({0, 1, 0}, 300);
+  fpw_options o;
+  for (int plan_kind = 0; plan_kind < 4; ++plan_kind) {
+    fpw_options_default(&o);
+    o.n_bins = 20;
+    o.topk = 3;
+    if (plan_kind == 1) o.baseline_terms = 2;
+    if (plan_kind == 2) o.fuse_prepare = 1;
+    const Batch& b = plan_kind == 3 ? mixed : small;
+    for (const Case& cs : {Case{"alloc", 1}, Case{"copy", 2}, Case{"launch", 3}, Case{"capture", 4}}) {
+      for (long n = 1; n < 400; ++n) {
+        stub_fail(cs.kind, n);
+        fpw_plan_t p = nullptr;
+        fpw_status st = plan_of(b, o, &p);
+        const bool in_plan = stub_failed() != 0;
+        if (in_plan) {
+          const fpw_status want = cs.kind == 1 ? FPW_ENOMEM : (cs.kind == 4 ? FPW_OK : FPW_EHIP);
+          if (cs.kind != 4) {
+            expect(st, want, cs.what);
+            if (p != nullptr || fpw_last_error()[0] == 0) {
+              std::printf("FAIL %s %ld in plan: plan left behind or no message\n", cs.what, n);
+              ++failures;
+            }
+          }
+          if (p) fpw_plan_destroy(p);
+          continue;
+        }
+        expect(st, FPW_OK, "plan before the failure");
+        if (!p) break;
+        // the failure falls in the passes: each pass either succeeds or reports it
+        auto S = buf<float>(6 * 300);
+        auto idx = buf<int32_t>(6 * 3);
+        auto val = buf<float>(6 * 3);
+        bool any = false;
+        for (int r = 0; r < 3; ++r) {
+          const bool before = stub_failed() != 0;
+          st = fpw_eval_batch(p, S.data(), idx.data(), val.data(), nullptr);
+          const bool now = stub_failed() != 0 && !before;
+          if (now && cs.kind != 4 && st == FPW_OK) {
+            // a failure while capturing is retried as direct launches
+          } else if (now && cs.kind != 4) {
+            expect(st, cs.kind == 1 ? FPW_ENOMEM : FPW_EHIP, cs.what);
+            if (fpw_last_error()[0] == 0) {
+              std::printf("FAIL %s %ld in a pass: no message\n", cs.what, n);
+              ++failures;
+            }
+          } else {
+            expect(st, FPW_OK, "pass");
+          }
+          any = any || now;
+        }
+        fpw_plan_destroy(p);
+        if (!any) break;  // n is past every call a plan and its passes make
+      }
+    }
+  }
+  stub_fail(0, 0);
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
+  sum_formats();
+  failure_paths();
   const Batch b = make_batch(10, 477);
   fpw_options o;
   // general and baseline plans over bin counts, waves per histogram and point sources

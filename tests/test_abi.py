@@ -291,3 +291,66 @@ def test_every_registered_kernel_exists_in_the_device_code(tmp_path):
         defined |= {line.split()[-1] for line in syms.splitlines() if " FUNC " in line}
     missing = sorted(registered - defined)
     assert not missing, f"{len(missing)} registered kernels have no device code, e.g. {missing[0]}"
+
+
+# ---------------------------------------------------------------- per-bin sum formats (host-side routing)
+def _weights_batch(kind, n=400, C=3):
+    rng = np.random.default_rng(7)
+    t = np.concatenate([np.sort(rng.uniform(0, 1000, n)) for _ in range(C)])
+    if kind == "ordinary":
+        dy = 0.02 * np.exp(0.5 * rng.standard_normal(n * C))
+    elif kind == "dominant":
+        dy = np.full(n * C, 0.02)
+        dy[n // 2] = 1e-6  # curve 0: one point 2e4 times more precise
+    else:  # errors over nine decades in curve 0: beyond the wide format as well
+        dy = np.full(n * C, 0.02)
+        dy[:n] = 10.0 ** rng.uniform(-9.0, 0.0, n)
+    y = dy * rng.standard_normal(n * C)
+    return np.arange(C + 1) * n, t, y, dy, np.linspace(0.1, 5.0, 100)
+
+
+@pytest.mark.parametrize(
+    "kind,opts,expect",
+    [
+        ("dominant", dict(baseline_terms=2), fpw.EUNSUPPORTED),  # the baseline kernel's sums are 32-bit
+        ("dominant", dict(derived_bins=(10,)), fpw.EUNSUPPORTED),  # multi-M reuse needs the narrow words
+        ("dominant", dict(phase="df32"), fpw.EUNSUPPORTED),
+        ("dominant", dict(phase="fp32"), fpw.EUNSUPPORTED),
+        ("dominant", dict(fuse_prepare=1), fpw.EUNSUPPORTED),
+        ("dominant", dict(n_bins=157), fpw.EUNSUPPORTED),  # wide histograms: M <= FPW_MAX_WIDE_BINS
+        ("beyond", {}, fpw.EUNSUPPORTED),
+        ("ordinary", dict(sum_format="wide", baseline_terms=1), fpw.EUNSUPPORTED),
+        ("ordinary", dict(sum_format=2), fpw.EINVAL),
+        # accepted on the host: these reach the device (no GPU here: a HIP error, never an argument error)
+        ("dominant", {}, fpw.EHIP),
+        ("dominant", dict(n_bins=156), fpw.EHIP),
+        ("ordinary", dict(sum_format="wide"), fpw.EHIP),
+        ("ordinary", dict(baseline_terms=2), fpw.EHIP),
+    ],
+)
+def test_sum_formats_routed_on_host(kind, opts, expect):
+    off, t, y, dy, f = _weights_batch(kind)
+    opts = dict(opts)
+    M = opts.pop("n_bins", 20)
+    st, msg = fpw.plan_status(off, t, y, dy, f, M, **opts)
+    if expect == fpw.EHIP and st in (fpw.EHIP, fpw.ENOMEM):
+        return
+    assert st == expect, (st, msg)
+    assert msg
+
+
+@pytest.mark.parametrize("dy_bad", [1e-170, 1e160])
+def test_weights_must_be_finite_normal_doubles(dy_bad):
+    off, t, y, dy, f = _weights_batch("ordinary")
+    dy = dy.copy()
+    dy[5] = dy_bad
+    st, msg = fpw.plan_status(off, t, y, dy, f, 20)
+    assert st == fpw.EUNSUPPORTED and "1/dy^2" in msg
+
+
+def test_shared_plan_with_wide_weights_refuses_the_matrix_kernel():
+    off, t, y, dy, f = _weights_batch("dominant", n=300, C=4)
+    T = t[:300]
+    Y, DY = y.reshape(4, 300), dy.reshape(4, 300)
+    st, msg = fpw.plan_shared_status(T, Y, DY, f, 20, shared_kernel="matrix")
+    assert st == fpw.EUNSUPPORTED and "30-bit" in msg
