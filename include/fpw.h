@@ -329,6 +329,15 @@ fpw_status fpw_debug_bins(fpw_plan_t plan, int32_t phase, int64_t curve, int64_t
 fpw_status fpw_pass_timings(fpw_plan_t plan, float ms[3]);
 
 /*
+ * The part of ms[1] of fpw_pass_timings spent in the wide-format fold kernel
+ * (curves whose bin sums take the wide format, see FPW_SUMS_*), in
+ * milliseconds, from a HIP event recorded between the two fold kernels: ms[1]
+ * minus it is the batched kernel alone.  0 when the pass launched no wide
+ * kernel.  Same conditions as fpw_pass_timings.
+ */
+fpw_status fpw_pass_wide_ms(fpw_plan_t plan, float* ms);
+
+/*
  * Phase entropy of each curve's observation times at given trial frequencies
  * (App. C): H = -sum_m (N_m/N) log(N_m/N) over the plan's n_bins phase bins
  * (N_m observations of the curve in bin m, natural log), with the expectation
@@ -368,6 +377,7 @@ typedef struct {
                              or of the baseline kernel; 0 for the matrix-core kernel */
   int32_t fuse_prepare;   /* 1 if the plan runs the fused pass (see fpw_options) */
   int32_t n_wide_curves;  /* curves whose bin sums take the wide format (see FPW_SUMS_*) */
+  int64_t n_wide_points;  /* their observations (the wide kernel folds n_wide_points * n_freq) */
 } fpw_plan_info;
 
 fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);

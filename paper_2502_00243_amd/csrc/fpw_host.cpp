@@ -136,10 +136,12 @@ struct fpw_plan_s {
   DevBuf bm_rec, bm_z, bm_const, bm_S;
   // fused pass (small plans): prepare fused into the fold kernel, then the merge
   bool fused = false;
-  // profiling events: before prepare, after prepare, after batched, after merge
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // profiling events: before prepare, after prepare, after the fold kernels, after merge, and between
+  // the batched and the wide-format fold kernels
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   bool ev_recorded = false;
   bool ev_merge = false;
+  bool ev_wide = false;
   ~fpw_plan_s() {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -818,6 +820,7 @@ fpw::FusedArgs fused_args(const fpw_plan_s* p) {
 
 // One full pass: prepare, fold/bin/accumulate/reduce (+ fused peaks), merge.
 fpw_status enqueue_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipStream_t s) {
+  p->ev_wide = false;
   if (p->mfma) return enqueue_shared_pass(p, S, idx, val, s);
   if (p->bm) return enqueue_bm_pass(p, S, idx, val, s);
   const bool prof = p->opt.profile != 0;
@@ -839,6 +842,8 @@ fpw_status enqueue_pass(fpw_plan_s* p, float* S, int32_t* idx, float* val, hipSt
     FPW_HIP(fpw::launch_batched(batch_args(p, S, p->items, p->n_items), p->shape, p->opt.phase,
                                 launch_groups(p, p->n_items), p->lds_bytes, s),
             "batched kernel");
+  p->ev_wide = prof && p->n_items_w > 0;
+  if (p->ev_wide) FPW_HIP(hipEventRecord(p->ev[4], s), "event record");
   if (p->n_items_w > 0)
     FPW_HIP(fpw::launch_wide(wide_args(p, S), p->opt.phase, p->wide_share, p->wide_grid, s), "wide kernel");
   if (prof) FPW_HIP(hipEventRecord(p->ev[2], s), "event record");
@@ -1440,6 +1445,18 @@ fpw_status fpw_pass_timings(fpw_plan_t p, float ms[3]) {
   return FPW_OK;
 }
 
+fpw_status fpw_pass_wide_ms(fpw_plan_t p, float* ms) {
+  g_err.clear();
+  if (!p || !ms) return fail(FPW_EINVAL, "NULL argument");
+  if (!p->opt.profile) return fail(FPW_ESTATE, "plan was made with profile = 0");
+  if (!p->ev_recorded) return fail(FPW_ESTATE, "no fpw_eval_batch has run on this plan");
+  *ms = 0.f;
+  if (!p->ev_wide) return FPW_OK;
+  FPW_HIP(hipEventSynchronize(p->ev[2]), "event sync");
+  FPW_HIP(hipEventElapsedTime(ms, p->ev[4], p->ev[2]), "event time");
+  return FPW_OK;
+}
+
 fpw_status fpw_phase_entropy(fpw_plan_t p, const int32_t* freq_idx_dev, int32_t k, float* H_dev, float* E_dev,
                              float* V_dev, void* stream) {
   g_err.clear();
@@ -1490,6 +1507,7 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   info->grid_groups = p->grid_groups;
   info->work_items = p->n_items + p->n_items_w;
   info->n_wide_curves = (int32_t)p->n_wide;
+  info->n_wide_points = p->n_wide > 0 ? p->h_offw[(size_t)p->n_curves] : 0;
   info->lds_bytes = (int32_t)p->lds_bytes;
   info->tuned = p->tuned ? 1 : 0;
   info->point_source = p->shape.point_source + 1;

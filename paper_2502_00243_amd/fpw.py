@@ -88,6 +88,7 @@ class PlanInfo(ctypes.Structure):
         ("hist_share", ctypes.c_int32),
         ("fuse_prepare", ctypes.c_int32),
         ("n_wide_curves", ctypes.c_int32),
+        ("n_wide_points", ctypes.c_int64),
     ]
 
 
@@ -135,6 +136,8 @@ def load(path: str = LIB_PATH):
     lib.fpw_debug_bins.restype = ctypes.c_int
     lib.fpw_pass_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
     lib.fpw_pass_timings.restype = ctypes.c_int
+    lib.fpw_pass_wide_ms.argtypes = [P, ctypes.POINTER(ctypes.c_float)]
+    lib.fpw_pass_wide_ms.restype = ctypes.c_int
     lib.fpw_phase_entropy.argtypes = [P, P, i32, P, P, P, P]
     lib.fpw_phase_entropy.restype = ctypes.c_int
     lib.fpw_variant.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -331,10 +334,17 @@ class Plan:
         return out
 
     def timings(self):
-        """(prepare, batched, merge) kernel milliseconds of the last eval (plan made with profile=True)."""
+        """(prepare, fold, merge) kernel milliseconds of the last eval (plan made with profile=True); the fold
+        time covers the batched kernel and, with wide-format curves, the wide kernel (see wide_ms)."""
         ms = (ctypes.c_float * 3)()
         _check(load().fpw_pass_timings(self._h, ms))
         return float(ms[0]), float(ms[1]), float(ms[2])
+
+    def wide_ms(self):
+        """Milliseconds of the fold time of the last eval spent in the wide-format kernel (0 if none ran)."""
+        ms = ctypes.c_float()
+        _check(load().fpw_pass_wide_ms(self._h, ctypes.byref(ms)))
+        return float(ms.value)
 
     def phase_entropy(self, freq_idx, stream=None):
         """(H, E, V) of the phase occupancy at freq_idx (device int32 [n_curves, k]), App. C."""

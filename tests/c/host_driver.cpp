@@ -67,8 +67,9 @@ void passes(fpw_plan_t p, const fpw_options& o, int64_t C, int64_t F, int nvar) 
            "eval");
   if (o.topk) expect(fpw_eval_batch(p, nullptr, idx.data(), val.data(), nullptr), FPW_OK, "eval without S");
   if (o.profile) {
-    float ms[3];
+    float ms[3], wide = -1.f;
     expect(fpw_pass_timings(p, ms), FPW_OK, "timings");
+    expect(fpw_pass_wide_ms(p, &wide), FPW_OK, "wide-kernel time");
   }
 }
 
