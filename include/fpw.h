@@ -382,6 +382,37 @@ typedef struct {
 
 fpw_status fpw_get_plan_info(fpw_plan_t plan, fpw_plan_info* info);
 
+/*
+ * One periodogram pass with no plan and no allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Inputs and outputs are the caller's
+ * DEVICE buffers, with the layouts of fpw_plan and fpw_eval_batch:
+ *   offsets      int64 [n_curves + 1]; t, y, dy float64 [n_points]; freqs float64 [n_freq]
+ *   S_dev        float32 [n_curves * n_freq] or NULL
+ *   topk_idx, topk_val  int32 / float32 [n_curves * opt.topk] or both NULL
+ * Every other buffer the pass needs lives in one static device array of 16 MiB
+ * per GPU (kept until the process ends): with topk k it must hold about
+ * 32 n_points + 44 n_curves + (36 + 8k) n_items bytes (n_items = n_curves *
+ * chunks per curve, about one per workgroup the GPU holds at once; 256-byte
+ * alignment of each region on top), else FPW_EUNSUPPORTED.
+ * The sums take the wide format (see FPW_SUMS_*) and the phase is folded in
+ * the listing order (FPW_PHASE_FP64 and FPW_PHASE_FP64_LISTING give the same
+ * exact-floor bins here), so S has the plan's definition and tolerance; a curve
+ * whose weights exceed the wide format's bound gets S = NaN and no peaks.
+ * Options: n_bins <= FPW_MAX_WIDE_BINS, center, tref_mode, t_ref, inv_alpha2,
+ * stat_scale, topk; FPW_EUNSUPPORTED for the FP32-based phase modes, derived
+ * bin counts, baseline terms, autotune and launch-shape overrides.
+ * The argument checks cover sizes, pointers and options only (FPW_EINVAL,
+ * before any HIP call): the values on the device are not read on the host,
+ * so they must meet fpw_plan's conditions for S to be meaningful (no device
+ * access leaves the buffers whatever they hold).  Calls that overlap on one
+ * GPU race on the static array: serialise them (one stream, or synchronise).
+ */
+fpw_status fpw_eval_static(int64_t n_curves, const int64_t* offsets, int64_t n_points, const double* t,
+                           const double* y, const double* dy, int64_t n_freq, const double* freqs,
+                           const fpw_options* opt, float* S_dev, int32_t* topk_idx, float* topk_val,
+                           void* stream);
+
 /* Releases the plan and its device memory.  NULL is a no-op. */
 void fpw_plan_destroy(fpw_plan_t plan);
 

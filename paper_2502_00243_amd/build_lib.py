@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfpw.so")
 ARCH = "gfx950"
 
-SOURCES = ["fpw_batched.hip", "fpw_aux.hip", "fpw_shared.hip", "fpw_baseline.hip", "fpw_host.cpp"]
+SOURCES = ["fpw_batched.hip", "fpw_aux.hip", "fpw_shared.hip", "fpw_baseline.hip", "fpw_static.hip", "fpw_host.cpp"]
 
 # Device code: no automatic fma contraction (the folds spell out every fused
 # operation they want) and no packed-FP32 instructions.

@@ -1537,6 +1537,84 @@ fpw_status fpw_get_plan_info(fpw_plan_t p, fpw_plan_info* info) {
   return FPW_OK;
 }
 
+fpw_status fpw_eval_static(int64_t n_curves, const int64_t* offsets, int64_t n_points, const double* t,
+                           const double* y, const double* dy, int64_t n_freq, const double* freqs,
+                           const fpw_options* opt, float* S_dev, int32_t* topk_idx, float* topk_val, void* stream) {
+  g_err.clear();
+  fpw_options o;
+  fpw_options_default(&o);
+  if (opt) o = *opt;
+  fpw_status st = check_options(o);
+  if (st != FPW_OK) return st;
+  if (!offsets || !t || !y || !dy || !freqs) return fail(FPW_EINVAL, "null input pointer");
+  if (n_curves < 1) return fail(FPW_EINVAL, "n_curves must be >= 1");
+  if (n_curves > INT32_MAX - 1) return fail(FPW_EUNSUPPORTED, "n_curves too large");
+  if (n_points < n_curves) return fail(FPW_EINVAL, "n_points must be >= n_curves (every curve has a point)");
+  if (n_freq < 1) return fail(FPW_EINVAL, "n_freq must be >= 1");
+  if (n_freq >= INT32_MAX) return fail(FPW_EUNSUPPORTED, "n_freq must be < 2^31");
+  if ((topk_idx == nullptr) != (topk_val == nullptr))
+    return fail(FPW_EINVAL, "topk_idx and topk_val must both be set or both NULL");
+  if (topk_idx && o.topk <= 0) return fail(FPW_EINVAL, "peaks asked for with topk = 0");
+  if (!topk_idx && !S_dev) return fail(FPW_EINVAL, "no output: S_dev and topk_idx are NULL");
+  if (o.topk > n_freq) return fail(FPW_EINVAL, "topk %d exceeds n_freq %lld", o.topk, (long long)n_freq);
+  if (o.phase != FPW_PHASE_FP64 && o.phase != FPW_PHASE_FP64_LISTING)
+    return fail(FPW_EUNSUPPORTED, "fpw_eval_static folds in FP64 (listing order)");
+  if (o.derived_bins[0] != 0 || o.baseline_terms != 0 || o.autotune || o.freqs_per_lane || o.waves_per_group ||
+      o.chunk_freqs || o.point_source || o.hist_share || o.fuse_prepare == 1)
+    return fail(FPW_EUNSUPPORTED, "fpw_eval_static takes no derived bin counts, baseline terms, autotune or "
+                "launch-shape overrides");
+  if (o.n_bins > FPW_MAX_WIDE_BINS)
+    return fail(FPW_EUNSUPPORTED, "fpw_eval_static: n_bins %d > FPW_MAX_WIDE_BINS = %d", o.n_bins, FPW_MAX_WIDE_BINS);
+  const int topk = topk_idx ? o.topk : 0;
+  // ---- checks done: from here on HIP queries (none allocates)
+  int dev = 0, n_cu = 0, per_cu = 0;
+  FPW_HIP(hipGetDevice(&dev), "hipGetDevice");
+  FPW_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+  const int M = o.n_bins;
+  const int share = M < 8 ? 1 : (M < 16 ? 2 : 4);
+  FPW_HIP(fpw::wide_groups_per_cu(FPW_PHASE_FP64_LISTING, topk, M, share, &per_cu), "wide kernel occupancy");
+  const int64_t consumers = (int64_t)std::max(1, per_cu) * n_cu;
+  // about one item per workgroup, in whole sweeps of 64 frequencies
+  int64_t chunk = (n_freq * n_curves + consumers - 1) / consumers;
+  chunk = std::max<int64_t>(kWave, ((chunk + kWave - 1) / kWave) * kWave);
+  chunk = std::min<int64_t>(chunk, std::max<int64_t>(kWave, ((n_freq + kWave - 1) / kWave) * kWave));
+  int64_t per_curve = (n_freq + chunk - 1) / chunk;
+  if (per_curve > 1 && n_freq - (per_curve - 1) * chunk == 1) --per_curve;  // a lone trailing frequency joins
+  const int64_t n_items = per_curve * n_curves;
+  fpw::StaticLayout lay;
+  if (n_items > INT32_MAX || !fpw::static_layout(n_curves, n_points, n_items, topk, &lay))
+    return fail(FPW_EUNSUPPORTED,
+                "fpw_eval_static: %lld curves, %lld points and %lld work items need %zu bytes of its %zu-byte static "
+                "scratch", (long long)n_curves, (long long)n_points, (long long)n_items, lay.total,
+                fpw::kStaticScratchBytes);
+  fpw::StaticPass sp{};
+  sp.offsets = offsets;
+  sp.t = t;
+  sp.y = y;
+  sp.dy = dy;
+  sp.freqs = freqs;
+  sp.n_curves = n_curves;
+  sp.n_points = n_points;
+  sp.n_items = n_items;
+  sp.center = o.center;
+  sp.tref_mode = o.tref_mode;
+  sp.t_ref = o.t_ref;
+  sp.inv_alpha2 = o.inv_alpha2;
+  sp.stat_scale = o.stat_scale == FPW_STAT_LISTING_HALF ? 0.5 : 1.0;
+  sp.n_freq = (int32_t)n_freq;
+  sp.n_bins = M;
+  sp.topk = topk;
+  sp.chunk = (int32_t)chunk;
+  sp.per_curve = (int32_t)per_curve;
+  sp.share = share;
+  sp.grid = (int)std::min<int64_t>(consumers, n_items);
+  sp.S = S_dev;
+  sp.idx = topk_idx;
+  sp.val = topk_val;
+  FPW_HIP(fpw::launch_static_pass(sp, (hipStream_t)stream), "static pass");
+  return FPW_OK;
+}
+
 void fpw_plan_destroy(fpw_plan_t p) { delete p; }
 
 }  // extern "C"

@@ -288,6 +288,38 @@ hipError_t launch_bm(const BmArgs& a, int phase, int grid, hipStream_t s);
 hipError_t bm_groups_per_cu(int phase, int n_bins, int n_terms, int share, int source, int* out);
 size_t bm_lds_bytes(int n_bins, int n_terms, int share);
 
+// The pass that allocates nothing (fpw_eval_static): its scratch is one
+// file-scope device array of kStaticScratchBytes per GPU.
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+
+// Byte offsets of one call's regions in that array.
+struct StaticLayout {
+  size_t offs, recw, wc, items, slot_k0, curve_slot, cand_val, cand_idx, edge, queue, total;
+};
+
+struct StaticPass {
+  const int64_t* offsets;  // caller's device arrays
+  const double* t;
+  const double* y;
+  const double* dy;
+  const double* freqs;
+  int64_t n_curves, n_points, n_items;
+  int center, tref_mode;
+  double t_ref, inv_alpha2, stat_scale;
+  int32_t n_freq, n_bins, topk;
+  int32_t chunk, per_curve;  // frequencies per work item, items per curve
+  int share, grid;           // wide-kernel waves per histogram and workgroups
+  float* S;                  // outputs (device), S may be null, idx/val null when topk == 0
+  int32_t* idx;
+  float* val;
+};
+
+// False when the regions of a call do not fit the array.
+bool static_layout(int64_t n_curves, int64_t n_points, int64_t n_items, int topk, StaticLayout* l);
+// Prepare, wide-format fold and peak merge, with every buffer beyond the
+// caller's in the static array (hipGetSymbolAddress once per device).
+hipError_t launch_static_pass(const StaticPass& s, hipStream_t st);
+
 // Launch shapes of the batched kernel.
 struct Shape {
   int freqs_per_lane;   // 1 or 2

@@ -144,6 +144,8 @@ def load(path: str = LIB_PATH):
     lib.fpw_variant.restype = ctypes.c_int
     lib.fpw_get_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
     lib.fpw_get_plan_info.restype = ctypes.c_int
+    lib.fpw_eval_static.argtypes = [i64, P, i64, P, P, P, i64, P, ctypes.POINTER(Options), P, P, P, P]
+    lib.fpw_eval_static.restype = ctypes.c_int
     lib.fpw_plan_destroy.argtypes = [P]
     lib.fpw_plan_destroy.restype = None
     lib.fpw_last_error.argtypes = []
@@ -389,6 +391,34 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def eval_static(offsets, t, y, dy, freqs, n_bins, store_s=True, stream=None, S_out=None, idx_out=None, val_out=None,
+                **opts):
+    """fpw_eval_static: one pass with no plan and no allocation by the library.
+
+    offsets (int64), t, y, dy, freqs (float64) are device tensors; returns (S [n_curves, n_freq] or None,
+    idx, val) as device tensors (peaks when opts has topk > 0).  Outputs may be passed preallocated."""
+    import torch
+
+    for name, a, dt in (("offsets", offsets, torch.int64), ("t", t, torch.float64), ("y", y, torch.float64),
+                        ("dy", dy, torch.float64), ("freqs", freqs, torch.float64)):
+        if not (a.is_cuda and a.dtype == dt and a.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dt} device tensor")
+    n_curves, n_points, n_freq = offsets.numel() - 1, t.numel(), freqs.numel()
+    if y.numel() != n_points or dy.numel() != n_points:
+        raise ValueError("t, y and dy must have the same length")
+    o = make_options(n_bins, **opts)
+    S = S_out if S_out is not None else (
+        torch.empty((n_curves, n_freq), dtype=torch.float32, device="cuda") if store_s else None)
+    idx = val = None
+    if o.topk > 0:
+        idx = idx_out if idx_out is not None else torch.empty((n_curves, o.topk), dtype=torch.int32, device="cuda")
+        val = val_out if val_out is not None else torch.empty((n_curves, o.topk), dtype=torch.float32, device="cuda")
+    addr = lambda x: ctypes.c_void_p(x.data_ptr() if x is not None else 0)  # noqa: E731
+    _check(load().fpw_eval_static(n_curves, addr(offsets), n_points, addr(t), addr(y), addr(dy), n_freq, addr(freqs),
+                                  ctypes.byref(o), addr(S), addr(idx), addr(val), _stream_handle(stream)))
+    return S, idx, val
 
 
 def plan_status(offsets, t, y, dy, freqs, n_bins, **opts):

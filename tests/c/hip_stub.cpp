@@ -99,6 +99,21 @@ hipError_t launch_wide(const BatchArgs& a, int phase, int share, int grid, hipSt
 }
 size_t wide_lds_bytes(int n_bins, int share) { return (size_t)(n_bins + 1) * 1024 + (share > 1 ? 2064 : 0); }
 hipError_t wide_groups_per_cu(int, int, int, int, int* out) { *out = 2; return hipSuccess; }
+bool static_layout(int64_t n_curves, int64_t n_points, int64_t n_items, int topk, StaticLayout* l) {
+  *l = StaticLayout{};
+  l->total = (size_t)(32 * n_points + 44 * n_curves + (36 + 8 * topk) * n_items + 2560);
+  return l->total <= kStaticScratchBytes;
+}
+hipError_t launch_static_pass(const StaticPass& s, hipStream_t) {
+  // sizes and outputs as the entry point promises; the layout fits
+  StaticLayout l;
+  if (s.n_items < 1 || s.n_curves < 1 || s.n_points < s.n_curves || s.chunk < 64 || s.chunk % 64 != 0 ||
+      s.per_curve < 1 || s.n_items != s.per_curve * s.n_curves || (int64_t)(s.per_curve - 1) * s.chunk >= s.n_freq ||
+      s.grid < 1 || s.grid > s.n_items || (s.topk > 0) != (s.idx != nullptr) || (s.S == nullptr && s.idx == nullptr) ||
+      !static_layout(s.n_curves, s.n_points, s.n_items, s.topk, &l))
+    return hipErrorInvalidValue;
+  return fail_now(3) ? hipErrorLaunchFailure : hipSuccess;
+}
 size_t fused_lds_bytes(int n_bins) { return (size_t)(n_bins + 1) * 512 + 1024; }
 int fused_waves() { return 4; }
 hipError_t launch_topk(const TopkArgs&, hipStream_t) { return fail_now(3) ? hipErrorLaunchFailure : hipSuccess; }

@@ -8,6 +8,7 @@
 // with the HIP stand-ins in hip_stub.cpp under the sanitizers.  argv[1]: a
 // scratch path for the autotune cache.  Prints "failures: 0" when every call
 // returned what it should.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -342,9 +343,70 @@ void failure_paths() {
   stub_fail(0, 0);
 }
 
+// fpw_eval_static: argument checks, shapes over sizes, refusal beyond its scratch.
+void static_pass() {
+  fpw_options o;
+  for (int nf : {1, 2, 64, 65, 129, 10000})
+    for (int M : {1, 10, 20, 156})
+      for (int k : {0, 5}) {
+        const Batch b = make_batch(7, nf);
+        fpw_options_default(&o);
+        o.n_bins = M;
+        o.topk = std::min(k, nf);
+        auto S = buf<float>((size_t)7 * nf);
+        auto idx = buf<int32_t>(7 * 5);
+        auto val = buf<float>(7 * 5);
+        expect(fpw_eval_static(7, b.off.data(), b.off[7], b.t.data(), b.y.data(), b.dy.data(), nf, b.f.data(), &o,
+                               S.data(), o.topk ? idx.data() : nullptr, o.topk ? val.data() : nullptr, nullptr),
+               FPW_OK, "static pass");
+      }
+  const Batch b = make_batch(7, 300);
+  auto S = buf<float>(7 * 300);
+  auto idx = buf<int32_t>(7 * 5);
+  auto val = buf<float>(7 * 5);
+  struct Bad {
+    const char* what;
+    fpw_status want;
+    int phase, derived, terms, share, M;
+    bool no_out, idx_only, npts_short;
+  };
+  for (const Bad& c : {Bad{"df32", FPW_EUNSUPPORTED, 2, 0, 0, 0, 20, false, false, false},
+                       Bad{"derived", FPW_EUNSUPPORTED, 0, 10, 0, 0, 20, false, false, false},
+                       Bad{"baseline", FPW_EUNSUPPORTED, 0, 0, 1, 0, 20, false, false, false},
+                       Bad{"share override", FPW_EUNSUPPORTED, 0, 0, 0, 2, 20, false, false, false},
+                       Bad{"M above wide max", FPW_EUNSUPPORTED, 0, 0, 0, 0, 157, false, false, false},
+                       Bad{"no output", FPW_EINVAL, 0, 0, 0, 0, 20, true, false, false},
+                       Bad{"idx without val", FPW_EINVAL, 0, 0, 0, 0, 20, false, true, false},
+                       Bad{"fewer points than curves", FPW_EINVAL, 0, 0, 0, 0, 20, false, false, true}}) {
+    fpw_options_default(&o);
+    o.n_bins = c.M;
+    o.topk = 3;
+    o.phase = c.phase;
+    o.derived_bins[0] = c.derived;
+    o.baseline_terms = c.terms;
+    o.hist_share = c.share;
+    expect(fpw_eval_static(7, b.off.data(), c.npts_short ? 6 : b.off[7], b.t.data(), b.y.data(), b.dy.data(), 300,
+                           b.f.data(), &o, c.no_out ? nullptr : S.data(), c.no_out ? nullptr : idx.data(),
+                           c.no_out || c.idx_only ? nullptr : val.data(), nullptr),
+           c.want, c.what);
+  }
+  // beyond the static scratch: 1e6 points need 32 MB of records
+  Batch big;
+  big.off = {0, 1000000};
+  big.t.assign(1000000, 1.0);
+  big.y.assign(1000000, 0.0);
+  big.dy.assign(1000000, 0.1);
+  big.f.assign(100, 1.0);
+  fpw_options_default(&o);
+  expect(fpw_eval_static(1, big.off.data(), 1000000, big.t.data(), big.y.data(), big.dy.data(), 100, big.f.data(),
+                         &o, S.data(), nullptr, nullptr, nullptr),
+         FPW_EUNSUPPORTED, "beyond the static scratch");
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
+  static_pass();
   sum_formats();
   failure_paths();
   const Batch b = make_batch(10, 477);

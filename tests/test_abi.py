@@ -264,10 +264,10 @@ def _llvm_tool(name):
 
 
 def test_every_registered_kernel_exists_in_the_device_code(tmp_path):
-    """The host side registers each kernel under its mangled device name; the gfx950 code objects
-    must define every one of them, or the runtime cannot load the library's kernels.  (Host and
-    device compilations number unnamed types independently, so a kernel signature that mentions
-    one can mangle differently on the two sides.)"""
+    """The host side registers each kernel (and device variable) under its mangled device name; the
+    gfx950 code objects must define every one of them, or the runtime cannot load the library's
+    kernels.  (Host and device compilations number unnamed types independently, so a kernel
+    signature that mentions one can mangle differently on the two sides.)"""
     objcopy, readelf, bundler = _llvm_tool("llvm-objcopy"), _llvm_tool("llvm-readelf"), _llvm_tool("clang-offload-bundler")
     rodata, fatbin = tmp_path / "rodata.bin", tmp_path / "fatbin.bin"
     subprocess.run([objcopy, "-O", "binary", "--only-section=.rodata", LIB, str(rodata)], check=True)
@@ -288,7 +288,7 @@ def test_every_registered_kernel_exists_in_the_device_code(tmp_path):
         subprocess.run([bundler, "--unbundle", "--type=o", f"--input={part}", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
                         f"--output={code}"], check=True)
         syms = subprocess.run([readelf, "--dyn-syms", "-W", str(code)], check=True, capture_output=True, text=True).stdout
-        defined |= {line.split()[-1] for line in syms.splitlines() if " FUNC " in line}
+        defined |= {line.split()[-1] for line in syms.splitlines() if " FUNC " in line or " OBJECT " in line}
     missing = sorted(registered - defined)
     assert not missing, f"{len(missing)} registered kernels have no device code, e.g. {missing[0]}"
 
