@@ -179,17 +179,78 @@ __device__ __forceinline__ void accumulate(const Src& src, int n, const Folder<P
   }
 }
 
+// One derived variant (k fine bins per coarse bin, the first coarse bin
+// starting at fine bin o; Sec. 3.4) from prefix slots.  The slots are split
+// into R consecutive ranges, range r = slots lo[r] .. lo[r+1]-1 (lo[R] = M);
+// a slot x that a window reads holds L(x) = F(lo[r]) + ... + F(x) for its
+// range r, base[r] = F(0) + ... + F(lo[r] - 1), and base[R] is the total.
+// The windows are taken in order, the one that wraps around the end last;
+// each window's packed sum is the difference of two prefixes (exact in
+// 64-bit wrap-around arithmetic), and a range's base enters once per range,
+// not once per window.  Slots past a range's last window are read in the
+// batches of four but not used.
+template <int R>
+__device__ __forceinline__ float derived_sum(const uint64_t* h, int M, int k, int o, const int (&lo)[R + 1],
+                                             const uint64_t (&base)[R + 1], float ia2q) {
+  // F(0) + ... + F(o - 1), the prefix before the first window (0 when o == 0)
+  uint64_t start = 0;
+  if (o > 0) {
+    uint64_t b = base[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r)
+      if (o - 1 >= lo[r]) b = base[r];  // the last range starting at or before o - 1 holds it
+    start = b + h[(o - 1) * kWave];
+  }
+  uint64_t prev_p = start;  // prefix through the last slot of the previous window
+  int e = o + k - 1;        // last slot of the next window
+  float out = 0.f;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int hi = lo[r + 1];
+    if (e >= hi) continue;
+    uint64_t prev = prev_p - base[r];
+    while (e < hi) {
+      uint64_t pe[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pe[q] = h[min(e + q * k, M) * kWave];
+      int next = e;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (e + q * k < hi) {
+          out = add_bin_term(out, pe[q] - prev, ia2q);
+          prev = pe[q];
+          next = e + (q + 1) * k;
+        }
+      }
+      e = next;
+    }
+    prev_p = prev + base[r];
+  }
+  if (o > 0) out = add_bin_term(out, base[R] - prev_p + start, ia2q);  // the window that wraps around
+  return out;
+}
+
+// Clears the prefix slots (need bits) in [lo, hi).
+__device__ __forceinline__ void clear_need_range(uint64_t* h, int lo, int hi, const Variants& vs) {
+  for (int w = lo >> 5; w * 32 < hi; ++w) {
+    uint32_t bits = vs.need[w];
+    while (bits) {
+      const int m = w * 32 + __builtin_ctz(bits);
+      bits &= bits - 1;
+      if (m >= lo && m < hi) h[m * kWave] = 0;
+    }
+  }
+}
+
 // Reduces one lane's fine histogram for every variant: variant v sums k[v]
 // consecutive fine bins (from fine bin o[v], cyclically) into each coarse
 // bin, exactly, then adds the Eq. 1 terms.
 //  1. One pass over the fine bins in order, read and cleared eight at a time:
 //     variant 0 (the fine bins themselves) takes its terms directly, and the
-//     running prefix P(m+1) = F(0) + ... + F(m) is written back only to the
-//     slots some derived variant reads (its window ends).
-//  2. Each derived variant forms the coarse sum of window [s, e) as
-//     P(e) - P(s), with the prefix extended periodically, P(M + x) =
-//     P(M) + P(x), for the window that wraps around the end.  The last
-//     variant clears the slots it reads; a final pass clears the others.
+//     running prefix F(0) + ... + F(m) is written back only to the slots
+//     some derived variant reads.
+//  2. Each derived variant walks its windows (derived_sum, one range); then
+//     the prefix slots are cleared.
 template <int PH, int NV>
 __device__ __forceinline__ void reduce_variants(uint64_t* h, int M, float ia2q, const Variants& vs, float (&out)[NV]) {
   const uint64_t wrap = take_wrap_slot<PH>(h, M);
@@ -216,43 +277,12 @@ __device__ __forceinline__ void reduce_variants(uint64_t* h, int M, float ia2q, 
       }
     }
   }
-  const uint64_t total = run;  // P(M)
   out[0] = fine_parts + fine;
+  const int lo[2] = {0, M};
+  const uint64_t base[2] = {0, run};
 #pragma unroll
-  for (int v = 1; v < NV; ++v) {
-    out[v] = 0.f;
-    if (v < vs.n) {
-      const bool clears = v == vs.n - 1;
-      const int k = vs.k[v], o = vs.o[v], mv = M / k;
-      uint64_t prev = o == 0 ? (uint64_t)0 : h[(o - 1) * kWave];  // P(o)
-      for (int c0 = 0; c0 < mv; c0 += kReduceBlock) {
-        uint64_t pe[kReduceBlock];
-#pragma unroll
-        for (int q = 0; q < kReduceBlock; ++q) {
-          // end of window c0+q: e = o + (c0+q+1) k, clamped past the last window
-          const int e = min(o + (c0 + q + 1) * k, M + o);
-          const int x = e > M ? e - M : e;  // 1 <= x <= M
-          pe[q] = clears ? lds_take(h + (x - 1) * kWave) : h[(x - 1) * kWave];
-          if (e > M) pe[q] += total;
-        }
-#pragma unroll
-        for (int q = 0; q < kReduceBlock; ++q) {
-          if (c0 + q < mv) {
-            out[v] = add_bin_term(out[v], pe[q] - prev, ia2q);
-            prev = pe[q];
-          }
-        }
-      }
-    }
-  }
-  for (int w = 0; w * 32 < M; ++w) {
-    uint32_t bits = vs.rest[w];
-    while (bits) {
-      const int b = __builtin_ctz(bits);
-      bits &= bits - 1;
-      h[(w * 32 + b) * kWave] = 0;
-    }
-  }
+  for (int v = 1; v < NV; ++v) out[v] = v < vs.n ? derived_sum<1>(h, M, vs.k[v], vs.o[v], lo, base, ia2q) : 0.f;
+  clear_need_range(h, 0, M, vs);
 }
 
 // The part sums of reduce_hist that one wave of a histogram shared by SH
@@ -289,10 +319,11 @@ __device__ __forceinline__ void reduce_parts(uint64_t* h, int M, int wave, float
 //    of its own range (from the range start) back to the slots a derived
 //    variant reads, and its range total to totals[wave].
 //  Phase 2 (after a barrier): the wave computes the derived variants it owns
-//    (v = 1, 2, ... go to waves SH-1, SH-2, ..., cyclically, so the lead gets
-//    the fewest); P(x) is the prefix at slot x-1 plus the totals of the waves
-//    before that slot's owner.  Reads are plain: a slot may serve variants of
-//    several waves.  Results go to var_sums[v].
+//    (Variants::own, balanced on the host) with derived_sum over the SH
+//    ranges, the bases being sums of the range totals.  Reads are plain: a
+//    slot may serve variants of several waves.  The sums stay in the owner's
+//    registers: the owner also stores those variants' S and keeps their
+//    peaks.
 //  Then (after a barrier) each wave clears the prefix slots of its range.
 template <int PH, int SH>
 __device__ __forceinline__ void variants_phase1(uint64_t* h, int M, int wave, float ia2q, const Variants& vs,
@@ -325,56 +356,27 @@ __device__ __forceinline__ void variants_phase1(uint64_t* h, int M, int wave, fl
   totals[wave * kWave + lane] = run;
 }
 
-template <int SH>
-__device__ __forceinline__ int wave_of_variant(int v) {
-  return (SH - 1) - (v - 1) % SH;
-}
+// Derived variants per wave (at most): the kernel's register slots for them.
+template <int NV, int SH>
+constexpr int kOwned = (NV - 1 + SH - 1) / SH;
 
 template <int NV, int SH>
 __device__ __forceinline__ void variants_phase2(const uint64_t* h, int M, int wave, float ia2q, const Variants& vs,
-                                                const uint64_t* totals, float* var_sums, int lane) {
+                                                const uint64_t* totals, float (&own)[kOwned<NV, SH>], int lane) {
   const int nb = (M + kReduceBlock - 1) / kReduceBlock;
-  // first block of the ranges of waves 1..3, and the prefix offset of waves 1..3
-  // (waves beyond SH-1 start past the last block and are never chosen)
-  const int wb1 = part_block(1 * kSumParts / SH, nb);
-  const int wb2 = SH > 2 ? part_block(2 * kSumParts / SH, nb) : nb;
-  const int wb3 = SH > 3 ? part_block(3 * kSumParts / SH, nb) : nb;
-  const uint64_t off1 = totals[lane];
-  const uint64_t off2 = SH > 2 ? off1 + totals[kWave + lane] : (uint64_t)0;
-  const uint64_t off3 = SH > 3 ? off2 + totals[2 * kWave + lane] : (uint64_t)0;
-  const uint64_t total = SH == 2 ? off1 + totals[kWave + lane] : (SH == 3 ? off2 + totals[2 * kWave + lane]
-                                                                          : off3 + totals[3 * kWave + lane]);
-  // P(x), 1 <= x <= M: prefix through slot x-1 (the owner's choice is wave-uniform)
-  auto prefix = [&](int x) -> uint64_t {
-    const int b = (x - 1) / kReduceBlock;
-    const uint64_t o = b >= wb3 ? off3 : (b >= wb2 ? off2 : (b >= wb1 ? off1 : (uint64_t)0));
-    return h[(x - 1) * kWave] + o;
-  };
+  int lo[SH + 1];
+  uint64_t base[SH + 1];
+  lo[0] = 0;
+  base[0] = 0;
 #pragma unroll
-  for (int v = 1; v < NV; ++v) {
-    if (v >= vs.n || wave_of_variant<SH>(v) != wave) continue;
-    const int k = vs.k[v], o = vs.o[v], mv = M / k;
-    uint64_t prev = o == 0 ? (uint64_t)0 : prefix(o);  // P(o)
-    float out = 0.f;
-    for (int c0 = 0; c0 < mv; c0 += kReduceBlock) {
-      uint64_t pe[kReduceBlock];
+  for (int r = 1; r <= SH; ++r) {
+    lo[r] = r < SH ? min(M, part_block(r * kSumParts / SH, nb) * kReduceBlock) : M;
+    base[r] = base[r - 1] + totals[(r - 1) * kWave + lane];
+  }
 #pragma unroll
-      for (int q = 0; q < kReduceBlock; ++q) {
-        // end of window c0+q: e = o + (c0+q+1) k, clamped past the last window
-        const int e = min(o + (c0 + q + 1) * k, M + o);
-        const int x = e > M ? e - M : e;  // 1 <= x <= M
-        pe[q] = prefix(x);
-        if (e > M) pe[q] += total;
-      }
-#pragma unroll
-      for (int q = 0; q < kReduceBlock; ++q) {
-        if (c0 + q < mv) {
-          out = add_bin_term(out, pe[q] - prev, ia2q);
-          prev = pe[q];
-        }
-      }
-    }
-    var_sums[v * kWave + lane] = out;
+  for (int j = 0; j < kOwned<NV, SH>; ++j) {
+    const int v = vs.own[SH == 4][wave][j];
+    own[j] = v == 0 ? 0.f : derived_sum<SH>(h, M, vs.k[v], vs.o[v], lo, base, ia2q);
   }
 }
 
@@ -382,16 +384,8 @@ __device__ __forceinline__ void variants_phase2(const uint64_t* h, int M, int wa
 template <int SH>
 __device__ __forceinline__ void clear_need_slots(uint64_t* h, int M, int wave, const Variants& vs) {
   const int nb = (M + kReduceBlock - 1) / kReduceBlock;
-  const int lo = part_block(wave * kSumParts / SH, nb) * kReduceBlock;
-  const int hi = min(M, part_block((wave + 1) * kSumParts / SH, nb) * kReduceBlock);
-  for (int w = lo >> 5; w * 32 < hi; ++w) {
-    uint32_t bits = vs.need[w];
-    while (bits) {
-      const int m = w * 32 + __builtin_ctz(bits);
-      bits &= bits - 1;
-      if (m >= lo && m < hi) h[m * kWave] = 0;
-    }
-  }
+  clear_need_range(h, part_block(wave * kSumParts / SH, nb) * kReduceBlock,
+                   min(M, part_block((wave + 1) * kSumParts / SH, nb) * kReduceBlock), vs);
 }
 
 // Peak bookkeeping of one periodogram variant along a work item.
@@ -454,8 +448,11 @@ struct PeakState {
 
 // SH > 1: the SH waves of the workgroup work on the same item with one shared
 // histogram; `part` holds the kSumParts part sums of S, and with several
-// variants `totals` the range totals and `var_sums` the derived variants'
-// sums.  Only wave 0 (the lead) stores S and keeps the peaks.
+// variants `totals` the range totals.  With one variant only wave 0 (the
+// lead) stores S and keeps the peaks; with several, each wave stores and
+// keeps the peaks of the derived variants it computed (Variants::own) and
+// the lead those of variant 0, so the work after the last barrier of a
+// sub-tile is spread over the group and each wave holds few peak states.
 // The observations [lo, lo + n) of a curve of n_all that wave `wave` of SH
 // folds (all of them when SH == 1).
 template <int SH>
@@ -474,7 +471,7 @@ __device__ __forceinline__ int slice_size(int wave, int n_all) {
 template <int PH, int FL, int PK, int SRC, int NV, int SH, class Src>
 __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, const Item& item, const CurveConst cc,
                                              const Src& src, int n, uint64_t* hist, int lane, int wave, float* part,
-                                             uint64_t* totals, float* var_sums, const double* f_first = nullptr) {
+                                             uint64_t* totals, const double* f_first = nullptr) {
   static_assert(SH == 1 || FL == 1, "a shared histogram serves one frequency per lane");
   static_assert(kSumParts % SH == 0, "each wave owns whole parts of the sum");
   const int M = a.n_bins;
@@ -484,11 +481,21 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
   const float outscale = cc.kc * cc.scale;
   const int nvar = NV == 1 ? 1 : a.var.n;
   const int64_t var_stride = (int64_t)a.n_curves * a.n_freq;
+  // periodograms this wave stores and keeps peaks for: slot p is variant
+  // slot_var(p) (NV stands for none)
+  constexpr bool kSplit = SH > 1 && NV > 1;
+  constexpr int NP = kSplit ? kOwned<NV, SH> + 1 : NV;
+  auto slot_var = [&](int p) -> int {
+    if constexpr (!kSplit) return p;
+    if (p == 0) return lead ? 0 : NV;
+    const int v = a.var.own[SH == 4][wave][p - 1];
+    return v == 0 ? NV : v;
+  };
 
-  PeakState peaks[NV];
+  PeakState peaks[NP];
   if (PK) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) peaks[v].init();
+    for (int p = 0; p < NP; ++p) peaks[p].init();
   }
   bool pend = false;  // the last index of the previous sub-tile waits for its right neighbour
 
@@ -508,7 +515,7 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
     for (int j = 0; j < FL; ++j) {
       const int kb = kt + j * kWave;
       if (kb >= k1) break;
-      float sv[NV];
+      float sv[NP];
       if constexpr (SH > 1 && NV == 1) {
         __syncthreads();  // every slice is in the histogram
         reduce_parts<PH, SH>(h[j], M, wave, cc.ia2q, part, lane);
@@ -522,19 +529,19 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
         __syncthreads();  // every slice is in the histogram
         variants_phase1<PH, SH>(h[j], M, wave, cc.ia2q, a.var, part, totals, lane);
         __syncthreads();  // prefixes, range totals and part sums visible
-        variants_phase2<NV, SH>(h[j], M, wave, cc.ia2q, a.var, totals, var_sums, lane);
-        __syncthreads();  // every derived variant has read its prefixes
-        clear_need_slots<SH>(h[j], M, wave, a.var);
+        float own[kOwned<NV, SH>];
+        variants_phase2<NV, SH>(h[j], M, wave, cc.ia2q, a.var, totals, own, lane);
+        float s0 = 0.f;
         if (lead) {
-          float s0 = 0.f;
 #pragma unroll
           for (int p = 0; p < kSumParts; ++p) s0 += part[p * kWave + lane];
-          sv[0] = s0;
-#pragma unroll
-          for (int v = 1; v < NV; ++v) sv[v] = v < nvar ? var_sums[v * kWave + lane] : 0.f;
         }
-        __syncthreads();  // histogram clear for the next sub-tile; sums read
-        if (!lead) continue;
+        __syncthreads();  // every derived variant has read its prefixes, the lead the part sums
+        clear_need_slots<SH>(h[j], M, wave, a.var);
+        __syncthreads();  // histogram clear for the next sub-tile
+        sv[0] = s0;
+#pragma unroll
+        for (int q = 0; q < kOwned<NV, SH>; ++q) sv[1 + q] = own[q];
       } else if constexpr (NV == 1) {
         sv[0] = reduce_hist<PH>(h[j], M, cc.ia2q);
       } else {
@@ -542,22 +549,24 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
       }
       const int k = kb + lane;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
+      for (int p = 0; p < NP; ++p) {
+        const int v = slot_var(p);
         if (v < nvar) {
-          const float s = outscale * sv[v];
+          const float s = outscale * sv[p];
           if (a.S != nullptr && k < k1) a.S[v * var_stride + (int64_t)c * a.n_freq + k] = s;
-          if (PK) peaks[v].step(s, kb, k0, k1, a.n_freq, pend, a.topk, a.edge + ((int64_t)item.slot * nvar + v) * 4, lane);
+          if (PK) peaks[p].step(s, kb, k0, k1, a.n_freq, pend, a.topk, a.edge + ((int64_t)item.slot * nvar + v) * 4, lane);
         }
       }
       pend = kb + kWave - 1 < k1 - 1;
     }
   }
-  if (PK && lead) {
+  if (PK && (kSplit || lead)) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
+    for (int p = 0; p < NP; ++p) {
+      const int v = slot_var(p);
       if (v < nvar) {
         const int64_t o = ((int64_t)item.slot * nvar + v) * a.topk;
-        peaks[v].top.store(a.topk, a.cand_val + o, a.cand_idx + o, lane);
+        peaks[p].top.store(a.topk, a.cand_val + o, a.cand_idx + o, lane);
       }
     }
   }
@@ -570,8 +579,7 @@ __device__ __forceinline__ void process_item(const BatchArgs& a, const RO& ro, c
 // LDS: SH == 1: one histogram set per wave, [wave][j][bin][lane].  SH > 1
 // (the workgroup is the SH waves of one histogram): [bin][lane], then the
 // part sums [kSumParts][lane] (float), with several variants the range
-// totals [SH][lane] (64-bit) and the variant sums [NV][lane] (float), and
-// the item index of the group.
+// totals [SH][lane] (64-bit), and the item index of the group.
 template <int PH, int FL, int PK, int SRC, int NV, int SH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == SRC_DPP && SH == 1 ? 2 : 10))) void batched_kernel(BatchArgs a, const Rec* __restrict__ rec,
                                                       const int64_t* __restrict__ offsets,
@@ -585,9 +593,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
   const int slots = a.n_bins + 1;
   uint64_t* hist = lds + (SH > 1 ? (size_t)0 : (size_t)wave * FL * slots * kWave);
   float* part = reinterpret_cast<float*>(lds + (size_t)slots * kWave);
-  uint64_t* totals = reinterpret_cast<uint64_t*>(part + kSumParts * kWave);        // used when NV > 1
-  float* var_sums = reinterpret_cast<float*>(totals + (NV > 1 ? SH * kWave : 0));  // used when NV > 1
-  int* group_item = reinterpret_cast<int*>(var_sums + (NV > 1 ? NV * kWave : 0));
+  uint64_t* totals = reinterpret_cast<uint64_t*>(part + kSumParts * kWave);  // used when NV > 1
+  int* group_item = reinterpret_cast<int*>(totals + (NV > 1 ? SH * kWave : 0));
   if (SH > 1) {
     for (int s = wave; s < slots; s += SH) hist[s * kWave + lane] = 0;
     // every wave clears its own slots but folds into all of them: the
@@ -627,7 +634,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, SRC == S
     const int lo = slice_begin<SH>(wave, n_all);
     const RecSource src{ro.rec + p0 + lo};
     process_item<PH, FL, PK, SRC, NV, SH>(a, ro, item, ro.cc[item.curve], src, slice_size<SH>(wave, n_all), hist,
-                                          lane, wave, part, totals, var_sums);
+                                          lane, wave, part, totals);
   }
 }
 
@@ -811,8 +818,7 @@ __global__ __launch_bounds__(kFusedShare * kWave) void fused_kernel(BatchArgs a,
   const RO ro{nullptr, a.offsets, nullptr, a.freqs};
   // (the count passed only tells whether this wave has observations)
   process_item<PH, 1, PK, SRC_LANES, 1, kFusedShare>(a, ro, item, make_curve_const(k, o.inv_alpha2, o.stat_scale), src,
-                                                     n_all - wave * kWave, hist, lane, wave, part, nullptr, nullptr,
-                                                     &f0);
+                                                     n_all - wave * kWave, hist, lane, wave, part, nullptr, &f0);
 }
 
 void* fused_fn(int phase, int pk) {
@@ -890,7 +896,7 @@ size_t batched_lds_bytes(const Shape& shape, int n_bins, int n_var) {
   const size_t hist = (size_t)(n_bins + 1) * kWave * sizeof(uint64_t);
   if (shape.share > 1) {
     size_t extra = (size_t)kSumParts * kWave * sizeof(float) + 16;
-    if (n_var > 1) extra += (size_t)shape.share * kWave * sizeof(uint64_t) + (size_t)kMaxVariants * kWave * sizeof(float);
+    if (n_var > 1) extra += (size_t)shape.share * kWave * sizeof(uint64_t);
     return hist + extra;
   }
   return (size_t)shape.waves_per_group * shape.freqs_per_lane * hist;

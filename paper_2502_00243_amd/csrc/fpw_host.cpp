@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -990,6 +991,48 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
   return FPW_OK;
 }
 
+// Which wave of a histogram shared by 2 or 4 waves computes (and keeps the
+// S and peaks of) each derived variant: of all assignments of variants
+// 1..n-1 to the waves, at most as many per wave as the kernel has register
+// slots for (ceil((NV - 1) / SH) for its NV = 4 or 8), the one whose busiest
+// wave has the least work, counted as the variant's coarse bins plus a
+// fixed cost for its set-up, store and peak step; wave 0 also stores and
+// keeps variant 0.  At most 4^7 assignments: exhaustive search.
+void assign_variant_waves(fpw::Variants& var, int M) {
+  constexpr int kPerVariant = 5, kLeadExtra = 5;
+  std::memset(var.own, 0, sizeof(var.own));
+  const int nd = var.n - 1;
+  if (nd <= 0) return;
+  const int nv_inst = var.n <= 4 ? 4 : fpw::kMaxVariants;
+  for (int s = 0; s < 2; ++s) {
+    const int sh = s == 0 ? 2 : 4;
+    const int cap = (nv_inst - 1 + sh - 1) / sh;
+    int n_assign = 1;
+    for (int d = 0; d < nd; ++d) n_assign *= sh;
+    int best = -1, best_cost = INT_MAX;
+    for (int code = 0; code < n_assign; ++code) {
+      int load[4] = {kLeadExtra, 0, 0, 0}, count[4] = {0, 0, 0, 0};
+      bool ok = true;
+      for (int d = 0, c = code; d < nd; ++d, c /= sh) {
+        const int w = c % sh;
+        load[w] += M / var.k[d + 1] + kPerVariant;
+        ok = ok && ++count[w] <= cap;
+      }
+      if (!ok) continue;
+      const int cost = *std::max_element(load, load + sh);
+      if (cost < best_cost) {
+        best_cost = cost;
+        best = code;
+      }
+    }
+    int count[4] = {0, 0, 0, 0};
+    for (int d = 0, c = best; d < nd; ++d, c /= sh) {
+      const int w = c % sh;
+      var.own[s][w][count[w]++] = (int8_t)(d + 1);
+    }
+  }
+}
+
 template <class T>
 fpw_status upload(DevBuf& b, const T* src, size_t n, hipStream_t s, const char* what) {
   FPW_HIP(b.alloc(n * sizeof(T)), what);
@@ -1087,10 +1130,9 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
         const int e = off + (c + 1) * k;
         const int slot = (e > M ? e - M : e) - 1;
         p->var.need[slot >> 5] |= 1u << (slot & 31);
-        if (v == p->var.n - 1) p->var.rest[slot >> 5] |= 1u << (slot & 31);  // read (and cleared) by the last
       }
     }
-    for (int w = 0; w < 8; ++w) p->var.rest[w] = p->var.need[w] & ~p->var.rest[w];
+    assign_variant_waves(p->var, o.n_bins);
     hipStream_t s = (hipStream_t)stream;
     FPW_HIP(hipGetDevice(&p->device), "hipGetDevice");
     FPW_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device), "CU count");

@@ -86,11 +86,15 @@ struct Variants {
   int32_t n;
   int32_t k[kMaxVariants];
   int32_t o[kMaxVariants];
-  // bit m of need: slot m must hold the prefix sum P(m+1) because a derived
-  // variant reads it; bit m of rest: such a slot that the last variant does
-  // not read (and so does not clear)
+  // bit m of need: slot m must hold the prefix sum F(0) + ... + F(m) because
+  // a derived variant reads it (the last slot of one of its windows, or the
+  // slot before its first window)
   uint32_t need[8];
-  uint32_t rest[8];
+  // With a histogram shared by 2 (own[0]) or 4 (own[1]) waves: the derived
+  // variants that wave w computes and keeps (S and peaks), own[.][w][j], 0
+  // for none; chosen on the host so that the waves' epilogues take about
+  // equal time.
+  int8_t own[2][4][4];
 };
 
 struct BatchArgs {
