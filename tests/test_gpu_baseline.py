@@ -93,7 +93,8 @@ def test_baseline_kernel_against_oracle(case):
     for c in range(b.n_curves):
         ref, S_abs = _reference(plan, b, y, K, beta, opts, c, exact_bins=phase == "fp64_listing")
         guard.append(parity.assert_s_close(S[c], ref, S_abs, what=f"curve {c}"))
-    assert np.mean(guard) < 0.02 or M == 1
+    print(f"  guard fraction {np.mean(guard):.2e}", flush=True)
+    assert np.mean(guard) <= parity.MAX_GUARD_FRACTION
     plan.close()
 
 

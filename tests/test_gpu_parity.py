@@ -146,6 +146,28 @@ def test_fp64_comparator():
     plan.close()
 
 
+def test_precision_study_references_on_ztf1000():
+    """The precision study's references, on its own data (the 1000 ZTF-like curves at M = 20): the
+    listing-order FP64 bins equal the oracle's bin for bin, and the FP64 comparator's S the oracle's
+    within 1e-10, on four curves (the longest and shortest among them) at every 10th frequency."""
+    _say("precision references on ztf1000")
+    b = synth.ztf_batch()
+    plan = fpw.Plan.from_batch(b, phase="fp64_listing")
+    S = plan.eval_fp64()
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    fi = np.arange(0, len(b.freqs), 10)
+    for c in (int(np.argmax(b.lengths)), int(np.argmin(b.lengths)), 17, 503):
+        t, y, dy = b.curve(c)
+        gb = plan.debug_bins(c, 0, len(b.freqs)).cpu().numpy()[fi]
+        np.testing.assert_array_equal(gb, oracle.curve_bins(t, b.freqs[fi], b.n_bins), err_msg=f"curve {c}")
+        ref = oracle.curve_periodogram(t, y, dy, b.freqs[fi], b.n_bins)
+        tau, w, x = oracle.prepare_curve(t, y, dy)
+        scale = np.sum(np.abs(w * x)) ** 2 / np.sum(w)
+        assert np.all(np.abs(S[c, fi] - ref) <= 1e-10 * np.abs(ref) + 1e-13 * scale), c
+    plan.close()
+
+
 def test_edge_cases():
     _say("edge cases")
     # one frequency; two frequencies; curves of one point; M at its maximum

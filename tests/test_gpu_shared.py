@@ -72,8 +72,10 @@ def test_matrix_kernel_against_oracle(case):
     plan = _shared_plan(b, phase=phase, shared_kernel="matrix")
     assert plan.info().kernel == 1
     g, _ = _check(b, plan, {}, exact_bins=phase == "fp64_listing")
-    # with one bin S is Y^2/W with Y = sum(w x) = 0: only the cancellation guard applies
-    assert g < 0.02 or M == 1
+    # every curve's fraction is gated at MAX_GUARD_FRACTION inside _check; with one bin S is
+    # Y^2/W with Y = sum(w x) = 0, a structural zero that the gate does not count
+    _say(f"  guard fraction {g:.2e}")
+    assert g <= parity.MAX_GUARD_FRACTION
     plan.close()
 
 
@@ -84,7 +86,8 @@ def test_general_kernel_on_shared_plan_and_kernels_agree():
     pm = _shared_plan(b, shared_kernel="matrix")
     assert pg.info().kernel == 0 and pm.info().kernel == 1
     g, Sg = _check(b, pg, {})
-    assert g < 0.02
+    _say(f"  guard fraction {g:.2e}")
+    assert g <= parity.MAX_GUARD_FRACTION
     Sm = pm.eval(topk=False)[0].cpu().numpy()
     rel = np.abs(Sm - Sg) / np.maximum(np.abs(Sg), 1e-30)
     assert np.median(rel) < 1e-6
@@ -103,7 +106,8 @@ def test_matrix_kernel_options(opts):
     b = synth.random_shared_batch(12, 20, 180, FREQS, 16)
     plan = _shared_plan(b, shared_kernel="matrix", **opts)
     g, _ = _check(b, plan, opts)
-    assert g < 0.02
+    _say(f"  guard fraction {g:.2e}")
+    assert g <= parity.MAX_GUARD_FRACTION
     plan.close()
 
 
@@ -160,7 +164,8 @@ def test_field_of_1000_curves_sampled():
     fi = np.sort(rng.choice(len(b.freqs), 300, replace=False))
     curves = list(rng.choice(b.n_curves, 12, replace=False)) + [0, b.n_curves - 1]
     g, S_gpu = _check(b, plan, {}, curves=curves, freq_idx=fi)
-    assert g < 0.02
+    _say(f"  guard fraction {g:.2e}")
+    assert g <= parity.MAX_GUARD_FRACTION
     Sn = S.cpu().numpy()
     np.testing.assert_array_equal(Sn[curves], S_gpu[curves])
     idx, val = idx.cpu().numpy(), val.cpu().numpy()
