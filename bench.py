@@ -219,6 +219,17 @@ def profiled_kernel_ms(batch, passes, warmup=1, store_s=False, **opts):
     return np.asarray(kms).mean(axis=0), info
 
 
+def copy_calibration():
+    """A 256 MiB device copy: the reference that scales the HBM byte counters of a PMC run."""
+    import torch
+
+    src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def _traffic(path, workload):
     if os.path.exists(path):
         tr = json.load(open(path))
@@ -302,12 +313,7 @@ def bench_headline(args):
     plan.close()
 
     if args.copy_calibration:
-        # a 256 MiB device copy: the reference that scales the HBM byte counters of a PMC run
-        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
     if args.kernel_only:
         print(json.dumps({"workload": "stress", "value": value, "ms_per_step": wall * 1e3, "steps": args.steps,
                           "pass_event_ms": ev_ms}), flush=True)
@@ -461,6 +467,8 @@ def bench_ztf1000(args):
 
     torch.cuda.set_device(0)
     summary = ztf1000_summary(args, steps=max(args.steps, 20), warmup=max(args.warmup, 3))
+    if args.copy_calibration:
+        copy_calibration()
     plain = None
     if not args.no_fp64_plain:
         plan = fpw.Plan.from_batch(batch, topk=5, phase=args.phase)
