@@ -773,7 +773,12 @@ def bench_precision(args):
     FP64, which the parity tests find bit-identical to the oracle's bins); a flip counts as off-edge
     when that point lies at least 1e-6 bin widths from an edge (distance from tau f in FP64).  S: the
     plain per-curve FP64 comparator (listing-order FP64 fold, FP64 sums and statistic), which the
-    parity tests check against the oracle."""
+    parity tests check against the oracle.  The parity bar is |dS| <= 1e-5 S + 1e-7 S_abs, where
+    S_abs = sum_m (sum over bin m of |w x|)^2 / (W_m + 1/alpha^2) is the statistic of |x| with no
+    further centring (a plan of its own over |y - mu|, mu the weighted mean); per mode the line reports
+    the fraction that needed the second term (the cancellation guard) and the fraction beyond both
+    (near-edge points that the mode and the listing-order reference place in neighbouring bins)."""
+    import numpy as np
     import torch
 
     from paper_2502_00243_amd import fpw, synth
@@ -784,6 +789,13 @@ def bench_precision(args):
     evals = batch.evals()
     ref = fpw.Plan.from_batch(batch, phase="fp64_listing")
     S64 = ref.eval_fp64()
+    w = 1.0 / (batch.dy * batch.dy)
+    seg = np.repeat(np.arange(C), np.diff(batch.offsets))
+    mu = np.bincount(seg, weights=w * batch.y, minlength=C) / np.bincount(seg, weights=w, minlength=C)
+    p_abs = fpw.Plan(batch.offsets, batch.t, np.abs(batch.y - mu[seg]), batch.dy, batch.freqs, M, center="none",
+                     phase="fp64_listing")
+    S_abs = p_abs.eval(topk=False)[0].double()
+    p_abs.close()
     torch.cuda.synchronize()
     freqs_d = torch.as_tensor(batch.freqs, dtype=torch.float64, device="cuda")
     out = {}
@@ -804,6 +816,11 @@ def bench_precision(args):
                     u = (u - torch.floor(u)) * M
                     off_edge += int(((u - torch.round(u)).abs() >= 1e-6).sum())
                 del d, fi, pi
+        err = (S_gpu.double() - S64).abs()
+        bar = 1e-5 * S64.abs()
+        guard_hits = float(((err > bar) & (err <= bar + 1e-7 * S_abs)).double().mean())
+        beyond = float((err > bar + 1e-7 * S_abs).double().mean())
+        del err, bar
         rel = ((S_gpu.double() - S64).abs() / S64.abs().clamp_min(1e-300)).flatten()
         srt = torch.sort(rel).values
         n = srt.numel()
@@ -814,7 +831,8 @@ def bench_precision(args):
                       "S_values_compared": n,
                       "S_rel_err_median": float(srt[n // 2]), "S_rel_err_p99": float(srt[int(0.99 * (n - 1))]),
                       "S_rel_err_p99_99": float(srt[int(0.9999 * (n - 1))]), "S_rel_err_max": float(srt[-1]),
-                      "S_frac_above_1e-5": float((rel > 1e-5).double().mean())}
+                      "S_frac_above_1e-5": float((rel > 1e-5).double().mean()),
+                      "guard_hit_fraction": guard_hits, "S_frac_beyond_bar": beyond}
         del rel, srt
         log(f"{phase}: {out[phase]} ({time.perf_counter() - t0:.1f} s of checks)")
         plan.close()
