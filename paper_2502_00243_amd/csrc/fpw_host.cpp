@@ -997,12 +997,14 @@ fpw_status autotune(fpw_plan_s* p, hipStream_t s) {
 // slots for (ceil((NV - 1) / SH) for its NV = 4 or 8), the one whose busiest
 // wave has the least work, counted as the variant's coarse bins plus a
 // fixed cost for its set-up, store and peak step; wave 0 also stores and
-// keeps variant 0.  At most 4^7 assignments: exhaustive search.
-void assign_variant_waves(fpw::Variants& var, int M) {
+// keeps variant 0.  At most 4^7 assignments: exhaustive search.  False if
+// no assignment fits the slots (not reachable with at most kMaxVariants
+// variants, but checked rather than assumed).
+bool assign_variant_waves(fpw::Variants& var, int M) {
   constexpr int kPerVariant = 5, kLeadExtra = 5;
   std::memset(var.own, 0, sizeof(var.own));
   const int nd = var.n - 1;
-  if (nd <= 0) return;
+  if (nd <= 0) return true;
   const int nv_inst = var.n <= 4 ? 4 : fpw::kMaxVariants;
   for (int s = 0; s < 2; ++s) {
     const int sh = s == 0 ? 2 : 4;
@@ -1025,12 +1027,14 @@ void assign_variant_waves(fpw::Variants& var, int M) {
         best = code;
       }
     }
+    if (best < 0) return false;
     int count[4] = {0, 0, 0, 0};
     for (int d = 0, c = best; d < nd; ++d, c /= sh) {
       const int w = c % sh;
       var.own[s][w][count[w]++] = (int8_t)(d + 1);
     }
   }
+  return true;
 }
 
 template <class T>
@@ -1132,7 +1136,8 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
         p->var.need[slot >> 5] |= 1u << (slot & 31);
       }
     }
-    assign_variant_waves(p->var, o.n_bins);
+    if (!assign_variant_waves(p->var, o.n_bins))
+      return fail(FPW_EUNSUPPORTED, "%d periodogram variants do not fit the kernels' register slots", p->var.n);
     hipStream_t s = (hipStream_t)stream;
     FPW_HIP(hipGetDevice(&p->device), "hipGetDevice");
     FPW_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device), "CU count");
