@@ -701,7 +701,8 @@ def single_curve_latency(passes):
     lats = []
     for fuse in (0, -1):
         p1 = fpw.Plan.from_batch(b1, topk=1, fuse_prepare=fuse)
-        for _ in range(3):
+        t_warm = time.perf_counter()  # steady-state clocks first (see bench_small)
+        while time.perf_counter() - t_warm < 0.2:
             p1.eval(S_out=S1, idx_out=i1, val_out=v1)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -726,7 +727,9 @@ def bench_latency(args):
 
 def bench_small(args):
     """Small and mid-size plans (N ~ U(100, 1000), M = 20, S + top-5): µs per pass back to back with
-    the fused pass forced on and off; one JSON line per plan size."""
+    the fused pass forced on and off; one JSON line per plan size.  Each plan first runs passes back to
+    back for 200 ms: the GPU lowers its clocks when idle for a fraction of a second, and passes this
+    short, timed after a few warm-up passes only, measured 6-10 % slower than in steady state."""
     import numpy as np
     import torch
 
@@ -746,10 +749,11 @@ def bench_small(args):
                 S = torch.empty((C, nf), dtype=torch.float32, device="cuda")
                 i = torch.empty((C, 5), dtype=torch.int32, device="cuda")
                 v = torch.empty((C, 5), dtype=torch.float32, device="cuda")
-                for _ in range(3):
+                t_warm = time.perf_counter()
+                while time.perf_counter() - t_warm < 0.2:
                     p.eval(S_out=S, idx_out=i, val_out=v)
                 torch.cuda.synchronize()
-                reps = 20 if C * nf < 1e6 else 5
+                reps = 50 if C * nf < 1e6 else 20
                 t = time.perf_counter()
                 for _ in range(reps):
                     p.eval(S_out=S, idx_out=i, val_out=v)
