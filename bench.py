@@ -703,8 +703,9 @@ def single_curve_latency(passes):
         p1 = fpw.Plan.from_batch(b1, topk=1, fuse_prepare=fuse)
         t_warm = time.perf_counter()  # steady-state clocks first (see bench_small)
         while time.perf_counter() - t_warm < 0.2:
-            p1.eval(S_out=S1, idx_out=i1, val_out=v1)
-        torch.cuda.synchronize()
+            for _ in range(20):
+                p1.eval(S_out=S1, idx_out=i1, val_out=v1)
+            torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(passes):
             p1.eval(S_out=S1, idx_out=i1, val_out=v1)
@@ -750,9 +751,9 @@ def bench_small(args):
                 i = torch.empty((C, 5), dtype=torch.int32, device="cuda")
                 v = torch.empty((C, 5), dtype=torch.float32, device="cuda")
                 t_warm = time.perf_counter()
-                while time.perf_counter() - t_warm < 0.2:
+                while time.perf_counter() - t_warm < 0.2:  # synchronised: the host must not queue ahead
                     p.eval(S_out=S, idx_out=i, val_out=v)
-                torch.cuda.synchronize()
+                    torch.cuda.synchronize()
                 reps = 50 if C * nf < 1e6 else 20
                 t = time.perf_counter()
                 for _ in range(reps):
