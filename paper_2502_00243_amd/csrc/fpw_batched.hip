@@ -474,18 +474,18 @@ __device__ __forceinline__ int slice_size(int wave, int n_all) {
 constexpr int kLeadLighter = 16;
 template <int SH, bool LIGHT>
 __device__ __forceinline__ void lead_slices(int wave, int n_all, int& lo, int& n) {
-  if (SH == 1 || !LIGHT) {
+  if constexpr (SH == 1 || !LIGHT) {
     lo = slice_begin<SH>(wave, n_all);
     n = slice_size<SH>(wave, n_all);
-    return;
-  }
-  const int b1 = max(0, n_all / SH - kLeadLighter);
-  if (wave == 0) {
-    lo = 0;
-    n = b1;
   } else {
-    lo = b1 + (int)((int64_t)(wave - 1) * (n_all - b1) / (SH - 1));
-    n = b1 + (int)((int64_t)wave * (n_all - b1) / (SH - 1)) - lo;
+    const int b1 = max(0, n_all / SH - kLeadLighter);
+    if (wave == 0) {
+      lo = 0;
+      n = b1;
+    } else {
+      lo = b1 + (int)((int64_t)(wave - 1) * (n_all - b1) / (SH - 1));
+      n = b1 + (int)((int64_t)wave * (n_all - b1) / (SH - 1)) - lo;
+    }
   }
 }
 
