@@ -107,7 +107,9 @@ typedef struct {
   double t_ref;        /* used iff tref_mode == FPW_TREF_GIVEN */
   int32_t autotune;    /* 1: time candidate launch shapes at plan time and keep the fastest */
   int32_t use_graph;   /* 1 (default): replay fpw_eval_batch as one captured hipGraph (not
-                          for the fused pass of small plans, see fuse_prepare) */
+                          for the fused pass of small plans, see fuse_prepare).  0: launch
+                          the pass's kernels directly, which costs the host about half as
+                          much per call and measured 4-5 us less per pass back to back */
   int32_t freqs_per_lane; /* launch shape override, 0 = default: frequencies per lane (1, 2) */
   int32_t waves_per_group;/* launch shape override, 0 = default: waves per workgroup (1, 2, 4) */
   int32_t chunk_freqs;    /* launch shape override, 0 = default: frequencies per work item
