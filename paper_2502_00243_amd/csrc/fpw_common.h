@@ -167,14 +167,16 @@ __device__ __forceinline__ uint64_t lds_take(uint64_t* p) {
 
 // Adds the Eq. 1 term of one bin, Y_q^2 / (W_q + ia2q), from its packed
 // fixed-point word.  Every non-empty bin has W_q >= 1 (weights are clamped to
-// at least one unit), and an empty bin has Y_q = 0, so clamping the
-// denominator at 1/2 leaves every term unchanged and makes empty bins add 0
-// without a branch.
+// at least one unit) and an empty bin has Y_q = 0; ia2q is at least
+// kMinPrior (make_curve_const), which leaves fl(W_q + ia2q) unchanged for
+// W_q >= 1 and keeps an empty bin's denominator positive, so it adds 0
+// without a branch or a clamp.
+constexpr float kMinPrior = 0x1p-100f;
 __device__ __forceinline__ float add_bin_term(float acc, uint64_t v, float ia2q) {
   const uint32_t l = lo32(v);
   const int32_t yq = (int32_t)l;
   const uint32_t wq = hi32(v) + (l >> 31);  // undo the borrow of a negative low word
-  const float d = fmaxf((float)wq + ia2q, 0.5f);
+  const float d = (float)wq + ia2q;
   const float yf = (float)yq;
   return __builtin_fmaf(yf, yf * __builtin_amdgcn_rcpf(d), acc);
 }
@@ -687,7 +689,7 @@ __device__ __forceinline__ void wide_parts(uint64_t* h, int M, int p0, const Wid
 __device__ __forceinline__ CurveConst make_curve_const(const PrepConst& k, double inv_alpha2, float stat_scale) {
   CurveConst c;
   c.kc = (float)(k.s_w / (k.s_y * k.s_y));
-  c.ia2q = (float)(inv_alpha2 * k.s_w);
+  c.ia2q = fmaxf((float)(inv_alpha2 * k.s_w), kMinPrior);  // see add_bin_term
   c.scale = stat_scale;
   c.pad = 0.f;
   return c;
