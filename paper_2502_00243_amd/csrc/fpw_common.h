@@ -59,6 +59,9 @@ struct Folder<PH_FP64> {
     f = freq;
     md = (double)M;
     nh = shift;
+    // tau comes from an SGPR, so the fma's other uniform operand must sit in
+    // a VGPR; held there once, it is not copied in again for every batch
+    asm volatile("" : "+v"(nh));
   }
   __device__ __forceinline__ int bin(uint64_t tb) const {
     const double tau = __longlong_as_double((long long)tb);
