@@ -167,8 +167,8 @@ typedef struct {
                              replay costs the host more than they do).  S and peaks are
                              bit-identical to the three-kernel pass.
                              0 = default: for plans of one periodogram variant and no
-                             baseline terms with at most 8 items of 64 frequencies per CU
-                             (n_curves * ceil(n_freq / 64) <= 8 * CUs), when no launch shape
+                             baseline terms with at most 4 items of 64 frequencies per CU
+                             (n_curves * ceil(n_freq / 64) <= 4 * CUs), when no launch shape
                              override and no autotune is set.  -1 = never.  1 = always (FPW_EUNSUPPORTED with
                              derived bin counts, baseline terms, or a shape override other
                              than chunk_freqs and four waves per group). */

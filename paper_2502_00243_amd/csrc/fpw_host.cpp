@@ -172,10 +172,10 @@ const double kShare4SmallPlanEvalsPerCu = 1.5e8;
 const int kDppMinBins = 32;
 const int kDppMinBinsShared = 128;
 // Largest plan that runs the fused pass by default, in items of 64
-// frequencies per CU (measured with N ~ U(100, 1000), M = 20: the fused pass
-// is 1.2-2x faster up to 6 items per CU, 0.86x at 10; beyond ~100 the
-// persistent kernel is up to 2.3x faster).
-const int kFusedItemsPerCu = 8;
+// frequencies per CU (measured with N ~ U(100, 1000), M = 20, 4-64 curves:
+// the fused pass is 1.05-1.2x faster at 3-4 items per CU, 0.9x at 5 and
+// 0.8-0.9x at 6-7; beyond ~100 the persistent kernel is up to 2.3x faster).
+const int kFusedItemsPerCu = 4;
 // Smallest work item of the persistent kernel, in evaluations per wave: a
 // pop of the queue's one counter costs ~20 ns serialised, so with ~3300
 // waves popping an item has to keep its wave busy ~70 us (~1.2e5

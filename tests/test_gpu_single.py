@@ -201,10 +201,10 @@ def test_fused_repeated_passes():
 
 
 def test_default_size_rule():
-    """Fused up to 8 items of 64 frequencies per CU, three kernels above, or when a shape is asked for."""
+    """Fused up to 4 items of 64 frequencies per CU, three kernels above, or when a shape is asked for."""
     _say("fused default size rule")
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-    budget = 8 * n_cu
+    budget = 4 * n_cu
     n_curves = 16
     per_curve = budget // n_curves
     b = synth.random_batch(12, n_curves, 20, 100, np.linspace(0.1, 5.0, 10), 10)
