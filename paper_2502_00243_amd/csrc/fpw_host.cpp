@@ -167,8 +167,9 @@ const int kShare4MinBins = 32;
 // two waves 1 % faster on the 5.5e10 of 1000 ZTF-like curves).
 const double kShare4SmallPlanEvalsPerCu = 1.5e8;
 // Smallest M for which the default point source is the DPP broadcast, with
-// private histograms (or several variants) and with shared histograms and
-// one variant (their extra waves hide the scalar loads' waits up to M ~ 100).
+// private histograms (or more than four variants) and with shared histograms
+// and up to four variants (their extra waves hide the scalar loads' waits up
+// to M ~ 100).
 const int kDppMinBins = 32;
 const int kDppMinBinsShared = 128;
 // Largest plan that runs the fused pass by default, in items of 64
@@ -1184,9 +1185,11 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
       share = !can ? 1 : (o.n_bins >= kShare4MinBins ? 4 : (o.n_bins >= kShare2MinBins ? 2 : 1));
       if (share == 2 && p->var.n == 1 && (double)np * (double)n_freq < kShare4SmallPlanEvalsPerCu * p->n_cu) share = 4;
     }
-    // with several variants the scalar source loses to the DPP broadcast even with shared
-    // histograms (measured: M = 40 -> 20, 10 on 1000 ZTF-like curves, 20.1 vs 17.8 ms)
-    const int dpp_from = share > 1 && p->var.n == 1 ? kDppMinBinsShared : kDppMinBins;
+    // with more than four variants (the 8-variant kernel) the DPP broadcast wins even with
+    // shared histograms (M = 40 -> 20, 10 at every offset, four waves per histogram: 2.90
+    // against 2.95 s on the uneven batch, even on the ZTF-like one); with up to four the
+    // scalar source does (offset 0 only: 2.35 against 2.37 s, 14.0 against 14.6 ms)
+    const int dpp_from = share > 1 && p->var.n <= 4 ? kDppMinBinsShared : kDppMinBins;
     const int src = o.point_source ? o.point_source - 1 : (o.n_bins >= dpp_from ? 1 : 0);
     const int fl = (src == 1 || p->var.n > 1 || share > 1) ? 1 : (o.freqs_per_lane ? o.freqs_per_lane : 1);
     const int wpg = share > 1 ? share : (o.waves_per_group ? o.waves_per_group : 1);

@@ -169,7 +169,10 @@ def test_default_share_by_bin_count():
     assert p.info().hist_share == 2  # the small-plan rule takes one variant only
     p.close()
     p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, derived_bins=(20,), **one)
-    assert (p.info().hist_share, p.info().point_source) == (4, 2)  # derived bin counts share too, DPP source
+    assert (p.info().hist_share, p.info().point_source) == (4, 1)  # derived bin counts share too, scalar source
+    p.close()
+    p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, derived_bins=(20, 10), all_offsets=True, **one)
+    assert (p.info().hist_share, p.info().point_source) == (4, 2)  # more than four variants: DPP source
     p.close()
     for phase in ("df32", "fp32"):  # the study modes share with one variant
         p = fpw.Plan(b.offsets, b.t, b.y, b.dy, b.freqs, 40, phase=phase, **one)
