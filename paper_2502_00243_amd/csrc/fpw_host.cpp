@@ -1187,7 +1187,7 @@ fpw_status fpw_plan(fpw_plan_t* out, int64_t n_curves, const int64_t* offsets, c
     }
     // with more than four variants (the 8-variant kernel) the DPP broadcast wins even with
     // shared histograms (M = 40 -> 20, 10 at every offset, four waves per histogram: 2.90
-    // against 2.95 s on the uneven batch, even on the ZTF-like one); with up to four the
+    // against 2.95 s on the uneven batch, a tie on the ZTF-like one); with up to four the
     // scalar source does (offset 0 only: 2.35 against 2.37 s, 14.0 against 14.6 ms)
     const int dpp_from = share > 1 && p->var.n <= 4 ? kDppMinBinsShared : kDppMinBins;
     const int src = o.point_source ? o.point_source - 1 : (o.n_bins >= dpp_from ? 1 : 0);
