@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_shared_kernel(SharedPrep
     if (t == 0) {
       CurveConst k;
       k.kc = (float)(s_w / (s_y * s_y));
-      k.ia2q = (float)(a.inv_alpha2 * s_w);
+      k.ia2q = fmaxf((float)(a.inv_alpha2 * s_w), kMinPrior);  // see add_bin_term
       k.scale = a.stat_scale;
       k.pad = 0.f;
       a.cc[c] = k;

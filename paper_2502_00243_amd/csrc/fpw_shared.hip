@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kSharedWaves * kWave) __attribute__((amdgpu_waves_p
         for (int u = 0; u < 2; ++u) {
           const uint32_t wq = recombine64(c, 8 * u);
           const int yq = (int)recombine64(c, 8 * u + 4);
-          const float d = fmaxf((float)wq + ia2q[ai][u], 0.5f);
+          const float d = (float)wq + ia2q[ai][u];  // ia2q >= kMinPrior: an empty bin adds 0
           const float yf = (float)yq;
           terms[(4 * ai + 2 * u + h) * kTermStride + 32 * b + n] = yf * (yf * __builtin_amdgcn_rcpf(d));
         }
